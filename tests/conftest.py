@@ -1,0 +1,61 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP library)")
+    config.addinivalue_line("markers", "slow: long-running CPU test")
+    # the oracle's many small LAPACK calls run fastest single-threaded
+    try:
+        from threadpoolctl import threadpool_limits
+
+        threadpool_limits(1, user_api="blas")
+    except Exception:
+        pass
+
+
+_CACHE = {}
+
+
+def workload(name, spec=None):
+    """Constructed workload (points, blob, rhs), cached per session."""
+    from h2gen import workloads
+
+    key = name
+    if key not in _CACHE:
+        _CACHE[key] = workloads.make(spec if spec is not None else name)
+    return _CACHE[key]
+
+
+def oracle_matrix(name, spec=None):
+    from oracle import blob as ob
+
+    key = ("H", name)
+    if key not in _CACHE:
+        _CACHE[key] = ob.parse(workload(name, spec)["blob"])
+    return _CACHE[key]
+
+
+def oracle_factor(name, tol=None, spec=None):
+    from oracle import factor as of
+
+    w = workload(name, spec)
+    tol = w["spec"]["tol"] if tol is None else tol
+    key = ("F", name, tol)
+    if key not in _CACHE:
+        _CACHE[key] = of.factor(oracle_matrix(name, spec), tol)
+    return _CACHE[key]
+
+
+# small 3D case shared by oracle pins and GPU parity (64 leaves, two skeletonized levels)
+EXP3D_4096 = dict(N=4096, dim=3, seed=116, kernel=("exp", 0.1, 1e-2), tree="kd", leaf=64,
+                  eta=0.7, tol=1e-6, nrhs=3, rhs_seed=216, p0=5)
+# one leaf-level block row per cluster with no admissible pair: pure dense LU
+NOFAR_256 = dict(N=256, dim=2, seed=121, kernel=("exp", 0.1, 1e-2), tree="2d", leaf=64,
+                 eta=0.7, tol=1e-8, nrhs=2, rhs_seed=221, p0=10)
