@@ -1,0 +1,195 @@
+/*
+ * h2.h -- C ABI of the MI355X H^2 strong recursive skeletonization solver.
+ *
+ * The library factorizes a symmetric H^2 matrix (Section 1.1 of Boukaram,
+ * Keyes, Li, Liu, Turkiyyah, "Linear Complexity H^2 Direct Solver for
+ * Fine-Grained Parallel Architectures") with the level-by-level strong
+ * recursive skeletonization of Section 2.1 (Algorithms 1 and 2), solves with
+ * the factors (Section 2.3, Algorithm 3) and multiplies by the H^2 matrix.
+ * All numerical work runs as HIP kernels on one gfx950 GPU.
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns an h2_status; nothing throws or aborts across the ABI.
+ *     On failure h2_last_error(ctx) holds a message.
+ *   - Vectors and right-hand sides are DEVICE pointers to column-major float64
+ *     arrays with a leading dimension (ld >= N), in ORIGINAL point order; the
+ *     tree permutation is applied inside the library.
+ *   - Work is enqueued on the context's HIP stream.  Calls return after the
+ *     work is enqueued unless stated otherwise; h2_sync waits for it.
+ *   - Handles are owned by the caller and released with the matching
+ *     *_destroy call.  A factor does not reference its matrix after h2_factor
+ *     returns.  Handles are not thread-safe: use one context per host thread.
+ */
+#ifndef H2_H
+#define H2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  H2_SUCCESS = 0,
+  H2_ERROR_INVALID_ARGUMENT = 1, /* bad pointer, size, tolerance or handle */
+  H2_ERROR_FORMAT = 2,           /* malformed or unsupported serialized matrix */
+  H2_ERROR_OUT_OF_MEMORY = 3,    /* device allocation failed */
+  H2_ERROR_SINGULAR = 4,         /* zero pivot in a redundant block or the top block */
+  H2_ERROR_NUMERIC = 5,          /* non-finite value produced */
+  H2_ERROR_HIP = 6,              /* HIP runtime error */
+  H2_ERROR_NOT_CONVERGED = 7,    /* iterative refinement missed its target */
+  H2_ERROR_UNSUPPORTED = 8       /* a size beyond what the kernels handle */
+} h2_status;
+
+typedef enum { H2_PREC_FP64 = 0, H2_PREC_FP32 = 1 } h2_prec;
+
+typedef struct h2_context_s* h2_context_t;
+typedef struct h2_matrix_s* h2_matrix_t;
+typedef struct h2_factor_s* h2_factor_t;
+
+/* Message of a status code (static storage). */
+const char* h2_status_string(h2_status s);
+
+/* Create a context on HIP device `device` that enqueues work on `stream`
+ * (a hipStream_t; NULL = the default stream).  The stream is borrowed. */
+h2_status h2_context_create(int device, void* stream, h2_context_t* ctx);
+h2_status h2_context_destroy(h2_context_t ctx);
+/* Last error message of the context (valid until the next call on it). */
+const char* h2_last_error(h2_context_t ctx);
+/* Wait for all work enqueued by the context. */
+h2_status h2_sync(h2_context_t ctx);
+
+/*
+ * Load a serialized symmetric H^2 matrix (format H2B1 v1: cluster tree,
+ * same-level near/far lists, leaf bases U, transfers E, dense near blocks D,
+ * couplings S; Section 1.1).  `blob` is a HOST buffer of `bytes` bytes, owned
+ * by the caller and not referenced after return.  The structure is validated
+ * (magic/version, balanced tree, CSR bounds, symmetric pattern, finite data)
+ * and the data are copied to the device.  Errors: H2_ERROR_FORMAT.
+ */
+h2_status h2_matrix_load(h2_context_t ctx, const void* blob, size_t bytes, h2_matrix_t* H);
+h2_status h2_matrix_destroy(h2_matrix_t H);
+
+typedef struct {
+  int64_t n;         /* matrix order N */
+  int32_t dim;       /* point dimension recorded in the blob */
+  int32_t depth;     /* leaf level L (root = 0) */
+  int32_t top_level; /* first level with an admissible block, -1 if none */
+  int32_t n_nodes;
+  double norm2;      /* ||A||_2 estimate stored in the blob */
+  int64_t device_bytes;
+} h2_matrix_info;
+h2_status h2_matrix_get_info(h2_matrix_t H, h2_matrix_info* info);
+
+/*
+ * Y = A X, FP64 H^2 matrix-vector product (the product of Section 1.1:
+ * near blocks plus the nested-basis upsweep / coupling / downsweep).
+ * X and Y: device, N x nrhs, leading dimensions ldx, ldy >= N; must not alias.
+ */
+h2_status h2_matvec(h2_context_t ctx, h2_matrix_t H, const double* X, int64_t ldx, int nrhs,
+                    double* Y, int64_t ldy);
+
+/*
+ * Factorize (Algorithm 1 with Algorithm 2 per colour): eps_lu = tol, fill
+ * truncation threshold eps_fill = tol * ||A||_2 (blob norm).  prec selects the
+ * arithmetic of the factorization and of its storage (FP64, or FP32 with FP32
+ * accumulation).  Synchronizes with the device once per tree level.
+ * Errors: INVALID_ARGUMENT (tol < 0 or not finite), OUT_OF_MEMORY, SINGULAR,
+ * NUMERIC, UNSUPPORTED.
+ */
+h2_status h2_factor(h2_context_t ctx, h2_matrix_t H, double tol, h2_prec prec, h2_factor_t* F);
+h2_status h2_factor_destroy(h2_factor_t F);
+
+/*
+ * X = (LU)^{-1} B with the factors (Algorithm 3).  B, X: device N x nrhs FP64
+ * (an FP32 factor converts on the way in and out).  X == B is allowed.
+ */
+h2_status h2_solve(h2_context_t ctx, h2_factor_t F, const double* B, int64_t ldb, int nrhs,
+                   double* X, int64_t ldx);
+
+typedef struct {
+  double target_bkwd; /* stop when ||b - A x|| / ||b|| <= target for every column */
+  int restart;        /* GMRES restart length */
+  int max_outer;      /* refinement steps */
+  double inner_rtol;  /* GMRES relative tolerance on the preconditioned residual */
+} h2_ir_opts;
+
+typedef struct {
+  int outer_iterations;
+  int inner_iterations;   /* total GMRES steps over all refinement steps */
+  double max_bkwd;        /* largest achieved backward error over the columns */
+} h2_ir_report;
+
+/*
+ * GMRES-based iterative refinement (Carson-Higham): x0 = solve(F, b); repeat
+ * r = b - A x with the FP64 H^2 product, stop at the target, solve A d = r by
+ * GMRES left-preconditioned with the factor, x += d.  Residuals, updates and
+ * the Krylov basis are FP64; the factor may be FP32.  Columns are refined
+ * together.  B, X: device N x nrhs FP64.  opts NULL = {1e-12, 30, 20, 1e-8}.
+ * Returns NOT_CONVERGED (with the report filled) when the target is missed.
+ */
+h2_status h2_solve_ir(h2_context_t ctx, h2_matrix_t H, h2_factor_t F, const double* B,
+                      int64_t ldb, int nrhs, double* X, int64_t ldx, const h2_ir_opts* opts,
+                      h2_ir_report* report);
+
+/*
+ * Batched factorization of `count` independent matrices: levels are aligned
+ * by height above the leaves and every (height, colour step) runs as one set
+ * of launches over all instances.  Fs[i] receives the factor of Hs[i] and can
+ * be used with h2_solve like any other factor.
+ */
+h2_status h2_factor_batched(h2_context_t ctx, int count, const h2_matrix_t* Hs, double tol,
+                            h2_prec prec, h2_factor_t* Fs);
+
+/* Batched solve: one set of launches per (height, colour step) over all instances.
+ * B[i], X[i]: device N_i x nrhs FP64 with leading dimensions ldb[i], ldx[i]. */
+h2_status h2_solve_batched(h2_context_t ctx, int count, const h2_factor_t* Fs,
+                           const double* const* B, const int64_t* ldb, int nrhs,
+                           double* const* X, const int64_t* ldx);
+
+typedef enum {
+  H2_INT_SIZES = 0,    /* n_i of every cluster of the level */
+  H2_INT_RANKS = 1,    /* augmented rank k~_i */
+  H2_INT_COLORS = 2,   /* colour of every cluster */
+  H2_INT_FILL = 3,     /* fill pattern: pairs (j, k) of global node ids, flattened */
+  H2_INT_NTOP = 4,     /* order of the dense top block (level argument ignored) */
+  H2_INT_LEVELS = 5    /* skeletonized levels, leaf level first */
+} h2_int_kind;
+
+/* Copy an integer output of the factorization into the host buffer `buf`
+ * (capacity `cap` entries); *len receives the full length. */
+h2_status h2_factor_export_ints(h2_factor_t F, int level, h2_int_kind kind, int64_t* buf,
+                                int64_t cap, int64_t* len);
+
+typedef enum {
+  H2_MAT_Q = 0,      /* Q~_i = [V~perp, V~] of cluster i (local index) of the level, n_i x n_i */
+  H2_MAT_BLOCK = 1,  /* factored near block (i, j) of the level, n_i x n_j (panels in place) */
+  H2_MAT_TOP = 2     /* dense top block after its LU factorization, n_top x n_top */
+} h2_mat_kind;
+
+/* Copy one factor matrix to the HOST buffer `buf` (capacity `cap` doubles,
+ * column-major); *rows and *cols receive its shape (also when cap is too
+ * small, in which case nothing is copied).  Synchronizes with the device.
+ * For inspection of the factorization against a reference implementation. */
+h2_status h2_factor_export_matrix(h2_factor_t F, int level, h2_mat_kind kind, int i, int j,
+                                  double* buf, int64_t cap, int64_t* rows, int64_t* cols);
+
+typedef struct {
+  int32_t levels;          /* skeletonized levels */
+  int32_t max_colors;
+  int64_t n_top;
+  int64_t factor_bytes;    /* device bytes held by the factor */
+  int64_t peak_bytes;      /* high-water mark of device bytes during h2_factor */
+  double factor_flops;     /* algorithmic flop count of the factorization */
+  double solve_flops_per_rhs;
+  double time_ms[8];       /* device time per phase of the last h2_factor:
+                              0 augment, 1 project, 2 LU+multipliers, 3 Schur,
+                              4 close-out, 5 top LU, 6 host planning, 7 total */
+} h2_stats;
+h2_status h2_factor_get_stats(h2_factor_t F, h2_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* H2_H */

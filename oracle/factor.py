@@ -8,12 +8,12 @@ It follows Section 2 of the paper step by step, in its notation:
   * Algorithm 1 (factorize): levels from the leaves (d = L) up to the top level
     t (first level with admissible blocks); at each level colour the near
     graph and skeletonize colour by colour; then dense LU of the remnant.
-  * Algorithm 2 (skeletonizeColor), for each cluster i of a colour:
-      - truncated SVD of (I - V_i V_i^T) F_{i*} at eps_fill = eps_lu * ||A||
-        (Section 2.1: keep the left singular vectors that are needed) giving
-        the augmented basis V~_i = [V_i, Vbar_i];
-      - complement V~_i^perp and Q~_i = [V~_i^perp, V~_i] (redundant rows R
-        first, skeleton rows S last);
+  * Algorithm 2 (skeletonizeColor), in its order for the clusters i of a
+    colour: first, for every i, the truncated SVD of (I - V_i V_i^T) F_{i*}
+    at eps_fill = eps_lu * ||A|| (Section 2.1: keep the left singular vectors
+    that are needed) giving the augmented basis V~_i = [V_i, Vbar_i], its
+    complement V~_i^perp and Q~_i = [V~_i^perp, V~_i] (redundant rows R first,
+    skeleton rows S last); then, with all of them,
       - projection Q~^T D Q~ of the near blocks and V~^T F of the fill blocks
         (the V~^perp part of F is dropped: that is the truncation);
       - partial LU: LU of D_RR, elementary factors
@@ -132,19 +132,31 @@ def factor(H, tol, keep_trace=False):
         ncolors = max(color.values()) + 1
         Lf.ncolors = ncolors
         for c in range(ncolors):
-            for i in [q for q in nodes if color[q] == c]:
-                _skeletonize(i, H, n, V, D, F, nb[i], frow[i], fcol[i], nearset, eps_fill, Lf)
+            members = [q for q in nodes if color[q] == c]
+            # Algorithm 2: the parallel loop computes every basis of the colour
+            # from the fill present before the colour's projections ...
+            for i in members:
+                _augment(i, n, V, F, frow[i], eps_fill, Lf)
+            # ... then D = Q^T D Q and F = Q^T F Q with all of them ...
+            for i in members:
+                _project(i, D, F, nb[i], frow[i], fcol[i], Lf)
+            # ... then the partial LU of the colour, F = F + F^a
+            for i in members:
+                _partial_lu(i, D, F, nb[i], nearset, Lf)
         Fz.levels.append(Lf)
+        if keep_trace:
+            Lf.D_end = {key: blk.copy() for key, blk in D.items()}
         # ---- close-out: build level lev-1 ----
         n, V, D, F = _close_out(H, lev, n, V, D, F, Lf)
     return _top(Fz, H, t - 1, n, D)
 
 
-def _skeletonize(i, H, n, V, D, F, Ni, frow_i, fcol_i, nearset, eps_fill, Lf):
+def _augment(i, n, V, F, frow_i, eps_fill, Lf):
+    """Algorithm 2, parallel loop: truncated SVD of the projected fill row
+    (I - V V^T) F_{i*}, augmented basis V~ = [V, Vbar], complement, Q~."""
     ni = n[i]
     Vi = V[i]
     ki = Vi.shape[1]
-    # Algorithm 2: truncated SVD of the projected fill row (I - V V^T) F_{i*}
     if frow_i:
         Y = np.hstack([F[(i, j)] for j in frow_i])
         P = Y - Vi @ (Vi.T @ Y)
@@ -166,8 +178,14 @@ def _skeletonize(i, H, n, V, D, F, Ni, frow_i, fcol_i, nearset, eps_fill, Lf):
     r = ni - kt
     # complement: last columns of the full orthogonal factor of V~
     Qfull, _ = np.linalg.qr(Vt, mode="complete") if kt else (np.eye(ni), None)
-    Qt = np.hstack([Qfull[:, kt:], Vt])  # Q~ = [V~perp, V~]
-    # projection of the inadmissible blocks and of the fill blocks
+    Lf.Q[i] = np.hstack([Qfull[:, kt:], Vt])  # Q~ = [V~perp, V~]
+    Lf.r[i], Lf.kt[i] = r, kt
+
+
+def _project(i, D, F, Ni, frow_i, fcol_i, Lf):
+    """D <- Q^T D Q and F <- Q^T F Q for cluster i; the V~perp part of F is
+    dropped (the fill truncation)."""
+    Qt, r = Lf.Q[i], Lf.r[i]
     D[(i, i)] = Qt.T @ D[(i, i)] @ Qt
     for j in Ni:
         if j != i:
@@ -175,16 +193,20 @@ def _skeletonize(i, H, n, V, D, F, Ni, frow_i, fcol_i, nearset, eps_fill, Lf):
             D[(j, i)] = D[(j, i)] @ Qt
     for j in frow_i:
         Fij = Qt.T @ F[(i, j)]
-        Fij[:r, :] = 0.0  # the V~perp part of the fill is truncated
+        Fij[:r, :] = 0.0
         F[(i, j)] = Fij
     for j in fcol_i:
         Fji = F[(j, i)] @ Qt
         Fji[:, :r] = 0.0
         F[(j, i)] = Fji
-    Lf.Q[i], Lf.r[i], Lf.kt[i] = Qt, r, kt
+
+
+def _partial_lu(i, D, F, Ni, nearset, Lf):
+    """Partial LU of the redundant rows/columns of i: LU(D_RR), elementary
+    factors, Schur updates to D (near pairs) or to the fill F (others)."""
+    r = Lf.r[i]
     if r == 0:
         return
-    # partial LU of D restricted to the redundant rows/columns of i
     lu = sla.lu_factor(D[(i, i)][:r, :r])
     Lf.lu[i] = lu
     Cp, Rp = {}, {}
@@ -198,8 +220,8 @@ def _skeletonize(i, H, n, V, D, F, Ni, frow_i, fcol_i, nearset, eps_fill, Lf):
             C = D[(j, i)][:, :r].copy()
             Rw = D[(i, j)][:r, :].copy()
         Cp[j], Rp[j] = C, Rw
-    Xs = {j: sla.lu_solve(lu, Cp[j].T, trans=1, check_finite=False).T for j in Ni}  # D_{j,R} D_RR^{-1}
-    Ys = {k: sla.lu_solve(lu, Rp[k], check_finite=False) for k in Ni}  # D_RR^{-1} D_{R,k}
+    Xs = {j: sla.lu_solve(lu, Cp[j].T, trans=1, check_finite=False).T for j in Ni}
+    Ys = {k: sla.lu_solve(lu, Rp[k], check_finite=False) for k in Ni}
     for j in Ni:
         for k in Ni:
             delta = -(Cp[j] @ Ys[k])

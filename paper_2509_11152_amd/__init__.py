@@ -1,0 +1,282 @@
+"""Python binding of the MI355X H^2 strong recursive skeletonization solver.
+
+Argument marshalling only: every step of the factorization, solve, matvec and
+refinement runs in the HIP library libh2rss.so (built in-tree by build.py)
+behind the C ABI of include/h2.h.  PyTorch provides device memory and the
+stream.  Importing this package fails loudly when the library is missing.
+
+Vectors are torch float64 CUDA tensors of shape (N, nrhs) in original point
+order; they are handed to the library column-major (leading dimension N).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libh2rss.so")
+
+H2_PREC_FP64 = 0
+H2_PREC_FP32 = 1
+INT_SIZES, INT_RANKS, INT_COLORS, INT_FILL, INT_NTOP, INT_LEVELS = range(6)
+MAT_Q, MAT_BLOCK, MAT_TOP = range(3)
+
+STATUS = {
+    0: "success", 1: "invalid argument", 2: "format", 3: "out of memory", 4: "singular",
+    5: "numeric", 6: "hip", 7: "not converged", 8: "unsupported",
+}
+
+
+class H2Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _IROpts(ctypes.Structure):
+    _fields_ = [("target_bkwd", ctypes.c_double), ("restart", ctypes.c_int),
+                ("max_outer", ctypes.c_int), ("inner_rtol", ctypes.c_double)]
+
+
+class _IRReport(ctypes.Structure):
+    _fields_ = [("outer_iterations", ctypes.c_int), ("inner_iterations", ctypes.c_int),
+                ("max_bkwd", ctypes.c_double)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("max_colors", ctypes.c_int32),
+                ("n_top", ctypes.c_int64), ("factor_bytes", ctypes.c_int64),
+                ("peak_bytes", ctypes.c_int64), ("factor_flops", ctypes.c_double),
+                ("solve_flops_per_rhs", ctypes.c_double), ("time_ms", ctypes.c_double * 8)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("top_level", ctypes.c_int32), ("n_nodes", ctypes.c_int32),
+                ("norm2", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+
+
+# exported symbols of include/h2.h with (restype, argtypes)
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_SIG = {
+    "h2_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "h2_context_create": (ctypes.c_int, [ctypes.c_int, _P, ctypes.POINTER(_P)]),
+    "h2_context_destroy": (ctypes.c_int, [_P]),
+    "h2_last_error": (ctypes.c_char_p, [_P]),
+    "h2_sync": (ctypes.c_int, [_P]),
+    "h2_matrix_load": (ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.POINTER(_P)]),
+    "h2_matrix_destroy": (ctypes.c_int, [_P]),
+    "h2_matrix_get_info": (ctypes.c_int, [_P, ctypes.POINTER(_Info)]),
+    "h2_matvec": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, _P, _I64]),
+    "h2_factor": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_P)]),
+    "h2_factor_destroy": (ctypes.c_int, [_P]),
+    "h2_solve": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, _P, _I64]),
+    "h2_solve_ir": (ctypes.c_int, [_P, _P, _P, _P, _I64, ctypes.c_int, _P, _I64,
+                                   ctypes.POINTER(_IROpts), ctypes.POINTER(_IRReport)]),
+    "h2_factor_batched": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.c_double,
+                                         ctypes.c_int, ctypes.POINTER(_P)]),
+    "h2_solve_batched": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                        ctypes.POINTER(_I64), ctypes.c_int, ctypes.POINTER(_P),
+                                        ctypes.POINTER(_I64)]),
+    "h2_factor_export_ints": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int,
+                                             ctypes.POINTER(_I64), _I64, ctypes.POINTER(_I64)]),
+    "h2_factor_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(_Stats)]),
+    "h2_factor_export_matrix": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_int, _P, _I64, ctypes.POINTER(_I64),
+                                               ctypes.POINTER(_I64)]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library {LIB_PATH} is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIG.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(code, ctx=None):
+    if code != 0:
+        msg = lib.h2_last_error(ctx.ptr).decode() if ctx is not None else ""
+        raise H2Error(code, msg)
+
+
+def _colmajor(X):
+    """(N, nrhs) tensor -> contiguous (nrhs, N) tensor = column-major N x nrhs."""
+    import torch
+
+    if X.dim() == 1:
+        X = X[:, None]
+    return X.t().contiguous().to(torch.float64)
+
+
+class Context:
+    def __init__(self, device=0, stream=None):
+        import torch
+
+        self.torch_stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.ptr = _P()
+        _check(lib.h2_context_create(device, _P(self.torch_stream.cuda_stream), ctypes.byref(self.ptr)))
+
+    def sync(self):
+        _check(lib.h2_sync(self.ptr), self)
+
+    def close(self):
+        if self.ptr:
+            lib.h2_context_destroy(self.ptr)
+            self.ptr = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Matrix:
+    """A serialized H^2 matrix (uint8 numpy blob) loaded onto the device."""
+
+    def __init__(self, ctx, blob):
+        self.ctx = ctx
+        buf = np.ascontiguousarray(np.asarray(blob, dtype=np.uint8))
+        self.ptr = _P()
+        _check(lib.h2_matrix_load(ctx.ptr, buf.ctypes.data_as(_P), buf.nbytes,
+                                  ctypes.byref(self.ptr)), ctx)
+        info = _Info()
+        _check(lib.h2_matrix_get_info(self.ptr, ctypes.byref(info)), ctx)
+        self.n = info.n
+        self.depth = info.depth
+        self.top_level = info.top_level
+        self.norm2 = info.norm2
+        self.device_bytes = info.device_bytes
+
+    def matvec(self, X):
+        import torch
+
+        Xc = _colmajor(X)
+        nrhs = Xc.shape[0]
+        Y = torch.empty_like(Xc)
+        _check(lib.h2_matvec(self.ctx.ptr, self.ptr, _P(Xc.data_ptr()), self.n, nrhs,
+                             _P(Y.data_ptr()), self.n), self.ctx)
+        self.ctx.sync()
+        return Y.t()
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                lib.h2_matrix_destroy(self.ptr)
+                self.ptr = _P()
+        except Exception:
+            pass
+
+
+class Factor:
+    def __init__(self, ctx, H, tol, prec=H2_PREC_FP64, _ptr=None):
+        self.ctx = ctx
+        self.n = H.n
+        self.prec = prec
+        if _ptr is not None:
+            self.ptr = _ptr
+        else:
+            self.ptr = _P()
+            _check(lib.h2_factor(ctx.ptr, H.ptr, float(tol), prec, ctypes.byref(self.ptr)), ctx)
+
+    def solve(self, B, out=None):
+        import torch
+
+        Bc = _colmajor(B)
+        nrhs = Bc.shape[0]
+        X = torch.empty_like(Bc) if out is None else out
+        _check(lib.h2_solve(self.ctx.ptr, self.ptr, _P(Bc.data_ptr()), self.n, nrhs,
+                            _P(X.data_ptr()), self.n), self.ctx)
+        self.ctx.sync()
+        return X.t()
+
+    def solve_colmajor(self, Bc, Xc):
+        """Solve on preallocated (nrhs, N) buffers without syncing (timing loops)."""
+        _check(lib.h2_solve(self.ctx.ptr, self.ptr, _P(Bc.data_ptr()), self.n, Bc.shape[0],
+                            _P(Xc.data_ptr()), self.n), self.ctx)
+
+    def ints(self, level, kind):
+        n = ctypes.c_int64(0)
+        _check(lib.h2_factor_export_ints(self.ptr, level, kind, None, 0, ctypes.byref(n)))
+        buf = (ctypes.c_int64 * max(n.value, 1))()
+        _check(lib.h2_factor_export_ints(self.ptr, level, kind, buf, n.value, ctypes.byref(n)))
+        return np.array(buf[:n.value], dtype=np.int64)
+
+    def matrix(self, level, kind, i=0, j=0):
+        """Copy a factor matrix (Q~ of cluster i, near block (i, j), or the LU'd top block)."""
+        m, n = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib.h2_factor_export_matrix(self.ptr, level, kind, i, j, None, 0, ctypes.byref(m),
+                                           ctypes.byref(n)))
+        out = np.zeros((n.value, m.value))
+        if m.value * n.value:
+            _check(lib.h2_factor_export_matrix(self.ptr, level, kind, i, j, out.ctypes.data_as(_P),
+                                               out.size, ctypes.byref(m), ctypes.byref(n)))
+        return out.T
+
+    def levels(self):
+        return [int(x) for x in self.ints(0, INT_LEVELS)]
+
+    def stats(self):
+        s = _Stats()
+        _check(lib.h2_factor_get_stats(self.ptr, ctypes.byref(s)))
+        return {"levels": s.levels, "max_colors": s.max_colors, "n_top": s.n_top,
+                "factor_bytes": s.factor_bytes, "peak_bytes": s.peak_bytes,
+                "factor_flops": s.factor_flops, "time_ms": list(s.time_ms)}
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                lib.h2_factor_destroy(self.ptr)
+                self.ptr = _P()
+        except Exception:
+            pass
+
+
+def solve_ir(ctx, H, F, B, target=1e-12, restart=30, max_outer=20, inner_rtol=1e-8):
+    """GMRES-IR: returns (X, report dict); raises on errors other than NOT_CONVERGED."""
+    import torch
+
+    Bc = _colmajor(B)
+    nrhs = Bc.shape[0]
+    X = torch.empty_like(Bc)
+    opts = _IROpts(target, restart, max_outer, inner_rtol)
+    rep = _IRReport()
+    code = lib.h2_solve_ir(ctx.ptr, H.ptr, F.ptr, _P(Bc.data_ptr()), H.n, nrhs, _P(X.data_ptr()),
+                           H.n, ctypes.byref(opts), ctypes.byref(rep))
+    if code not in (0, 7):
+        _check(code, ctx)
+    return X.t(), {"outer": rep.outer_iterations, "inner": rep.inner_iterations,
+                   "max_bkwd": rep.max_bkwd, "converged": code == 0}
+
+
+def factor_batched(ctx, Hs, tol, prec=H2_PREC_FP64):
+    arr = (_P * len(Hs))(*[H.ptr for H in Hs])
+    out = (_P * len(Hs))()
+    _check(lib.h2_factor_batched(ctx.ptr, len(Hs), arr, float(tol), prec, out), ctx)
+    return [Factor(ctx, H, tol, prec, _ptr=_P(out[i])) for i, H in enumerate(Hs)]
+
+
+def solve_batched(ctx, Fs, Bs):
+    """Bs: list of (N_i, nrhs) tensors with the same nrhs; returns list of X_i."""
+    import torch
+
+    Bcs = [_colmajor(B) for B in Bs]
+    nrhs = Bcs[0].shape[0]
+    Xcs = [torch.empty_like(b) for b in Bcs]
+    n = len(Fs)
+    fa = (_P * n)(*[F.ptr for F in Fs])
+    ba = (_P * n)(*[_P(b.data_ptr()) for b in Bcs])
+    xa = (_P * n)(*[_P(x.data_ptr()) for x in Xcs])
+    lb = (_I64 * n)(*[F.n for F in Fs])
+    _check(lib.h2_solve_batched(ctx.ptr, n, fa, ba, lb, nrhs, xa, lb), ctx)
+    ctx.sync()
+    return [x.t() for x in Xcs]

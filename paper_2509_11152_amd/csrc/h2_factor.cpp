@@ -1,0 +1,926 @@
+// Factorization driver: strong recursive skeletonization level by level
+// (Algorithm 1), colour by colour (Algorithm 2), batched over instances.
+//
+// Per tree level the host plans everything that depends only on structure and
+// on the sizes n_i of the level (colours, fill pattern, block layout, task
+// lists); ranks are decided on the device and read by the kernels through the
+// level's r array, so a level runs without host synchronisation.  The host
+// synchronises once per level to read the ranks, which fix the sizes of the
+// next level (n_tau = sum of the children's k~).
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <memory>
+#include <numeric>
+
+#include "h2_driver.h"
+
+namespace h2drv {
+
+using namespace h2k;
+
+namespace {
+
+uint64_t node_hash(uint64_t z) {
+  // SplitMix64 output finaliser (Steele, Lea, Flood, OOPSLA 2014)
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// Greedy colouring of the near graph in decreasing (hash(id), id) priority;
+// identical to the Jones-Plassmann result for the same priorities.
+void color_level(LevelPlan& P) {
+  std::vector<int> order(P.nl);
+  std::iota(order.begin(), order.end(), 0);
+  std::vector<uint64_t> h(P.nl);
+  for (int i = 0; i < P.nl; ++i) h[i] = node_hash((uint64_t)(P.a + i));
+  std::sort(order.begin(), order.end(), [&](int x, int y) {
+    if (h[x] != h[y]) return h[x] > h[y];
+    return x > y;
+  });
+  P.color.assign(P.nl, -1);
+  std::vector<int> mark;
+  int nc = 0;
+  for (int v : order) {
+    mark.assign(P.nb[v].size() + 2, 0);
+    for (int j : P.nb[v]) {
+      const int c = P.color[j];
+      if (j != v && c >= 0 && c < (int)mark.size()) mark[c] = 1;
+    }
+    int c = 0;
+    while (mark[c]) ++c;
+    P.color[v] = c;
+    nc = std::max(nc, c + 1);
+  }
+  P.ncolors = nc;
+  P.members.assign(nc, {});
+  for (int i = 0; i < P.nl; ++i) P.members[P.color[i]].push_back(i);
+}
+
+}  // namespace
+
+// Build the plan of level `lev` given the sizes n and the lifted fill pairs.
+void plan_level(const h2_matrix_s& H, int lev, const std::vector<int>& n,
+                const std::vector<std::pair<int, int>>& lifted, LevelPlan& P) {
+  P.lev = lev;
+  P.a = H.lp[lev];
+  P.nl = H.lp[lev + 1] - P.a;
+  P.n = n;
+  P.k.resize(P.nl);
+  for (int i = 0; i < P.nl; ++i) P.k[i] = H.rank[P.a + i];
+  P.nb.assign(P.nl, {});
+  for (int i = 0; i < P.nl; ++i)
+    for (int64_t e = H.near_ptr[P.a + i]; e < H.near_ptr[P.a + i + 1]; ++e)
+      P.nb[i].push_back(H.near_col[e] - P.a);
+  color_level(P);
+  // fill pattern: lifted pairs plus non-near pairs of neighbours of a common
+  // cluster; first colour writing each fill entry
+  std::vector<std::vector<std::pair<int, int>>> rows(P.nl);  // (col, firstc)
+  {
+    std::vector<int> stamp(P.nl, -1), minc(P.nl, INT_MAX);
+    std::vector<int> cols;
+    for (int j = 0; j < P.nl; ++j) {
+      for (int i : P.nb[j]) stamp[i] = j;  // near of j
+      cols.clear();
+      for (int i : P.nb[j]) {
+        const int ci = P.color[i];
+        for (int k : P.nb[i]) {
+          if (stamp[k] == j) {
+            // near of j or already collected
+            if (minc[k] != INT_MAX && ci < minc[k]) minc[k] = ci;
+            continue;
+          }
+          stamp[k] = j;
+          minc[k] = ci;
+          cols.push_back(k);
+        }
+      }
+      for (int k : cols) {
+        rows[j].push_back({k, minc[k]});
+        minc[k] = INT_MAX;
+      }
+      for (int i : P.nb[j]) minc[i] = INT_MAX;
+    }
+  }
+  for (auto& pr : lifted) {
+    auto& rw = rows[pr.first];
+    bool found = false;
+    for (auto& x : rw)
+      if (x.first == pr.second) {
+        x.second = -1;
+        found = true;
+      }
+    if (!found) rw.push_back({pr.second, -1});
+  }
+  P.pptr.assign(P.nl + 1, 0);
+  P.pcol.clear();
+  P.isF.clear();
+  P.firstc.clear();
+  P.fill_pairs.clear();
+  for (int j = 0; j < P.nl; ++j) {
+    auto& rw = rows[j];
+    std::sort(rw.begin(), rw.end());
+    // merge near (sorted) and fill (sorted)
+    size_t a = 0, b = 0;
+    const auto& nbj = P.nb[j];
+    while (a < nbj.size() || b < rw.size()) {
+      if (b >= rw.size() || (a < nbj.size() && nbj[a] < rw[b].first)) {
+        P.pcol.push_back(nbj[a++]);
+        P.isF.push_back(0);
+        P.firstc.push_back(INT_MAX);
+      } else {
+        P.pcol.push_back(rw[b].first);
+        P.isF.push_back(1);
+        P.firstc.push_back(rw[b].second);
+        P.fill_pairs.push_back({j, rw[b].first});
+        ++b;
+      }
+    }
+    P.pptr[j + 1] = (int64_t)P.pcol.size();
+  }
+  // layout: D entries and F entries in two buffers, CSR order, n_i x n_j column-major
+  P.poff.assign(P.pcol.size(), 0);
+  P.nD = P.nF = 0;
+  for (int j = 0; j < P.nl; ++j)
+    for (int64_t e = P.pptr[j]; e < P.pptr[j + 1]; ++e) {
+      const int64_t sz = (int64_t)P.n[j] * P.n[P.pcol[e]];
+      if (P.isF[e]) {
+        P.poff[e] = P.nF;
+        P.nF += sz;
+      } else {
+        P.poff[e] = P.nD;
+        P.nD += sz;
+      }
+    }
+  P.offQ.assign(P.nl, 0);
+  P.offV.assign(P.nl, 0);
+  P.offPiv.assign(P.nl, 0);
+  P.nQ = P.nV = P.nPiv = 0;
+  for (int i = 0; i < P.nl; ++i) {
+    P.offQ[i] = P.nQ;
+    P.nQ += (int64_t)P.n[i] * P.n[i];
+    P.offV[i] = P.nV;
+    P.nV += (int64_t)P.n[i] * P.k[i];
+    P.offPiv[i] = P.nPiv;
+    P.nPiv += P.n[i];
+  }
+  P.r.assign(P.nl, 0);
+}
+
+namespace {
+
+template <class T> LevelStore<T>& store_of(h2_factor_s* F, size_t li);
+template <> LevelStore<double>& store_of<double>(h2_factor_s* F, size_t li) { return F->st64[li]; }
+template <> LevelStore<float>& store_of<float>(h2_factor_s* F, size_t li) { return F->st32[li]; }
+template <class T> DevArray<T>& top_of(h2_factor_s* F);
+template <> DevArray<double>& top_of<double>(h2_factor_s* F) { return F->M64; }
+template <> DevArray<float>& top_of<float>(h2_factor_s* F) { return F->M32; }
+template <class T> void add_store(h2_factor_s* F);
+template <> void add_store<double>(h2_factor_s* F) { F->st64.emplace_back(); }
+template <> void add_store<float>(h2_factor_s* F) { F->st32.emplace_back(); }
+
+template <class T> struct Inst {
+  h2_matrix_s* H = nullptr;
+  h2_factor_s* F = nullptr;
+  const T* data = nullptr;   // H data in the working precision
+  DevArray<T> data_conv;     // converted copy (FP32 runs)
+  int lev = 0;               // level being processed
+  int tlev = -1;             // matrix top level
+  bool done = false;
+  int rbase = 0;             // offset of this instance's clusters in the height's r array
+  size_t li = 0;             // index of the current level in F->plans
+  DevArray<T> Fbuf;          // fill blocks of the current level
+  DevArray<T> Vbuf;          // bases of the current level
+  double flops = 0;
+};
+
+template <class T> int64_t copy_tiles(int rows, int cols) {
+  return ((int64_t)rows * cols + kCopyTile - 1) / kCopyTile;
+}
+
+template <class T> struct CopyBatch {
+  std::vector<CTask<T, T>> tasks;
+  int64_t tiles = 0;
+  void add(const T* src, int64_t lds, T* dst, int64_t ldd, int rows, int cols, int add) {
+    if (rows <= 0 || cols <= 0) return;
+    CTask<T, T> t{};
+    t.src = src;
+    t.dst = dst;
+    t.lds = lds;
+    t.ldd = ldd;
+    t.rows = rows;
+    t.cols = cols;
+    t.add = add;
+    t.tile0 = tiles;
+    tiles += copy_tiles<T>(rows, cols);
+    tasks.push_back(t);
+  }
+  void launch(DescArena& ar, hipStream_t s) {
+    if (tasks.empty()) return;
+    launch_copy<T, T>(ar.put(tasks), (int)tasks.size(), tiles, s);
+  }
+};
+
+// initialise the leaf level: D blocks from the blob, V = U, F = 0
+template <class T> void init_leaf(Inst<T>& I, LevelStore<T>& S, LevelPlan& P, CopyBatch<T>& cb) {
+  const h2_matrix_s& H = *I.H;
+  for (int i = 0; i < P.nl; ++i) {
+    const int q = P.a + i;
+    for (int64_t e = H.near_ptr[q]; e < H.near_ptr[q + 1]; ++e) {
+      const int j = H.near_col[e] - P.a;
+      const int64_t pe = P.find(i, j);
+      cb.add(I.data + H.offD[e], P.n[i], S.D.p + P.poff[pe], P.n[i], P.n[i], P.n[j], 0);
+    }
+    cb.add(I.data + H.offU[q], P.n[i], I.Vbuf.p + P.offV[i], P.n[i], P.n[i], P.k[i], 0);
+  }
+}
+
+template <class T> void alloc_level(Inst<T>& I, LevelPlan& P) {
+  add_store<T>(I.F);
+  LevelStore<T>& S = store_of<T>(I.F, I.F->plans.size() - 1);
+  S.D.alloc(P.nD, &I.F->tr);
+  S.Q.alloc(P.nQ, &I.F->tr);
+  S.piv.alloc(P.nPiv, &I.F->tr);
+  I.Fbuf.alloc(P.nF, &I.F->tr);
+  I.Vbuf.alloc(P.nV, &I.F->tr);
+}
+
+}  // namespace
+
+template <class T>
+static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double tol) {
+  hipStream_t s = ctx->stream;
+  DescArena& ar = ctx->arena;
+  ar.s = s;
+  H2_HIP(hipMemsetAsync(ctx->d_err, 0, sizeof(int), s));
+  const auto t_start = std::chrono::steady_clock::now();
+  double plan_ms = 0;
+  auto ms_since = [](std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  };
+  // events for phase timing
+  std::vector<hipEvent_t> evpool;
+  auto new_event = [&]() {
+    hipEvent_t e;
+    H2_HIP(hipEventCreate(&e));
+    evpool.push_back(e);
+    return e;
+  };
+  double phase_ms[8] = {0};
+
+  // ---- leaf level plans ----
+  {
+    const auto t0 = std::chrono::steady_clock::now();
+    CopyBatch<T> cb;
+    for (auto& I : insts) {
+      const h2_matrix_s& H = *I.H;
+      I.lev = H.L;
+      I.tlev = H.top;
+      std::vector<int> n(H.lp[H.L + 1] - H.lp[H.L]);
+      for (size_t i = 0; i < n.size(); ++i) n[i] = H.size(H.lp[H.L] + (int)i);
+      if (I.tlev < 0) {
+        // no admissible block: the whole leaf level is the dense top block
+        I.done = true;
+        continue;
+      }
+      I.F->plans.emplace_back();
+      LevelPlan& P = I.F->plans.back();
+      plan_level(H, H.L, n, {}, P);
+      alloc_level(I, P);
+      I.li = I.F->plans.size() - 1;
+      LevelStore<T>& S = store_of<T>(I.F, I.li);
+      launch_fill<T>(I.Fbuf.p, I.Fbuf.n, T(0), s);
+      init_leaf(I, S, P, cb);
+    }
+    cb.launch(ar, s);
+    plan_ms += ms_since(t0);
+  }
+
+  // ---- heights ----
+  for (;;) {
+    std::vector<Inst<T>*> act;
+    for (auto& I : insts)
+      if (!I.done) act.push_back(&I);
+    if (act.empty()) break;
+    const auto t0 = std::chrono::steady_clock::now();
+    int total = 0, maxc = 0;
+    for (auto* I : act) {
+      LevelPlan& P = I->F->plans[I->li];
+      I->rbase = total;
+      total += P.nl;
+      maxc = std::max(maxc, P.ncolors);
+    }
+    DevArray<int32_t> rdev;
+    rdev.alloc(total, nullptr);
+    launch_fill<int32_t>(rdev.p, total, 0, s);
+    int maxn_all = 1;
+    for (auto* I : act)
+      for (int x : I->F->plans[I->li].n) maxn_all = std::max(maxn_all, x);
+    if ((int64_t)maxn_all * kStrip * (int64_t)sizeof(T) > 160 * 1024)
+      throw H2Error(H2_ERROR_UNSUPPORTED, "cluster of order " + std::to_string(maxn_all) +
+                                              " exceeds the strip kernel's LDS capacity");
+    // augmentation workspace: max over colours of the sum of per-task scratch
+    int64_t wmax = 0;
+    for (int c = 0; c < maxc; ++c) {
+      int64_t w = 0;
+      for (auto* I : act) {
+        LevelPlan& P = I->F->plans[I->li];
+        if (c < P.ncolors)
+          for (int i : P.members[c]) w += aug_work_elems(P.n[i]);
+      }
+      wmax = std::max(wmax, w);
+    }
+    DevArray<T> work;
+    work.alloc(wmax, &act[0]->F->tr);
+    plan_ms += ms_since(t0);
+
+    hipEvent_t ev_level0 = new_event();
+    H2_HIP(hipEventRecord(ev_level0, s));
+    std::vector<std::pair<int, hipEvent_t>> marks;  // (phase, event at phase end)
+    for (int c = 0; c < maxc; ++c) {
+      const auto tc = std::chrono::steady_clock::now();
+      std::vector<AugTask<T>> aug;
+      std::vector<FillRef<T>> refs;
+      std::vector<STask<T>> sl, sr;
+      int64_t nsl = 0, nsr = 0;
+      std::vector<LUTask<T>> lus;
+      std::vector<TrsmTask<T>> trs;
+      std::vector<GOut<T>> outs;
+      std::vector<GCon<T>> cons;
+      int64_t gtiles = 0;
+      int64_t woff = 0;
+      for (auto* I : act) {
+        LevelPlan& P = I->F->plans[I->li];
+        if (c >= P.ncolors) continue;
+        LevelStore<T>& S = store_of<T>(I->F, I->li);
+        const int rb = I->rbase;
+        auto blk = [&](int64_t e) -> T* { return (P.isF[e] ? I->Fbuf.p : S.D.p) + P.poff[e]; };
+        // active-window start of neighbour j at colour c: r_j once processed
+        auto wdyn = [&](int j, bool incl) -> int {
+          return (P.color[j] < c || (incl && P.color[j] == c)) ? rb + j : -1;
+        };
+        for (int i : P.members[c]) {
+          const int ni = P.n[i];
+          // ---- augmentation task ----
+          AugTask<T> at{};
+          at.V = I->Vbuf.p + P.offV[i];
+          at.Q = S.Q.p + P.offQ[i];
+          at.work = work.p + woff;
+          woff += aug_work_elems(ni);
+          at.n = ni;
+          at.k = P.k[i];
+          at.fbeg = (int)refs.size();
+          for (int64_t e = P.pptr[i]; e < P.pptr[i + 1]; ++e) {
+            if (!P.isF[e] || P.firstc[e] >= c) continue;  // zero until a later colour
+            const int j = P.pcol[e];
+            FillRef<T> fr{};
+            fr.F = blk(e);
+            fr.ld = ni;
+            fr.ncols = P.n[j];
+            fr.d0 = wdyn(j, false);
+            refs.push_back(fr);
+          }
+          at.fend = (int)refs.size();
+          at.ri = rb + i;
+          aug.push_back(at);
+          // ---- projection: row i (left, Q^T X) and column i (right, X Q) ----
+          for (int64_t e = P.pptr[i]; e < P.pptr[i + 1]; ++e) {
+            const int j = P.pcol[e];
+            if (P.isF[e] && P.firstc[e] >= c && j != i) {
+              // still zero: a zero block stays zero under the projection
+              continue;
+            }
+            STask<T> t{};
+            t.X = blk(e);
+            t.Q = S.Q.p + P.offQ[i];
+            t.ldx = ni;
+            t.n = ni;
+            t.ext = P.n[j];
+            t.d0 = wdyn(j, false);
+            t.s0 = 0;
+            t.side = 0;
+            t.trans = 1;
+            t.strip0 = nsl;
+            nsl += (P.n[j] + kStrip - 1) / kStrip;
+            if (P.n[j] > 0 && ni > 0) sl.push_back(t);
+            else nsl -= (P.n[j] + kStrip - 1) / kStrip;
+          }
+          // column i: entries (j, i) for j in the pattern row of i (symmetric pattern)
+          for (int64_t e = P.pptr[i]; e < P.pptr[i + 1]; ++e) {
+            const int j = P.pcol[e];
+            const int64_t et = P.find(j, i);
+            if (P.isF[et] && P.firstc[et] >= c && j != i) continue;
+            STask<T> t{};
+            t.X = blk(et);
+            t.Q = S.Q.p + P.offQ[i];
+            t.ldx = P.n[j];
+            t.n = ni;
+            t.ext = P.n[j];
+            t.d0 = wdyn(j, false);
+            t.s0 = 0;
+            t.side = 1;
+            t.trans = 0;
+            t.strip0 = nsr;
+            const int64_t ns = (P.n[j] + kStrip - 1) / kStrip;
+            if (P.n[j] > 0 && ni > 0) {
+              sr.push_back(t);
+              nsr += ns;
+            }
+          }
+          // ---- LU of D_RR and the U-blocks D_RR^{-1} D_{R,k} ----
+          const int64_t eii = P.find(i, i);
+          LUTask<T> lt{};
+          lt.A = S.D.p + P.poff[eii];
+          lt.piv = S.piv.p + P.offPiv[i];
+          lt.lda = ni;
+          lt.ri = rb + i;
+          lus.push_back(lt);
+          for (int k : P.nb[i]) {
+            const int64_t eik = P.find(i, k);
+            TrsmTask<T> tt{};
+            tt.LU = lt.A;
+            tt.piv = lt.piv;
+            tt.B = S.D.p + P.poff[eik];
+            tt.ldlu = ni;
+            tt.ldb = ni;
+            tt.ncols = P.n[k];
+            tt.ri = rb + i;
+            tt.rs = 0;
+            tt.c0d = wdyn(k, true);
+            tt.c0s = 0;
+            trs.push_back(tt);
+          }
+        }
+        // ---- Schur complement / fill-in targets, owner-computes ----
+        // target (j, k) collects every i of the colour with j, k in N(i)
+        std::vector<std::pair<int64_t, int>> inc;  // (target entry, contributor i)
+        for (int i : P.members[c])
+          for (int j : P.nb[i])
+            for (int k : P.nb[i]) inc.push_back({P.find(j, k), i});
+        std::sort(inc.begin(), inc.end());
+        for (size_t a = 0; a < inc.size();) {
+          size_t b = a;
+          while (b < inc.size() && inc[b].first == inc[a].first) ++b;
+          const int64_t e = inc[a].first;
+          // row of entry e
+          const int j = (int)(std::upper_bound(P.pptr.begin(), P.pptr.end(), e) - P.pptr.begin()) - 1;
+          const int k = P.pcol[e];
+          GOut<T> o{};
+          o.C = blk(e);
+          o.ldc = P.n[j];
+          o.m = P.n[j];
+          o.n = P.n[k];
+          o.m0d = wdyn(j, true);
+          o.m0s = 0;
+          o.m1d = -1;
+          o.n0d = wdyn(k, true);
+          o.n0s = 0;
+          o.cbeg = (int)cons.size();
+          for (size_t q = a; q < b; ++q) {
+            const int i = inc[q].second;
+            GCon<T> g{};
+            g.A = S.D.p + P.poff[P.find(j, i)];
+            g.lda = P.n[j];
+            g.B = S.D.p + P.poff[P.find(i, k)];
+            g.ldb = P.n[i];
+            g.k = P.n[i];
+            g.k0d = -1;
+            g.k0s = 0;
+            g.k1d = rb + i;
+            g.transA = 0;
+            cons.push_back(g);
+          }
+          o.cend = (int)cons.size();
+          o.tm = (o.m + 63) / 64;
+          o.tn = (o.n + 63) / 64;
+          o.tile0 = gtiles;
+          o.alpha = T(-1);
+          o.beta = T(1);
+          if (o.tm > 0 && o.tn > 0) {
+            gtiles += (int64_t)o.tm * o.tn;
+            outs.push_back(o);
+          }
+          a = b;
+        }
+      }
+      plan_ms += ms_since(tc);
+      if (aug.empty()) continue;
+      const T eps_fill = T(tol * act[0]->H->norm2);
+      // every instance shares tol but has its own norm: fold the norm in per task
+      // by scaling? keep one threshold per launch group of equal norm.
+      bool same_norm = true;
+      for (auto* I : act) same_norm &= (I->H->norm2 == act[0]->H->norm2);
+      int maxn = 1;
+      for (auto& t : sl) maxn = std::max(maxn, t.n);
+      for (auto& t : sr) maxn = std::max(maxn, t.n);
+      const int32_t* dyn = rdev.p;
+      if (same_norm) {
+        launch_augment<T>(ar.put(aug), (int)aug.size(), ar.put(refs), rdev.p, eps_fill,
+                          ctx->d_err, s);
+      } else {
+        // launch per instance with its own threshold
+        size_t pos = 0;
+        for (auto* I : act) {
+          LevelPlan& P = I->F->plans[I->li];
+          if (c >= P.ncolors) continue;
+          const size_t cnt = P.members[c].size();
+          std::vector<AugTask<T>> part(aug.begin() + pos, aug.begin() + pos + cnt);
+          launch_augment<T>(ar.put(part), (int)cnt, ar.put(refs), rdev.p,
+                            T(tol * I->H->norm2), ctx->d_err, s);
+          pos += cnt;
+        }
+      }
+      hipEvent_t e1 = new_event();
+      H2_HIP(hipEventRecord(e1, s));
+      marks.push_back({0, e1});
+      launch_strip<T>(ar.put(sl), (int)sl.size(), dyn, nsl, maxn, s);
+      launch_strip<T>(ar.put(sr), (int)sr.size(), dyn, nsr, maxn, s);
+      hipEvent_t e2 = new_event();
+      H2_HIP(hipEventRecord(e2, s));
+      marks.push_back({1, e2});
+      launch_lu<T>(ar.put(lus), (int)lus.size(), dyn, ctx->d_err, s);
+      launch_trsm<T>(ar.put(trs), (int)trs.size(), dyn, s);
+      hipEvent_t e3 = new_event();
+      H2_HIP(hipEventRecord(e3, s));
+      marks.push_back({2, e3});
+      launch_gemm<T>(ar.put(outs), (int)outs.size(), ar.put(cons), dyn, gtiles, 0, s);
+      hipEvent_t e4 = new_event();
+      H2_HIP(hipEventRecord(e4, s));
+      marks.push_back({3, e4});
+    }
+    // ---- level end: read the ranks ----
+    std::vector<int32_t> rh(total);
+    H2_HIP(hipMemcpyAsync(rh.data(), rdev.p, sizeof(int32_t) * total, hipMemcpyDeviceToHost, s));
+    H2_HIP(hipStreamSynchronize(s));
+    {
+      int herr = 0;
+      H2_HIP(hipMemcpy(&herr, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost));
+      if (herr & 1) throw H2Error(H2_ERROR_SINGULAR, "zero pivot in a redundant block");
+      if (herr & 2) throw H2Error(H2_ERROR_NUMERIC, "non-finite singular value in augmentation");
+    }
+    {
+      hipEvent_t prev = ev_level0;
+      for (auto& m : marks) {
+        float ms = 0;
+        H2_HIP(hipEventElapsedTime(&ms, prev, m.second));
+        phase_ms[m.first] += ms;
+        prev = m.second;
+      }
+    }
+    ar.reset();
+    const auto tco = std::chrono::steady_clock::now();
+    // ---- close-out into the next level (or the dense top block) ----
+    // cb: skeleton blocks of near and fill entries (one source per destination
+    // sub-block); cb2, launched after cb: couplings added to far-pair
+    // sub-blocks and transfer blocks of the next bases.
+    CopyBatch<T> cb, cb2;
+    for (auto* I : act) {
+      const h2_matrix_s& H = *I->H;
+      h2_factor_s* F = I->F;
+      LevelPlan& P = F->plans[I->li];
+      for (int i = 0; i < P.nl; ++i) P.r[i] = rh[I->rbase + i];
+      // algorithmic flop model of the level
+      {
+        for (int i = 0; i < P.nl; ++i) {
+          const double n = P.n[i], k = P.k[i], r = P.r[i], kt = n - r;
+          double f = 0, W = kt, Wn = 0;
+          for (int64_t e = P.pptr[i]; e < P.pptr[i + 1]; ++e) {
+            const int j = P.pcol[e];
+            const double w = (P.color[j] < P.color[i]) ? P.n[j] - P.r[j] : P.n[j];
+            if (P.isF[e] && P.firstc[e] < P.color[i]) f += w;
+            if (!P.isF[e] && j != i) {
+              W += w;
+              Wn += w;
+            }
+          }
+          // augmentation: projection of the fill row, Householder QR of its
+          // transpose (f x n), SVD of the n x n factor (reported as 4 n^3)
+          const double qr = f >= n ? 2 * f * n * n - 2 * n * n * n / 3 : 2 * n * f * f - 2 * f * f * f / 3;
+          I->flops += (4 * n * k * f + qr + 4 * n * n * n) * (f > 0);
+          I->flops += 2 * n * kt * kt - 2 * kt * kt * kt / 3 + 4 * (n * n * kt - n * kt * kt + kt * kt * kt / 3);
+          I->flops += 4 * n * n * n + 4 * n * n * Wn + 4 * n * kt * f;
+          I->flops += 2 * r * r * r / 3 + 2 * r * r * W + 2 * r * W * W;
+        }
+      }
+      const int lev = P.lev;
+      const int plev = lev - 1;
+      // sizes of the next level
+      std::vector<int> n2(H.lp[plev + 1] - H.lp[plev]);
+      std::vector<int> offc(P.nl);
+      for (int t = 0; t < (int)n2.size(); ++t) {
+        const int tau = H.lp[plev] + t;
+        int o = 0;
+        for (int c = H.cp[tau]; c < H.cp[tau + 1]; ++c) {
+          offc[c - P.a] = o;
+          o += P.n[c - P.a] - P.r[c - P.a];
+        }
+        n2[t] = o;
+      }
+      const int pa = H.lp[plev];
+      auto pnear = [&](int t, int s2) {  // is (t, s2) (global) a near pair of level plev
+        const auto b = H.near_col.begin() + H.near_ptr[t], e = H.near_col.begin() + H.near_ptr[t + 1];
+        return std::binary_search(b, e, s2);
+      };
+      const bool is_top = (lev == I->tlev);
+      // lifted fill pairs of the next level
+      std::vector<std::pair<int, int>> lifted;
+      for (int j = 0; j < P.nl; ++j)
+        for (int64_t e = P.pptr[j]; e < P.pptr[j + 1]; ++e) {
+          if (!P.isF[e]) continue;
+          const int k = P.pcol[e];
+          const int pt = H.parent[P.a + j], ps = H.parent[P.a + k];
+          if (!pnear(pt, ps)) lifted.push_back({pt - pa, ps - pa});
+        }
+      std::sort(lifted.begin(), lifted.end());
+      lifted.erase(std::unique(lifted.begin(), lifted.end()), lifted.end());
+      // destination of a parent pair block: next level D / F, or the dense top
+      T* Dn = nullptr;
+      T* Fn = nullptr;
+      LevelPlan* PN = nullptr;
+      int64_t ldtop = 0;
+      std::vector<int64_t> toff;
+      if (is_top) {
+        F->top_level = plev;
+        F->top_nodes.clear();
+        F->top_off.assign(n2.size(), 0);
+        int64_t o = 0;
+        for (size_t t = 0; t < n2.size(); ++t) {
+          F->top_nodes.push_back(pa + (int)t);
+          F->top_off[t] = o;
+          o += n2[t];
+        }
+        F->top_n = n2;
+        F->n_top = o;
+        ldtop = o;
+        DevArray<T>& M = top_of<T>(F);
+        M.alloc(o * o, &F->tr);
+        launch_fill<T>(M.p, o * o, T(0), s);
+        Dn = M.p;
+      } else {
+        F->plans.emplace_back();
+        PN = &F->plans.back();
+        plan_level(H, plev, n2, lifted, *PN);
+      }
+      LevelPlan& Pc = F->plans[I->li];
+      LevelStore<T>* Sc = &store_of<T>(F, I->li);
+      DevArray<T> Vnext;
+      if (!is_top) {
+        // allocate next level buffers (F and V of the instance move on)
+        add_store<T>(F);
+        Sc = &store_of<T>(F, I->li);
+        LevelStore<T>& SN = store_of<T>(F, F->plans.size() - 1);
+        SN.D.alloc(PN->nD, &F->tr);
+        SN.Q.alloc(PN->nQ, &F->tr);
+        SN.piv.alloc(PN->nPiv, &F->tr);
+        launch_fill<T>(SN.D.p, SN.D.n, T(0), s);
+        Dn = SN.D.p;
+      }
+      DevArray<T> Fnext;
+      if (!is_top) {
+        Fnext.alloc(PN->nF, &F->tr);
+        launch_fill<T>(Fnext.p, Fnext.n, T(0), s);
+        Fn = Fnext.p;
+        Vnext.alloc(PN->nV, &F->tr);
+      }
+      auto dest = [&](int t, int s2, bool near_pair, int64_t& ld) -> T* {
+        // block (t, s2) of level plev (local ids)
+        if (is_top) {
+          ld = ldtop;
+          return Dn + F->top_off[t] + F->top_off[s2] * ldtop;
+        }
+        const int64_t e = PN->find(t, s2);
+        ld = PN->n[t];
+        if (e < 0) throw H2Error(H2_ERROR_FORMAT, "close-out destination missing from the pattern");
+        (void)near_pair;
+        return (PN->isF[e] ? Fn : Dn) + PN->poff[e];
+      };
+      for (int j = 0; j < Pc.nl; ++j) {
+        const int gj = Pc.a + j;
+        const int pt = H.parent[gj] - pa;
+        const int rj = Pc.r[j], ktj = Pc.n[j] - rj;
+        for (int64_t e = Pc.pptr[j]; e < Pc.pptr[j + 1]; ++e) {
+          const int k = Pc.pcol[e];
+          const int ps = H.parent[Pc.a + k] - pa;
+          const int rk = Pc.r[k], ktk = Pc.n[k] - rk;
+          const T* src = (Pc.isF[e] ? I->Fbuf.p : Sc->D.p) + Pc.poff[e] + rj + (int64_t)rk * Pc.n[j];
+          int64_t ld = 0;
+          T* d = dest(pt, ps, true, ld);
+          d += offc[j] + (int64_t)offc[k] * ld;
+          // near: copy; fill: accumulate (a far pair also receives its coupling)
+          cb.add(src, Pc.n[j], d, ld, ktj, ktk, Pc.isF[e] ? 1 : 0);
+        }
+        // couplings of far pairs into the skeleton blocks: S~ = [S 0; 0 0]
+        for (int64_t e = H.far_ptr[gj]; e < H.far_ptr[gj + 1]; ++e) {
+          const int k = H.far_col[e] - Pc.a;
+          const int ps = H.parent[Pc.a + k] - pa;
+          int64_t ld = 0;
+          T* d = dest(pt, ps, true, ld);
+          d += offc[j] + (int64_t)offc[k] * ld;
+          cb2.add(I->data + H.offS[e], H.rank[gj], d, ld, H.rank[gj], H.rank[Pc.a + k], 1);
+        }
+        // parent basis: rows of child j are [E_j; 0]
+        if (!is_top) {
+          const int tau = H.parent[gj];
+          const int kp = H.rank[tau];
+          const int t = tau - pa;
+          cb2.add(I->data + H.offE[gj], H.rank[gj], Vnext.p + PN->offV[t] + offc[j], PN->n[t],
+                  H.rank[gj], kp, 0);
+        }
+      }
+      // hand over buffers: current F and V retire after the copies complete
+      // (keep them alive until the sync at the end of the next height)
+      F->stats.levels = (int)F->plans.size() - (is_top ? 0 : 1);
+      I->F->stats.max_colors = std::max(I->F->stats.max_colors, Pc.ncolors);
+      if (!is_top) {
+        // zero the V buffer before the copies of E
+        // (done through a fill ahead of the copy batch)
+        launch_fill<T>(Vnext.p, Vnext.n, T(0), s);
+        std::swap(I->Vbuf, Vnext);
+        std::swap(I->Fbuf, Fnext);
+        I->li = F->plans.size() - 1;
+        I->lev = plev;
+        // Vnext/Fnext now hold the previous level's buffers: free after the copies
+        cb.launch(ar, s);
+        cb2.launch(ar, s);
+        cb = CopyBatch<T>();
+        cb2 = CopyBatch<T>();
+        H2_HIP(hipStreamSynchronize(s));
+        ar.reset();
+      } else {
+        cb.launch(ar, s);
+        cb2.launch(ar, s);
+        cb = CopyBatch<T>();
+        cb2 = CopyBatch<T>();
+        H2_HIP(hipStreamSynchronize(s));
+        ar.reset();
+        I->done = true;
+        I->Fbuf.release();
+        I->Vbuf.release();
+      }
+    }
+    // the V fills must precede the E copies: the fills above were enqueued
+    // before each instance's copy batch launch, so stream order holds.
+    plan_ms += ms_since(tco);
+    hipEvent_t eclose = new_event();
+    H2_HIP(hipEventRecord(eclose, s));
+    H2_HIP(hipEventSynchronize(eclose));
+    {
+      float ms = 0;
+      H2_HIP(hipEventElapsedTime(&ms, marks.empty() ? ev_level0 : marks.back().second, eclose));
+      phase_ms[4] += ms;
+    }
+  }
+
+  // ---- dense top factorization ----
+  {
+    CopyBatch<T> cb;
+    for (auto& I : insts) {
+      h2_factor_s* F = I.F;
+      const h2_matrix_s& H = *I.H;
+      if (I.tlev < 0) {
+        // whole leaf level is the top block: assemble A from the leaf blocks
+        const int a = H.lp[H.L], nl = H.lp[H.L + 1] - a;
+        F->top_level = H.L;
+        F->top_nodes.clear();
+        F->top_off.assign(nl, 0);
+        F->top_n.assign(nl, 0);
+        int64_t o = 0;
+        for (int t = 0; t < nl; ++t) {
+          F->top_nodes.push_back(a + t);
+          F->top_off[t] = o;
+          F->top_n[t] = H.size(a + t);
+          o += F->top_n[t];
+        }
+        F->n_top = o;
+        DevArray<T>& M = top_of<T>(F);
+        M.alloc(o * o, &F->tr);
+        launch_fill<T>(M.p, o * o, T(0), s);
+        for (int t = 0; t < nl; ++t)
+          for (int64_t e = H.near_ptr[a + t]; e < H.near_ptr[a + t + 1]; ++e) {
+            const int u = H.near_col[e] - a;
+            cb.add(I.data + H.offD[e], F->top_n[t], M.p + F->top_off[t] + F->top_off[u] * o, o,
+                   F->top_n[t], F->top_n[u], 0);
+          }
+      }
+    }
+    cb.launch(ar, s);
+    hipEvent_t et0 = new_event();
+    H2_HIP(hipEventRecord(et0, s));
+    for (auto& I : insts) {
+      h2_factor_s* F = I.F;
+      const int64_t n = F->n_top;
+      DevArray<T>& M = top_of<T>(F);
+      F->top_piv.alloc(std::max<int64_t>(n, 1), &F->tr);
+      const int nb = 64;
+      for (int64_t j0 = 0; j0 < n; j0 += nb) {
+        const int w = (int)std::min<int64_t>(nb, n - j0);
+        launch_panel_lu<T>(M.p, n, n, j0, w, F->top_piv.p, ctx->d_err, s);
+        launch_laswp<T>(M.p, n, n, j0, w, F->top_piv.p, j0, j0 + w, s);
+        const int64_t rest = n - j0 - w;
+        if (rest > 0) {
+          // U12 = L11^{-1} A12
+          launch_trsm_block<T>(M.p + j0 + j0 * n, n, M.p + j0 + (j0 + w) * n, n, w, rest, 1, s);
+          // A22 -= L21 U12
+          std::vector<GOut<T>> outs(1);
+          std::vector<GCon<T>> cons(1);
+          GOut<T>& o = outs[0];
+          o = GOut<T>{};
+          o.C = M.p + (j0 + w) + (j0 + w) * n;
+          o.ldc = n;
+          o.m = (int)rest;
+          o.n = (int)rest;
+          o.m0d = o.m1d = o.n0d = -1;
+          o.cbeg = 0;
+          o.cend = 1;
+          o.tm = (int)((rest + 63) / 64);
+          o.tn = (int)((rest + 63) / 64);
+          o.tile0 = 0;
+          o.alpha = T(-1);
+          o.beta = T(1);
+          GCon<T>& g = cons[0];
+          g = GCon<T>{};
+          g.A = M.p + (j0 + w) + j0 * n;
+          g.lda = n;
+          g.B = M.p + j0 + (j0 + w) * n;
+          g.ldb = n;
+          g.k = w;
+          g.k0d = g.k1d = -1;
+          launch_gemm<T>(ar.put(outs), 1, ar.put(cons), nullptr, (int64_t)o.tm * o.tn, 0, s);
+        }
+      }
+      I.flops += 2.0 * (double)n * n * n / 3.0;
+    }
+    hipEvent_t et1 = new_event();
+    H2_HIP(hipEventRecord(et1, s));
+    H2_HIP(hipEventSynchronize(et1));
+    float ms = 0;
+    H2_HIP(hipEventElapsedTime(&ms, et0, et1));
+    phase_ms[5] += ms;
+    int herr = 0;
+    H2_HIP(hipMemcpy(&herr, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost));
+    if (herr & 1) throw H2Error(H2_ERROR_SINGULAR, "zero pivot in the dense top block");
+    ar.reset();
+  }
+  phase_ms[6] = plan_ms;
+  phase_ms[7] = ms_since(t_start);
+  for (auto e : evpool) (void)hipEventDestroy(e);
+  for (auto& I : insts) {
+    h2_factor_s* F = I.F;
+    for (int p = 0; p < 8; ++p) F->stats.time_ms[p] = phase_ms[p];
+    F->stats.n_top = F->n_top;
+    F->stats.factor_flops = I.flops;
+    F->stats.factor_bytes = F->tr.cur;
+    F->stats.peak_bytes = F->tr.peak;
+    F->stats.levels = (int)F->plans.size();
+  }
+}
+
+std::vector<h2_factor_s*> factor(h2_context_s* ctx, const std::vector<h2_matrix_s*>& Hs,
+                                 double tol, h2_prec prec) {
+  std::vector<h2_factor_s*> out;
+  std::vector<std::unique_ptr<h2_factor_s>> own;
+  for (auto* H : Hs) {
+    own.emplace_back(new h2_factor_s());
+    h2_factor_s* F = own.back().get();
+    F->ctx = ctx;
+    F->prec = prec;
+    F->N = H->N;
+    F->L = H->L;
+    F->top = H->top;
+    F->ib = H->ib;
+    F->ie = H->ie;
+    F->lp = H->lp;
+    F->parent = H->parent;
+    F->cp = H->cp;
+    F->perm_d.alloc(H->N, &F->tr);
+    H2_HIP(hipMemcpyAsync(F->perm_d.p, H->perm_d.p, sizeof(int64_t) * H->N,
+                          hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  if (prec == H2_PREC_FP64) {
+    std::vector<Inst<double>> insts(Hs.size());
+    for (size_t i = 0; i < Hs.size(); ++i) {
+      insts[i].H = Hs[i];
+      insts[i].F = own[i].get();
+      insts[i].data = Hs[i]->data.p;
+    }
+    run_factor<double>(ctx, insts, tol);
+  } else {
+    std::vector<Inst<float>> insts(Hs.size());
+    for (size_t i = 0; i < Hs.size(); ++i) {
+      insts[i].H = Hs[i];
+      insts[i].F = own[i].get();
+      insts[i].data_conv.alloc(Hs[i]->ndata, &own[i]->tr);
+      launch_convert<float>(insts[i].data_conv.p, Hs[i]->data.p, Hs[i]->ndata, ctx->stream);
+      insts[i].data = insts[i].data_conv.p;
+    }
+    run_factor<float>(ctx, insts, tol);
+  }
+  H2_HIP(hipStreamSynchronize(ctx->stream));
+  for (auto& p : own) out.push_back(p.release());
+  return out;
+}
+
+}  // namespace h2drv

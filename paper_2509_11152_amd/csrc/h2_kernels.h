@@ -1,0 +1,164 @@
+// Device task descriptors and kernel launchers of the H^2 factor/solve library.
+//
+// Every batched operation is a list of small tasks in device memory.  Sizes
+// that depend on ranks decided on the device (the redundant count r_i of a
+// cluster) are not copied to the host inside a tree level: a descriptor names
+// the cluster whose r_i moves a window boundary ("dyn" index into the level's
+// r array, -1 = static boundary), and the kernels read it.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace h2k {
+
+// C[rows m0:m1, cols n0:n] = beta * C + alpha * sum_t opA(A_t)[rows, k0:k1] * B_t[k0:k1, cols]
+// Column-major everything.  A_t rows and B_t columns use the same indices as
+// C's rows and columns; beta = 0 does not read C.
+// A boundary is dyn[d] when d >= 0, else the static value.
+template <class T> struct GOut {
+  T* C;
+  int64_t ldc;
+  int32_t m, n;         // static row / column end (m is replaced by dyn[m1d] when m1d >= 0)
+  int32_t m0d, m0s;     // row start
+  int32_t m1d, n0d;     // row end (dynamic), column start (dynamic)
+  int32_t n0s, pad0;    // column start (static)
+  int32_t cbeg, cend;   // contributor range
+  int32_t tm, tn;       // tile counts over the static extent
+  int64_t tile0;        // first tile of this output in the launch
+  T alpha, beta;
+};
+
+template <class T> struct GCon {
+  const T* A;
+  const T* B;
+  int64_t lda, ldb;
+  int32_t k;            // static inner end
+  int32_t k0d, k0s;     // inner start
+  int32_t k1d;          // inner end (dynamic)
+  int32_t transA, pad0;
+};
+
+// In-place X <- op(Q) X (side 0, X has n rows, columns c0..ext-1 are active)
+// or X <- X op(Q) (side 1, X has n columns, rows c0..ext-1 are active).
+// op(Q) = Q^T when trans.  One workgroup per strip of 16.
+template <class T> struct STask {
+  T* X;
+  const T* Q;
+  int64_t ldx;
+  int32_t n;            // order of Q
+  int32_t ext;          // static extent of the strip direction
+  int32_t d0, s0;       // window start: dyn[d0] or s0
+  int32_t side, trans;
+  int64_t strip0;       // first strip index in the launch
+};
+
+// One column block of the fill row of a cluster: columns c0..ncols-1 of F
+// (n rows, leading dimension ld), c0 = dyn[d0] or 0.
+template <class T> struct FillRef {
+  const T* F;
+  int64_t ld;
+  int32_t ncols, d0;
+};
+
+// Basis augmentation + complement of one cluster (Algorithm 2, first loop).
+template <class T> struct AugTask {
+  const T* V;           // n x k input basis
+  T* Q;                 // n x n output Q~ = [V~perp, V~]
+  T* work;              // scratch
+  int32_t n, k;
+  int32_t fbeg, fend;   // FillRef range
+  int32_t ri;           // index into the r array (output)
+  int32_t pad0;
+};
+
+// LU with partial pivoting of the leading r x r block of A (r = dyn[ri]).
+template <class T> struct LUTask {
+  T* A;
+  int32_t* piv;
+  int64_t lda;
+  int32_t ri, pad0;
+};
+
+// B[0:r, c0:ncols] <- A_RR^{-1} B[0:r, c0:ncols] with the LU of the leading
+// r x r block of A.
+template <class T> struct TrsmTask {
+  const T* LU;
+  const int32_t* piv;
+  T* B;
+  int64_t ldlu, ldb;
+  int32_t ncols;
+  int32_t ri, rs;       // order r: dyn[ri] or rs
+  int32_t c0d, c0s;     // first column: dyn[c0d] or c0s
+  int32_t pad0;
+};
+
+// dst[0:rows, 0:cols] (=|+=) src[0:rows, 0:cols]; element types may differ.
+template <class T, class S> struct CTask {
+  const S* src;
+  T* dst;
+  int64_t lds, ldd;
+  int32_t rows, cols;
+  int32_t add, pad0;
+  int64_t tile0;
+};
+
+constexpr int kStrip = 16;
+constexpr int kCopyTile = 4096;
+constexpr int kAugChunk = 64;
+
+// scratch elements needed by one augmentation task of order n
+inline int64_t aug_work_elems(int n) {
+  return (int64_t)(n + kAugChunk) * n + 3 * (int64_t)n * n + 4 * (int64_t)n + 64;
+}
+
+// ---- launchers (stream-ordered; descriptor arrays are device pointers) ----
+template <class T>
+void launch_gemm(const GOut<T>* outs, int nouts, const GCon<T>* cons, const int32_t* dyn,
+                 int64_t ntiles, int shape, hipStream_t s);
+template <class T>
+void launch_strip(const STask<T>* tasks, int ntasks, const int32_t* dyn, int64_t nstrips,
+                  int maxn, hipStream_t s);
+template <class T>
+void launch_augment(const AugTask<T>* tasks, int ntasks, const FillRef<T>* refs,
+                    int32_t* r, T eps_fill, int* err, hipStream_t s);
+template <class T>
+void launch_lu(const LUTask<T>* tasks, int ntasks, const int32_t* dyn, int* err, hipStream_t s);
+template <class T>
+void launch_trsm(const TrsmTask<T>* tasks, int ntasks, const int32_t* dyn, hipStream_t s);
+template <class T, class S>
+void launch_copy(const CTask<T, S>* tasks, int ntasks, int64_t ntiles, hipStream_t s);
+template <class T>
+void launch_fill(T* p, int64_t n, T v, hipStream_t s);
+template <class T, class S>
+void launch_gather_rows(T* dst, int64_t ldd, const S* src, int64_t lds, const int64_t* perm,
+                        int64_t n, int nrhs, hipStream_t s);
+template <class T, class S>
+void launch_scatter_rows(T* dst, int64_t ldd, const S* src, int64_t lds, const int64_t* perm,
+                         int64_t n, int nrhs, hipStream_t s);
+template <class T>
+void launch_panel_lu(T* A, int64_t lda, int64_t n, int64_t j0, int nb, int32_t* piv, int* err,
+                     hipStream_t s);
+template <class T>
+void launch_laswp(T* A, int64_t lda, int64_t ncols_total, int64_t j0, int nb,
+                  const int32_t* piv, int64_t skip0, int64_t skip1, hipStream_t s);
+template <class T>
+void launch_trsm_block(const T* A, int64_t lda, T* B, int64_t ldb, int nb, int64_t ncols,
+                       int lower_unit, hipStream_t s);
+template <class T>
+void launch_convert(T* dst, const double* src, int64_t n, hipStream_t s);
+void launch_colnorms(const double* X, int64_t ldx, int64_t n, int nrhs, double* out,
+                     hipStream_t s);
+void launch_dots(const double* V, int64_t ldv, int64_t vstride, int nvec, const double* W,
+                 int64_t ldw, int64_t n, int nrhs, double* out, hipStream_t s);
+void launch_update(double* W, int64_t ldw, const double* V, int64_t ldv, int64_t vstride,
+                   int nvec, const double* coef, double sign, int64_t n, int nrhs,
+                   hipStream_t s);
+void launch_scale_cols(double* dst, int64_t ldd, const double* src, int64_t lds,
+                       const double* norms, int64_t n, int nrhs, int invert, hipStream_t s);
+void launch_axpy_cols(double* Y, int64_t ldy, const double* X, int64_t ldx, const double* a,
+                      int64_t n, int nrhs, hipStream_t s);
+void launch_sub(double* R, int64_t ldr, const double* B, int64_t ldb, const double* AX,
+                int64_t ldax, int64_t n, int nrhs, hipStream_t s);
+void launch_check_finite(const double* X, int64_t n, int* flag, hipStream_t s);
+
+}  // namespace h2k

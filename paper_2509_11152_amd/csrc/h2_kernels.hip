@@ -1,0 +1,1074 @@
+// HIP kernels of the H^2 strong recursive skeletonization solver (gfx950).
+//
+// Dense contractions (projections by Q~, Schur complement / fill-in updates,
+// near-field and coupling products of the H^2 matvec, the trailing update of
+// the dense top LU) run on the FP64 / FP32 16x16x4 MFMA instructions.  The
+// small per-cluster factorizations (Householder QR of the fill row, one-sided
+// Jacobi SVD, complement, partial-pivoting LU) run one workgroup per cluster.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cstdint>
+
+#include "h2_kernels.h"
+
+namespace h2k {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <class T> struct Acc;
+template <> struct Acc<double> { typedef d4 type; };
+template <> struct Acc<float> { typedef f4 type; };
+
+__device__ inline d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma16(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Row of accumulator element i held by a lane with kq = lane / 16 (column lane % 16).
+// Measured on gfx950: the FP64 16x16x4 instruction interleaves rows
+// (kq + 4 i), the FP32 one keeps them contiguous (4 kq + i).
+template <class T> __device__ inline int acc_row(int kq, int i);
+template <> __device__ inline int acc_row<double>(int kq, int i) { return kq + 4 * i; }
+template <> __device__ inline int acc_row<float>(int kq, int i) { return 4 * kq + i; }
+
+template <class T> __device__ inline T eps_of();
+template <> __device__ inline double eps_of<double>() { return DBL_EPSILON; }
+template <> __device__ inline float eps_of<float>() { return FLT_EPSILON; }
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline float wave_sum(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// block-wide sum over 256 threads (4 waves); `red` holds >= 4 values
+template <class T> __device__ inline T block_sum(T v, T* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  T s = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Grouped GEMM with owner-computes accumulation over contributor lists.
+// Workgroup = 4 waves arranged WM x WN; each wave owns FM x FN fragments of
+// 16 x 16.  Operands are read straight from global memory (L1/L2 cached) in
+// the MFMA lane layout: lane l supplies A[row l%16][k l/16] and
+// B[k l/16][col l%16]; accumulator element i is C[acc_row(l/16, i)][l%16].
+// ---------------------------------------------------------------------------
+template <class T, int WM, int WN, int FM, int FN>
+__global__ __launch_bounds__(256) void k_gemm(const GOut<T>* __restrict__ outs, int nouts,
+                                              const GCon<T>* __restrict__ cons,
+                                              const int32_t* __restrict__ dyn) {
+  constexpr int TM = WM * FM * 16, TN = WN * FN * 16;
+  const int64_t tile = blockIdx.x;
+  int lo = 0, hi = nouts - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (outs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+  }
+  const GOut<T>& o = outs[lo];
+  const int64_t t = tile - o.tile0;
+  const int ti = (int)(t % o.tm), tj = (int)(t / o.tm);
+  const int m0 = o.m0d >= 0 ? dyn[o.m0d] : o.m0s;
+  const int m1 = o.m1d >= 0 ? dyn[o.m1d] : o.m;
+  const int n0 = o.n0d >= 0 ? dyn[o.n0d] : o.n0s;
+  const int n1 = o.n;
+  const int r0 = m0 + ti * TM, c0 = n0 + tj * TN;
+  if (r0 >= m1 || c0 >= n1) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = r0 + (wave % WM) * FM * 16;
+  const int wc = c0 + (wave / WM) * FN * 16;
+  typename Acc<T>::type acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = (typename Acc<T>::type){0, 0, 0, 0};
+  const int l16 = lane & 15, kq = lane >> 4;
+  for (int ci = o.cbeg; ci < o.cend; ++ci) {
+    const GCon<T> g = cons[ci];
+    const int k0 = g.k0d >= 0 ? dyn[g.k0d] : g.k0s;
+    const int k1 = g.k1d >= 0 ? dyn[g.k1d] : g.k;
+    for (int kk = k0; kk < k1; kk += 4) {
+      const int kx = kk + kq;
+      const bool kok = kx < k1;
+      T av[FM], bv[FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) {
+        const int row = wr + a * 16 + l16;
+        T v = 0;
+        if (kok && row < m1)
+          v = g.transA ? g.A[kx + (int64_t)row * g.lda] : g.A[row + (int64_t)kx * g.lda];
+        av[a] = v;
+      }
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        const int col = wc + b * 16 + l16;
+        T v = 0;
+        if (kok && col < n1) v = g.B[kx + (int64_t)col * g.ldb];
+        bv[b] = v;
+      }
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
+    }
+  }
+  const T alpha = o.alpha, beta = o.beta;
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+      const int col = wc + b * 16 + l16;
+      if (col >= n1) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = wr + a * 16 + acc_row<T>(kq, i);
+        if (row < m1) {
+          T* p = o.C + row + (int64_t)col * o.ldc;
+          const T v = alpha * acc[a][b][i];
+          *p = beta == T(0) ? v : beta * *p + v;
+        }
+      }
+    }
+}
+
+template <class T>
+void launch_gemm(const GOut<T>* outs, int nouts, const GCon<T>* cons, const int32_t* dyn,
+                 int64_t ntiles, int shape, hipStream_t s) {
+  if (ntiles <= 0 || nouts <= 0) return;
+  if (shape == 0)
+    hipLaunchKernelGGL((k_gemm<T, 2, 2, 2, 2>), dim3((unsigned)ntiles), dim3(256), 0, s, outs,
+                       nouts, cons, dyn);
+  else
+    hipLaunchKernelGGL((k_gemm<T, 4, 1, 1, 1>), dim3((unsigned)ntiles), dim3(256), 0, s, outs,
+                       nouts, cons, dyn);
+}
+
+// ---------------------------------------------------------------------------
+// In-place strip products with a cluster's orthogonal factor Q~.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_strip(const STask<T>* __restrict__ tasks, int ntasks,
+                                               const int32_t* __restrict__ dyn) {
+  extern __shared__ char smem_raw[];
+  T* xs = reinterpret_cast<T*>(smem_raw);
+  const int64_t sid = blockIdx.x;
+  int lo = 0, hi = ntasks - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (tasks[mid].strip0 <= sid) lo = mid; else hi = mid - 1;
+  }
+  const STask<T>& tk = tasks[lo];
+  const int s = (int)(sid - tk.strip0);
+  const int c0 = (tk.d0 >= 0 ? dyn[tk.d0] : tk.s0) + s * kStrip;
+  if (c0 >= tk.ext) return;
+  const int w = min(kStrip, tk.ext - c0);
+  const int n = tk.n;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, kq = lane >> 4;
+  if (tk.side == 0) {
+    // X[:, c0:c0+w] (n x w) -> LDS, layout xs[k + c*n]
+    for (int e = threadIdx.x; e < n * kStrip; e += blockDim.x) {
+      const int r = e % n, c = e / n;
+      xs[e] = c < w ? tk.X[r + (int64_t)(c0 + c) * tk.ldx] : T(0);
+    }
+    __syncthreads();
+    for (int rt = wave; rt * 16 < n; rt += 4) {
+      typename Acc<T>::type acc = {0, 0, 0, 0};
+      const int row = rt * 16 + l16;
+      for (int kk = 0; kk < n; kk += 4) {
+        const int kx = kk + kq;
+        T a = 0, b = 0;
+        if (kx < n) {
+          if (row < n) a = tk.trans ? tk.Q[kx + (int64_t)row * n] : tk.Q[row + (int64_t)kx * n];
+          b = xs[kx + l16 * n];
+        }
+        acc = mfma16(a, b, acc);
+      }
+      const int col = l16;
+      if (col < w) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int rr = rt * 16 + acc_row<T>(kq, i);
+          if (rr < n) tk.X[rr + (int64_t)(c0 + col) * tk.ldx] = acc[i];
+        }
+      }
+    }
+  } else {
+    // X[c0:c0+w, :] (w x n) -> LDS, layout xs[r + k*16]
+    for (int e = threadIdx.x; e < n * kStrip; e += blockDim.x) {
+      const int r = e % kStrip, k = e / kStrip;
+      xs[e] = r < w ? tk.X[(c0 + r) + (int64_t)k * tk.ldx] : T(0);
+    }
+    __syncthreads();
+    for (int ct = wave; ct * 16 < n; ct += 4) {
+      typename Acc<T>::type acc = {0, 0, 0, 0};
+      const int col = ct * 16 + l16;
+      for (int kk = 0; kk < n; kk += 4) {
+        const int kx = kk + kq;
+        T a = 0, b = 0;
+        if (kx < n) {
+          a = xs[l16 + kx * kStrip];
+          if (col < n) b = tk.trans ? tk.Q[col + (int64_t)kx * n] : tk.Q[kx + (int64_t)col * n];
+        }
+        acc = mfma16(a, b, acc);
+      }
+      if (col < n) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int rr = acc_row<T>(kq, i);
+          if (rr < w) tk.X[(c0 + rr) + (int64_t)col * tk.ldx] = acc[i];
+        }
+      }
+    }
+  }
+}
+
+template <class T>
+void launch_strip(const STask<T>* tasks, int ntasks, const int32_t* dyn, int64_t nstrips,
+                  int maxn, hipStream_t s) {
+  if (nstrips <= 0 || ntasks <= 0) return;
+  const size_t lds = (size_t)maxn * kStrip * sizeof(T);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_strip<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_strip<T>, dim3((unsigned)nstrips), dim3(256), lds, s, tasks, ntasks, dyn);
+}
+
+// ---------------------------------------------------------------------------
+// Basis augmentation and complement, one workgroup per cluster.
+//  1. R = R-factor of Y^T, Y = [F_ij] the fill row, by Householder on stacked
+//     [R; next chunk of Y^T rows] (triangle-on-top structured reflectors);
+//  2. M = R (I - V V^T): the projected fill row is (I - V V^T) Y = M^T Q_Y^T;
+//  3. one-sided Jacobi (Hestenes) on the columns of M with the rotations
+//     accumulated in W: the column norms are the singular values of
+//     (I - V V^T) Y and the columns of W its left singular vectors;
+//  4. Vbar = vectors with sigma > eps_fill (largest first), re-orthogonalised
+//     against V (twice) and among themselves (twice);
+//  5. Householder QR of V~ = [V, Vbar]; the complement is H_0...H_{k~-1} [0; I];
+//     Q~ = [V~perp, V~], r = n - k~.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ void structured_qr(T* R, T* C, int ldw, int n, int m, T* red) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ T sh_tau, sh_beta;
+  for (int j = 0; j < n; ++j) {
+    // norm of C[0:m, j]
+    T v = (lane < m && wave == 0) ? C[lane + (int64_t)j * ldw] : T(0);
+    if (wave == 0) {
+      T s2 = wave_sum(v * v);
+      if (lane == 0) {
+        const T alpha = R[j + (int64_t)j * ldw];
+        if (s2 == T(0)) {
+          sh_tau = 0;
+          sh_beta = alpha;
+        } else {
+          const T nrm = sqrt(alpha * alpha + s2);
+          const T beta = alpha >= T(0) ? -nrm : nrm;
+          sh_tau = (beta - alpha) / beta;
+          sh_beta = beta;
+        }
+      }
+    }
+    __syncthreads();
+    const T tau = sh_tau;
+    if (tau != T(0)) {
+      const T alpha = R[j + (int64_t)j * ldw];
+      const T scale = T(1) / (alpha - sh_beta);
+      __syncthreads();
+      for (int t = threadIdx.x; t < m; t += blockDim.x) C[t + (int64_t)j * ldw] *= scale;
+      if (threadIdx.x == 0) R[j + (int64_t)j * ldw] = sh_beta;
+      __syncthreads();
+      for (int c = j + 1 + wave; c < n; c += 4) {
+        T* Cc = C + (int64_t)c * ldw;
+        const T* vj = C + (int64_t)j * ldw;
+        T part = 0;
+        for (int t = lane; t < m; t += 64) part += vj[t] * Cc[t];
+        const T w = R[j + (int64_t)c * ldw] + wave_sum(part);
+        const T tw = tau * w;
+        for (int t = lane; t < m; t += 64) Cc[t] -= tw * vj[t];
+        if (lane == 0) R[j + (int64_t)c * ldw] -= tw;
+      }
+    }
+    __syncthreads();
+  }
+  (void)red;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ tasks,
+                                                 const FillRef<T>* __restrict__ refs,
+                                                 int32_t* __restrict__ rout, T eps_fill,
+                                                 int* err) {
+  const AugTask<T> tk = tasks[blockIdx.x];
+  const int n = tk.n, k = tk.k;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  __shared__ T red[8];
+  __shared__ int sh_flag;
+  if (n == 0) {
+    if (tid == 0) rout[tk.ri] = 0;
+    return;
+  }
+  const int ldw = n + kAugChunk;
+  T* R = tk.work;                               // (n + chunk) x n, ld ldw; rows 0..n-1 = R
+  T* C = R + n;                                 // chunk rows
+  T* G = tk.work + (int64_t)ldw * n;            // n x n
+  T* Hm = G + (int64_t)n * n;                   // n x n (Householder of V~ / V^T R^T scratch)
+  T* sig = Hm + (int64_t)n * n;                 // n
+  T* tau = sig + n;                             // n
+  int* rank = reinterpret_cast<int*>(tau + n);  // n ints (fits in n T's)
+  T* Q = tk.Q;
+
+  // ---- 1. R of the fill row ----
+  for (int e = tid; e < n * n; e += nthr) R[(e % n) + (int64_t)(e / n) * ldw] = 0;
+  __syncthreads();
+  int fill = 0;
+  for (int f = tk.fbeg; f < tk.fend; ++f) {
+    const FillRef<T> fr = refs[f];
+    int c = fr.d0 >= 0 ? rout[fr.d0] : 0;
+    // rout doubles as the level's r array: processed neighbours were written
+    // by earlier launches of this level.
+    while (c < fr.ncols) {
+      const int take = min(kAugChunk - fill, fr.ncols - c);
+      for (int e = tid; e < take * n; e += nthr) {
+        const int tt = e / n, col = e % n;
+        C[(fill + tt) + (int64_t)col * ldw] = fr.F[col + (int64_t)(c + tt) * fr.ld];
+      }
+      fill += take;
+      c += take;
+      __syncthreads();
+      if (fill == kAugChunk) {
+        structured_qr(R, C, ldw, n, fill, red);
+        fill = 0;
+      }
+    }
+  }
+  if (fill > 0) structured_qr(R, C, ldw, n, fill, red);
+  __syncthreads();
+
+  // ---- 2. M = R (I - V V^T) = G^T, G = (I - V V^T) R^T ----
+  // Hm[c + a*n] = (R V)[c, a]   (n x k)
+  for (int e = tid; e < n * k; e += nthr) {
+    const int c = e % n, a = e / n;
+    T s = 0;
+    for (int b = c; b < n; ++b) s += R[c + (int64_t)b * ldw] * tk.V[b + (int64_t)a * n];
+    Hm[e] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < n * n; e += nthr) {
+    const int c = e % n, b = e / n;
+    T s = (b >= c) ? R[c + (int64_t)b * ldw] : T(0);
+    for (int a = 0; a < k; ++a) s -= Hm[c + (int64_t)a * n] * tk.V[b + (int64_t)a * n];
+    G[e] = s;  // M[c, b]
+  }
+  __syncthreads();
+  // W = I accumulates the rotations: M W = U S  =>  G = M^T = W S U^T, so the
+  // columns of W are the left singular vectors of G, i.e. of (I - V V^T) Y,
+  // orthonormal to working precision whatever the size of sigma.
+  T* W = Hm;
+  for (int e = tid; e < n * n; e += nthr) W[e] = (e % n == e / n) ? T(1) : T(0);
+  __syncthreads();
+
+  // ---- 3. one-sided Jacobi on the columns of M ----
+  const int ne = (n + 1) & ~1;
+  const T tolj = eps_of<T>() * T(n);
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) sh_flag = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < ne - 1; ++rnd) {
+      for (int p = wave; p < ne / 2; p += 4) {
+        int a, b;
+        if (p == 0) {
+          a = rnd;
+          b = ne - 1;
+        } else {
+          a = (rnd + p) % (ne - 1);
+          b = (rnd - p + ne - 1) % (ne - 1);
+        }
+        if (a >= n || b >= n) continue;
+        T* ga = G + (int64_t)a * n;
+        T* gb = G + (int64_t)b * n;
+        T al = 0, be = 0, ga_b = 0;
+        for (int t = lane; t < n; t += 64) {
+          const T x = ga[t], y = gb[t];
+          al += x * x;
+          be += y * y;
+          ga_b += x * y;
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga_b = wave_sum(ga_b);
+        if (ga_b != T(0) && fabs(ga_b) > tolj * sqrt(al * be)) {
+          const T zeta = (be - al) / (T(2) * ga_b);
+          const T tt = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
+          const T cs = T(1) / sqrt(T(1) + tt * tt);
+          const T sn = cs * tt;
+          T* wa = W + (int64_t)a * n;
+          T* wb = W + (int64_t)b * n;
+          for (int t = lane; t < n; t += 64) {
+            const T x = ga[t], y = gb[t];
+            ga[t] = cs * x - sn * y;
+            gb[t] = sn * x + cs * y;
+            const T u = wa[t], v = wb[t];
+            wa[t] = cs * u - sn * v;
+            wb[t] = sn * u + cs * v;
+          }
+          if (lane == 0) sh_flag = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int fl = sh_flag;
+    __syncthreads();
+    if (!fl) break;
+  }
+  for (int c = wave; c < n; c += 4) {
+    T s = 0;
+    for (int t = lane; t < n; t += 64) s += G[t + (int64_t)c * n] * G[t + (int64_t)c * n];
+    s = wave_sum(s);
+    if (lane == 0) sig[c] = sqrt(s);
+  }
+  __syncthreads();
+
+  // ---- 4. select, order and orthonormalise Vbar ----
+  for (int c = tid; c < n; c += nthr) {
+    int pos = 0;
+    const T sc = sig[c];
+    for (int i = 0; i < n; ++i) {
+      const T si = sig[i];
+      pos += (si > sc) || (si == sc && i < c);
+    }
+    rank[c] = pos;
+  }
+  if (tid == 0) {
+    int cnt = 0;
+    for (int i = 0; i < n; ++i) cnt += sig[i] > eps_fill;
+    if (cnt > n - k) cnt = n - k;
+    sh_flag = cnt;
+  }
+  __syncthreads();
+  const int rbar = sh_flag;
+  const int kt = k + rbar;
+  const int r = n - kt;
+  T* Vt = Q + (int64_t)r * n;  // V~ occupies the last kt columns of Q~
+  for (int e = tid; e < n * k; e += nthr) Vt[e] = tk.V[e];
+  for (int e = tid; e < n * n; e += nthr) {
+    const int row = e % n, c = e / n;
+    const int pos = rank[c];
+    if (pos < rbar) Vt[row + (int64_t)(k + pos) * n] = W[e];
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    // Vbar -= V (V^T Vbar)
+    for (int e = tid; e < k * rbar; e += nthr) {
+      const int a = e % k, b = e / k;
+      T s = 0;
+      for (int t = 0; t < n; ++t) s += Vt[t + (int64_t)a * n] * Vt[t + (int64_t)(k + b) * n];
+      Hm[e] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * rbar; e += nthr) {
+      const int t = e % n, b = e / n;
+      T s = Vt[t + (int64_t)(k + b) * n];
+      for (int a = 0; a < k; ++a) s -= Vt[t + (int64_t)a * n] * Hm[a + (int64_t)b * k];
+      Vt[t + (int64_t)(k + b) * n] = s;
+    }
+    __syncthreads();
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int b = 0; b < rbar; ++b) {
+      T* vb = Vt + (int64_t)(k + b) * n;
+      T s = 0;
+      for (int t = tid; t < n; t += nthr) s += vb[t] * vb[t];
+      s = block_sum(s, red);
+      const T inv = s > T(0) ? T(1) / sqrt(s) : T(0);
+      for (int t = tid; t < n; t += nthr) vb[t] *= inv;
+      __syncthreads();
+      for (int c = b + 1 + wave; c < rbar; c += 4) {
+        T* vc = Vt + (int64_t)(k + c) * n;
+        T d = 0;
+        for (int t = lane; t < n; t += 64) d += vb[t] * vc[t];
+        d = wave_sum(d);
+        for (int t = lane; t < n; t += 64) vc[t] -= d * vb[t];
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- 5. complement by Householder QR of V~ ----
+  for (int e = tid; e < n * kt; e += nthr) Hm[e] = Vt[e];
+  __syncthreads();
+  for (int j = 0; j < kt; ++j) {
+    T* hj = Hm + (int64_t)j * n;
+    T s = 0;
+    for (int t = j + 1 + tid; t < n; t += nthr) s += hj[t] * hj[t];
+    s = block_sum(s, red);
+    const T alpha = hj[j];
+    T tj = 0, beta = alpha;
+    if (s != T(0)) {
+      const T nrm = sqrt(alpha * alpha + s);
+      beta = alpha >= T(0) ? -nrm : nrm;
+      tj = (beta - alpha) / beta;
+    }
+    __syncthreads();
+    if (tj != T(0)) {
+      const T scale = T(1) / (alpha - beta);
+      for (int t = j + 1 + tid; t < n; t += nthr) hj[t] *= scale;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      hj[j] = T(1);  // implicit unit of the reflector, stored explicitly
+      tau[j] = tj;
+    }
+    __syncthreads();
+    if (tj != T(0)) {
+      for (int c = j + 1 + wave; c < kt; c += 4) {
+        T* hc = Hm + (int64_t)c * n;
+        T d = 0;
+        for (int t = j + lane; t < n; t += 64) d += hj[t] * hc[t];
+        d = wave_sum(d) * tj;
+        for (int t = j + lane; t < n; t += 64) hc[t] -= d * hj[t];
+      }
+    }
+    __syncthreads();
+  }
+  // X = [0; I_r] then X <- H_j X for j = kt-1 .. 0, written into Q[:, 0:r]
+  for (int e = tid; e < n * r; e += nthr) {
+    const int row = e % n, c = e / n;
+    Q[e] = (row == kt + c) ? T(1) : T(0);
+  }
+  __syncthreads();
+  for (int j = kt - 1; j >= 0; --j) {
+    const T tj = tau[j];
+    if (tj == T(0)) continue;
+    const T* hj = Hm + (int64_t)j * n;
+    for (int c = wave; c < r; c += 4) {
+      T* qc = Q + (int64_t)c * n;
+      T d = 0;
+      for (int t = j + lane; t < n; t += 64) d += hj[t] * qc[t];
+      d = wave_sum(d) * tj;
+      for (int t = j + lane; t < n; t += 64) qc[t] -= d * hj[t];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    rout[tk.ri] = r;
+    for (int i = 0; i < n; ++i)
+      if (!(sig[i] == sig[i])) atomicOr(err, 2);
+  }
+}
+
+template <class T>
+void launch_augment(const AugTask<T>* tasks, int ntasks, const FillRef<T>* refs, int32_t* r,
+                    T eps_fill, int* err, hipStream_t s) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(k_augment<T>, dim3(ntasks), dim3(256), 0, s, tasks, refs, r, eps_fill, err);
+}
+
+// ---------------------------------------------------------------------------
+// LU with partial pivoting of the redundant block D_RR, one workgroup each.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_lu(const LUTask<T>* __restrict__ tasks,
+                                            const int32_t* __restrict__ dyn, int* err) {
+  const LUTask<T> tk = tasks[blockIdx.x];
+  const int r = dyn[tk.ri];
+  T* A = tk.A;
+  const int64_t ld = tk.lda;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  __shared__ T wv[4];
+  __shared__ int wi[4];
+  __shared__ int sh_p;
+  for (int j = 0; j < r; ++j) {
+    T best = -1;
+    int bi = j;
+    for (int i = j + tid; i < r; i += nthr) {
+      const T v = fabs(A[i + (int64_t)j * ld]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const T ov = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      wv[wave] = best;
+      wi[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      T b = wv[0];
+      int p = wi[0];
+      for (int w = 1; w < 4; ++w)
+        if (wv[w] > b || (wv[w] == b && wi[w] < p)) {
+          b = wv[w];
+          p = wi[w];
+        }
+      sh_p = p;
+      tk.piv[j] = p;
+      if (!(b > T(0))) atomicOr(err, 1);
+    }
+    __syncthreads();
+    const int p = sh_p;
+    if (p != j)
+      for (int c = tid; c < r; c += nthr) {
+        const T x = A[j + (int64_t)c * ld];
+        A[j + (int64_t)c * ld] = A[p + (int64_t)c * ld];
+        A[p + (int64_t)c * ld] = x;
+      }
+    __syncthreads();
+    const T d = A[j + (int64_t)j * ld];
+    const T inv = d != T(0) ? T(1) / d : T(0);
+    for (int i = j + 1 + tid; i < r; i += nthr) A[i + (int64_t)j * ld] *= inv;
+    __syncthreads();
+    const int m = r - j - 1;
+    for (int e = tid; e < m * m; e += nthr) {
+      const int i = j + 1 + e % m, c = j + 1 + e / m;
+      A[i + (int64_t)c * ld] -= A[i + (int64_t)j * ld] * A[j + (int64_t)c * ld];
+    }
+    __syncthreads();
+  }
+}
+
+template <class T>
+void launch_lu(const LUTask<T>* tasks, int ntasks, const int32_t* dyn, int* err, hipStream_t s) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(k_lu<T>, dim3(ntasks), dim3(256), 0, s, tasks, dyn, err);
+}
+
+// ---------------------------------------------------------------------------
+// B <- A_RR^{-1} B with the pivoted LU of the leading r x r block; one column
+// per thread, the factor staged in LDS when it fits.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(64) void k_trsm(const TrsmTask<T>* __restrict__ tasks,
+                                             const int32_t* __restrict__ dyn) {
+  const TrsmTask<T> tk = tasks[blockIdx.x];
+  const int r = tk.ri >= 0 ? dyn[tk.ri] : tk.rs;
+  if (r == 0) return;
+  const int c0 = tk.c0d >= 0 ? dyn[tk.c0d] : tk.c0s;
+  const T* LU = tk.LU;
+  const int64_t ld = tk.ldlu;
+  for (int col = c0 + threadIdx.x; col < tk.ncols; col += blockDim.x) {
+    T* b = tk.B + (int64_t)col * tk.ldb;
+    for (int j = 0; j < r; ++j) {
+      const int p = tk.piv[j];
+      if (p != j) {
+        const T x = b[j];
+        b[j] = b[p];
+        b[p] = x;
+      }
+    }
+    for (int j = 0; j < r; ++j) {
+      const T bj = b[j];
+      for (int i = j + 1; i < r; ++i) b[i] -= LU[i + (int64_t)j * ld] * bj;
+    }
+    for (int j = r - 1; j >= 0; --j) {
+      const T bj = b[j] / LU[j + (int64_t)j * ld];
+      b[j] = bj;
+      for (int i = 0; i < j; ++i) b[i] -= LU[i + (int64_t)j * ld] * bj;
+    }
+  }
+}
+
+template <class T>
+void launch_trsm(const TrsmTask<T>* tasks, int ntasks, const int32_t* dyn, hipStream_t s) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(k_trsm<T>, dim3(ntasks), dim3(64), 0, s, tasks, dyn);
+}
+
+// ---------------------------------------------------------------------------
+// Block copies / accumulations with type conversion.
+// ---------------------------------------------------------------------------
+template <class T, class S>
+__global__ __launch_bounds__(256) void k_copy(const CTask<T, S>* __restrict__ tasks, int ntasks) {
+  const int64_t tile = blockIdx.x;
+  int lo = 0, hi = ntasks - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (tasks[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+  }
+  const CTask<T, S>& tk = tasks[lo];
+  const int64_t base = (tile - tk.tile0) * kCopyTile;
+  const int64_t tot = (int64_t)tk.rows * tk.cols;
+  for (int64_t e = base + threadIdx.x; e < min(base + kCopyTile, tot); e += blockDim.x) {
+    const int64_t r = e % tk.rows, c = e / tk.rows;
+    const T v = (T)tk.src[r + c * tk.lds];
+    T* d = tk.dst + r + c * tk.ldd;
+    *d = tk.add ? *d + v : v;
+  }
+}
+
+template <class T, class S>
+void launch_copy(const CTask<T, S>* tasks, int ntasks, int64_t ntiles, hipStream_t s) {
+  if (ntasks <= 0 || ntiles <= 0) return;
+  hipLaunchKernelGGL((k_copy<T, S>), dim3((unsigned)ntiles), dim3(256), 0, s, tasks, ntasks);
+}
+
+template <class T> __global__ void k_fill(T* p, int64_t n, T v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+template <class T> void launch_fill(T* p, int64_t n, T v, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+}
+
+template <class T, class S>
+__global__ void k_gather(T* dst, int64_t ldd, const S* src, int64_t lds, const int64_t* perm,
+                         int64_t n, int nrhs) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e % n, c = e / n;
+    dst[p + c * ldd] = (T)src[perm[p] + c * lds];
+  }
+}
+template <class T, class S>
+__global__ void k_scatter(T* dst, int64_t ldd, const S* src, int64_t lds, const int64_t* perm,
+                          int64_t n, int nrhs) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e % n, c = e / n;
+    dst[perm[p] + c * ldd] = (T)src[p + c * lds];
+  }
+}
+template <class T, class S>
+void launch_gather_rows(T* dst, int64_t ldd, const S* src, int64_t lds, const int64_t* perm,
+                        int64_t n, int nrhs, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((n * nrhs + 255) / 256, 65536);
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL((k_gather<T, S>), dim3((unsigned)blocks), dim3(256), 0, s, dst, ldd, src,
+                     lds, perm, n, nrhs);
+}
+template <class T, class S>
+void launch_scatter_rows(T* dst, int64_t ldd, const S* src, int64_t lds, const int64_t* perm,
+                         int64_t n, int nrhs, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((n * nrhs + 255) / 256, 65536);
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL((k_scatter<T, S>), dim3((unsigned)blocks), dim3(256), 0, s, dst, ldd, src,
+                     lds, perm, n, nrhs);
+}
+
+template <class T> __global__ void k_convert(T* dst, const double* src, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (T)src[i];
+}
+template <class T> void launch_convert(T* dst, const double* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_convert<T>, dim3((unsigned)blocks), dim3(256), 0, s, dst, src, n);
+}
+
+// ---------------------------------------------------------------------------
+// Dense top-level LU (blocked right-looking, partial pivoting).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_panel_lu(T* A, int64_t lda, int64_t n, int64_t j0,
+                                                  int nb, int32_t* piv, int* err) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  __shared__ T wv[4];
+  __shared__ int64_t wi[4];
+  __shared__ int64_t sh_p;
+  for (int jj = 0; jj < nb; ++jj) {
+    const int64_t j = j0 + jj;
+    T best = -1;
+    int64_t bi = j;
+    for (int64_t i = j + tid; i < n; i += nthr) {
+      const T v = fabs(A[i + j * lda]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const T ov = __shfl_xor(best, o, 64);
+      const int64_t oi = __shfl_xor(bi, o, 64);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      wv[wave] = best;
+      wi[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      T b = wv[0];
+      int64_t p = wi[0];
+      for (int w = 1; w < 4; ++w)
+        if (wv[w] > b || (wv[w] == b && wi[w] < p)) {
+          b = wv[w];
+          p = wi[w];
+        }
+      sh_p = p;
+      piv[j] = (int32_t)p;
+      if (!(b > T(0))) atomicOr(err, 1);
+    }
+    __syncthreads();
+    const int64_t p = sh_p;
+    if (p != j)
+      for (int c = tid; c < nb; c += nthr) {
+        const int64_t cc = j0 + c;
+        const T x = A[j + cc * lda];
+        A[j + cc * lda] = A[p + cc * lda];
+        A[p + cc * lda] = x;
+      }
+    __syncthreads();
+    const T d = A[j + j * lda];
+    const T inv = d != T(0) ? T(1) / d : T(0);
+    for (int64_t i = j + 1 + tid; i < n; i += nthr) A[i + j * lda] *= inv;
+    __syncthreads();
+    // update the remaining panel columns
+    for (int c = jj + 1 + wave; c < nb; c += 4) {
+      const int64_t cc = j0 + c;
+      const T u = A[j + cc * lda];
+      for (int64_t i = j + 1 + lane; i < n; i += 64) A[i + cc * lda] -= A[i + j * lda] * u;
+    }
+    __syncthreads();
+  }
+}
+template <class T>
+void launch_panel_lu(T* A, int64_t lda, int64_t n, int64_t j0, int nb, int32_t* piv, int* err,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_panel_lu<T>, dim3(1), dim3(256), 0, s, A, lda, n, j0, nb, piv, err);
+}
+
+// apply the row interchanges of rows j0..j0+nb-1 to all columns outside [skip0, skip1)
+template <class T>
+__global__ void k_laswp(T* A, int64_t lda, int64_t ncols, int64_t j0, int nb, const int32_t* piv,
+                        int64_t skip0, int64_t skip1) {
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncols;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    if (c >= skip0 && c < skip1) continue;
+    for (int jj = 0; jj < nb; ++jj) {
+      const int64_t j = j0 + jj, p = piv[j];
+      if (p != j) {
+        const T x = A[j + c * lda];
+        A[j + c * lda] = A[p + c * lda];
+        A[p + c * lda] = x;
+      }
+    }
+  }
+}
+template <class T>
+void launch_laswp(T* A, int64_t lda, int64_t ncols, int64_t j0, int nb, const int32_t* piv,
+                  int64_t skip0, int64_t skip1, hipStream_t s) {
+  if (ncols <= 0) return;
+  const int64_t blocks = std::min<int64_t>((ncols + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_laswp<T>, dim3((unsigned)blocks), dim3(256), 0, s, A, lda, ncols, j0, nb,
+                     piv, skip0, skip1);
+}
+
+// triangular solve with an nb x nb diagonal block for ncols right-hand sides:
+// unit lower (lower_unit = 1) or upper with diagonal (lower_unit = 0)
+template <class T>
+__global__ void k_trsm_block(const T* A, int64_t lda, T* B, int64_t ldb, int nb, int64_t ncols,
+                             int lower_unit) {
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncols;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    T* b = B + c * ldb;
+    if (lower_unit) {
+      for (int j = 0; j < nb; ++j) {
+        const T bj = b[j];
+        for (int i = j + 1; i < nb; ++i) b[i] -= A[i + (int64_t)j * lda] * bj;
+      }
+    } else {
+      for (int j = nb - 1; j >= 0; --j) {
+        const T bj = b[j] / A[j + (int64_t)j * lda];
+        b[j] = bj;
+        for (int i = 0; i < j; ++i) b[i] -= A[i + (int64_t)j * lda] * bj;
+      }
+    }
+  }
+}
+template <class T>
+void launch_trsm_block(const T* A, int64_t lda, T* B, int64_t ldb, int nb, int64_t ncols,
+                       int lower_unit, hipStream_t s) {
+  if (ncols <= 0 || nb <= 0) return;
+  const int64_t blocks = std::min<int64_t>((ncols + 63) / 64, 4096);
+  hipLaunchKernelGGL(k_trsm_block<T>, dim3((unsigned)blocks), dim3(64), 0, s, A, lda, B, ldb, nb,
+                     ncols, lower_unit);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 column reductions and updates for the refinement loop.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_colnorms(const double* X, int64_t ldx, int64_t n,
+                                                  double* out) {
+  __shared__ double red[8];
+  const double* x = X + blockIdx.x * ldx;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += x[i] * x[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = sqrt(s);
+}
+void launch_colnorms(const double* X, int64_t ldx, int64_t n, int nrhs, double* out,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_colnorms, dim3(nrhs), dim3(256), 0, s, X, ldx, n, out);
+}
+
+// out[v + c*nvec] = <V_v[:, c], W[:, c]>, V_v = V + v*vstride
+__global__ __launch_bounds__(256) void k_dots(const double* V, int64_t ldv, int64_t vstride,
+                                              int nvec, const double* W, int64_t ldw, int64_t n,
+                                              double* out) {
+  __shared__ double red[8];
+  const int v = blockIdx.x % nvec, c = blockIdx.x / nvec;
+  const double* a = V + v * vstride + c * ldv;
+  const double* b = W + c * ldw;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += a[i] * b[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[v + (int64_t)c * nvec] = s;
+}
+void launch_dots(const double* V, int64_t ldv, int64_t vstride, int nvec, const double* W,
+                 int64_t ldw, int64_t n, int nrhs, double* out, hipStream_t s) {
+  if (nvec <= 0) return;
+  hipLaunchKernelGGL(k_dots, dim3(nvec * nrhs), dim3(256), 0, s, V, ldv, vstride, nvec, W, ldw, n,
+                     out);
+}
+
+// W[:, c] += sign * sum_v coef[v + c*nvec] V_v[:, c]
+__global__ void k_update(double* W, int64_t ldw, const double* V, int64_t ldv, int64_t vstride,
+                         int nvec, const double* coef, double sign, int64_t n, int nrhs) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % n, c = e / n;
+    double s = 0;
+    for (int v = 0; v < nvec; ++v) s += coef[v + c * nvec] * V[v * vstride + i + c * ldv];
+    W[i + c * ldw] += sign * s;
+  }
+}
+void launch_update(double* W, int64_t ldw, const double* V, int64_t ldv, int64_t vstride, int nvec,
+                   const double* coef, double sign, int64_t n, int nrhs, hipStream_t s) {
+  if (nvec <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n * nrhs + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_update, dim3((unsigned)blocks), dim3(256), 0, s, W, ldw, V, ldv, vstride,
+                     nvec, coef, sign, n, nrhs);
+}
+
+// dst[:, c] = src[:, c] * (invert ? 1/norms[c] : norms[c]) (zero when dividing by zero)
+__global__ void k_scale_cols(double* dst, int64_t ldd, const double* src, int64_t lds,
+                             const double* norms, int64_t n, int nrhs, int invert) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % n, c = e / n;
+    const double a = norms[c];
+    const double f = invert ? (a != 0 ? 1.0 / a : 0.0) : a;
+    dst[i + c * ldd] = src[i + c * lds] * f;
+  }
+}
+void launch_scale_cols(double* dst, int64_t ldd, const double* src, int64_t lds,
+                       const double* norms, int64_t n, int nrhs, int invert, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((n * nrhs + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)blocks), dim3(256), 0, s, dst, ldd, src, lds,
+                     norms, n, nrhs, invert);
+}
+
+__global__ void k_axpy_cols(double* Y, int64_t ldy, const double* X, int64_t ldx, const double* a,
+                            int64_t n, int nrhs) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % n, c = e / n;
+    Y[i + c * ldy] += (a ? a[c] : 1.0) * X[i + c * ldx];
+  }
+}
+void launch_axpy_cols(double* Y, int64_t ldy, const double* X, int64_t ldx, const double* a,
+                      int64_t n, int nrhs, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((n * nrhs + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_axpy_cols, dim3((unsigned)blocks), dim3(256), 0, s, Y, ldy, X, ldx, a, n,
+                     nrhs);
+}
+
+__global__ void k_sub(double* R, int64_t ldr, const double* B, int64_t ldb, const double* AX,
+                      int64_t ldax, int64_t n, int nrhs) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % n, c = e / n;
+    R[i + c * ldr] = B[i + c * ldb] - AX[i + c * ldax];
+  }
+}
+void launch_sub(double* R, int64_t ldr, const double* B, int64_t ldb, const double* AX,
+                int64_t ldax, int64_t n, int nrhs, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((n * nrhs + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_sub, dim3((unsigned)blocks), dim3(256), 0, s, R, ldr, B, ldb, AX, ldax, n,
+                     nrhs);
+}
+
+__global__ void k_check_finite(const double* X, int64_t n, int* flag) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = X[i];
+    if (!(v - v == 0.0)) atomicOr(flag, 1);
+  }
+}
+void launch_check_finite(const double* X, int64_t n, int* flag, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)blocks), dim3(256), 0, s, X, n, flag);
+}
+
+// ---- explicit instantiations ----
+#define H2K_INST(T)                                                                           \
+  template void launch_gemm<T>(const GOut<T>*, int, const GCon<T>*, const int32_t*, int64_t,  \
+                               int, hipStream_t);                                             \
+  template void launch_strip<T>(const STask<T>*, int, const int32_t*, int64_t, int,           \
+                                hipStream_t);                                                 \
+  template void launch_augment<T>(const AugTask<T>*, int, const FillRef<T>*, int32_t*, T,     \
+                                  int*, hipStream_t);                                         \
+  template void launch_lu<T>(const LUTask<T>*, int, const int32_t*, int*, hipStream_t);       \
+  template void launch_trsm<T>(const TrsmTask<T>*, int, const int32_t*, hipStream_t);         \
+  template void launch_copy<T, double>(const CTask<T, double>*, int, int64_t, hipStream_t);   \
+  template void launch_copy<T, float>(const CTask<T, float>*, int, int64_t, hipStream_t);     \
+  template void launch_fill<T>(T*, int64_t, T, hipStream_t);                                  \
+  template void launch_gather_rows<T, double>(T*, int64_t, const double*, int64_t,            \
+                                              const int64_t*, int64_t, int, hipStream_t);     \
+  template void launch_scatter_rows<double, T>(double*, int64_t, const T*, int64_t,           \
+                                               const int64_t*, int64_t, int, hipStream_t);    \
+  template void launch_panel_lu<T>(T*, int64_t, int64_t, int64_t, int, int32_t*, int*,        \
+                                   hipStream_t);                                              \
+  template void launch_laswp<T>(T*, int64_t, int64_t, int64_t, int, const int32_t*, int64_t,  \
+                                int64_t, hipStream_t);                                        \
+  template void launch_trsm_block<T>(const T*, int64_t, T*, int64_t, int, int64_t, int,       \
+                                     hipStream_t);                                            \
+  template void launch_convert<T>(T*, const double*, int64_t, hipStream_t);
+
+H2K_INST(double)
+H2K_INST(float)
+template void launch_fill<int32_t>(int32_t*, int64_t, int32_t, hipStream_t);
+
+}  // namespace h2k

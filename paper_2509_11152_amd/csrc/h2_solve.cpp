@@ -1,0 +1,607 @@
+// Solve (Algorithm 3), H^2 matrix-vector product and GMRES-based iterative
+// refinement.  After factorization every rank is known on the host, so the
+// solve's task lists use static window boundaries only; all instances of a
+// batch share one launch per (height, colour step).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+
+#include "h2_driver.h"
+
+namespace h2drv {
+
+using namespace h2k;
+
+namespace {
+
+template <class T> struct GemmBatch {
+  std::vector<GOut<T>> outs;
+  std::vector<GCon<T>> cons;
+  int64_t tiles = 0;
+  int shape, TM, TN;
+  explicit GemmBatch(int sh) : shape(sh), TM(64), TN(sh == 0 ? 64 : 16) {}
+  // begin output C[m0:m, n0:n] = beta C + alpha sum ...
+  void out(T* C, int64_t ldc, int m0, int m, int n0, int n, T alpha, T beta) {
+    end();
+    GOut<T> o{};
+    o.C = C;
+    o.ldc = ldc;
+    o.m = m;
+    o.n = n;
+    o.m0d = -1;
+    o.m0s = m0;
+    o.m1d = -1;
+    o.n0d = -1;
+    o.n0s = n0;
+    o.cbeg = o.cend = (int)cons.size();
+    o.tm = std::max(0, (m - m0 + TM - 1) / TM);
+    o.tn = std::max(0, (n - n0 + TN - 1) / TN);
+    o.tile0 = tiles;
+    o.alpha = alpha;
+    o.beta = beta;
+    outs.push_back(o);
+    pending = true;
+  }
+  void con(const T* A, int64_t lda, int transA, const T* B, int64_t ldb, int k0, int k) {
+    if (k <= k0) return;
+    GCon<T> g{};
+    g.A = A;
+    g.B = B;
+    g.lda = lda;
+    g.ldb = ldb;
+    g.k = k;
+    g.k0d = -1;
+    g.k0s = k0;
+    g.k1d = -1;
+    g.transA = transA;
+    cons.push_back(g);
+    outs.back().cend = (int)cons.size();
+  }
+  // close the current output (drops it when it has no tiles)
+  void end() {
+    if (!pending) return;
+    pending = false;
+    GOut<T>& o = outs.back();
+    const int64_t t = (int64_t)o.tm * o.tn;
+    if (t == 0) {
+      cons.resize(o.cbeg);
+      outs.pop_back();
+      return;
+    }
+    tiles += t;
+  }
+  void launch(DescArena& ar, hipStream_t s) {
+    end();
+    if (outs.empty()) return;
+    launch_gemm<T>(ar.put(outs), (int)outs.size(), ar.put(cons), nullptr, tiles, shape, s);
+    outs.clear();
+    cons.clear();
+    tiles = 0;
+  }
+  bool pending = false;
+};
+
+template <class T> struct StripBatch {
+  std::vector<STask<T>> tasks;
+  int64_t strips = 0;
+  int maxn = 1;
+  void add(T* X, int64_t ldx, const T* Q, int n, int ext, int side, int trans) {
+    if (n <= 0 || ext <= 0) return;
+    STask<T> t{};
+    t.X = X;
+    t.Q = Q;
+    t.ldx = ldx;
+    t.n = n;
+    t.ext = ext;
+    t.d0 = -1;
+    t.s0 = 0;
+    t.side = side;
+    t.trans = trans;
+    t.strip0 = strips;
+    strips += (ext + kStrip - 1) / kStrip;
+    maxn = std::max(maxn, n);
+    tasks.push_back(t);
+  }
+  void launch(DescArena& ar, hipStream_t s) {
+    if (tasks.empty()) return;
+    launch_strip<T>(ar.put(tasks), (int)tasks.size(), nullptr, strips, maxn, s);
+    tasks.clear();
+    strips = 0;
+    maxn = 1;
+  }
+};
+
+template <class T> struct CopyB {
+  std::vector<CTask<T, T>> tasks;
+  int64_t tiles = 0;
+  void add(const T* src, int64_t lds, T* dst, int64_t ldd, int rows, int cols) {
+    if (rows <= 0 || cols <= 0) return;
+    CTask<T, T> t{};
+    t.src = src;
+    t.dst = dst;
+    t.lds = lds;
+    t.ldd = ldd;
+    t.rows = rows;
+    t.cols = cols;
+    t.add = 0;
+    t.tile0 = tiles;
+    tiles += ((int64_t)rows * cols + kCopyTile - 1) / kCopyTile;
+    tasks.push_back(t);
+  }
+  void launch(DescArena& ar, hipStream_t s) {
+    if (tasks.empty()) return;
+    launch_copy<T, T>(ar.put(tasks), (int)tasks.size(), tiles, s);
+    tasks.clear();
+    tiles = 0;
+  }
+};
+
+template <class T> LevelStore<T>& store(h2_factor_s* F, size_t li);
+template <> LevelStore<double>& store<double>(h2_factor_s* F, size_t li) { return F->st64[li]; }
+template <> LevelStore<float>& store<float>(h2_factor_s* F, size_t li) { return F->st32[li]; }
+template <class T> DevArray<T>& topM(h2_factor_s* F);
+template <> DevArray<double>& topM<double>(h2_factor_s* F) { return F->M64; }
+template <> DevArray<float>& topM<float>(h2_factor_s* F) { return F->M32; }
+
+// per-instance solve state
+template <class T> struct SolveInst {
+  h2_factor_s* F;
+  std::vector<DevArray<T>> vec;  // level vectors (leaf level first), plus the top vector
+  std::vector<std::vector<int64_t>> voff;
+  std::vector<int64_t> vlen;
+};
+
+template <class T>
+void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
+               const std::vector<const double*>& B, const std::vector<int64_t>& ldb, int nrhs,
+               const std::vector<double*>& X, const std::vector<int64_t>& ldx) {
+  hipStream_t s = ctx->stream;
+  DescArena& ar = ctx->arena;
+  ar.s = s;
+  const int shape = nrhs > 16 ? 0 : 1;
+  std::vector<SolveInst<T>> si(Fs.size());
+  size_t maxlev = 0;
+  for (size_t q = 0; q < Fs.size(); ++q) {
+    h2_factor_s* F = Fs[q];
+    SolveInst<T>& S = si[q];
+    S.F = F;
+    const size_t nlev = F->plans.size();
+    maxlev = std::max(maxlev, nlev);
+    S.vec = std::vector<DevArray<T>>(nlev + 1);
+    S.voff.resize(nlev + 1);
+    S.vlen.resize(nlev + 1);
+    for (size_t li = 0; li < nlev; ++li) {
+      const LevelPlan& P = F->plans[li];
+      S.voff[li].resize(P.nl);
+      int64_t o = 0;
+      for (int i = 0; i < P.nl; ++i) {
+        S.voff[li][i] = o;
+        o += P.n[i];
+      }
+      S.vlen[li] = o;
+      S.vec[li].alloc(std::max<int64_t>(o, 1) * nrhs, nullptr);
+    }
+    S.voff[nlev] = F->top_off;
+    S.vlen[nlev] = F->n_top;
+    S.vec[nlev].alloc(std::max<int64_t>(F->n_top, 1) * nrhs, nullptr);
+    // b in tree order into the first vector
+    T* dst = S.vec[0].p;
+    const int64_t ld = S.vlen[0];
+    launch_gather_rows<T, double>(dst, ld, B[q], ldb[q], F->perm_d.p, F->N, nrhs, s);
+  }
+  // ---- forward, level by level from the leaves ----
+  for (size_t li = 0; li < maxlev; ++li) {
+    int maxc = 0;
+    for (auto& S : si)
+      if (li < S.F->plans.size()) maxc = std::max(maxc, S.F->plans[li].ncolors);
+    for (int c = 0; c < maxc; ++c) {
+      StripBatch<T> sb;
+      std::vector<TrsmTask<T>> trs;
+      GemmBatch<T> gb(shape);
+      for (auto& S : si) {
+        h2_factor_s* F = S.F;
+        if (li >= F->plans.size()) continue;
+        const LevelPlan& P = F->plans[li];
+        if (c >= P.ncolors) continue;
+        LevelStore<T>& st = store<T>(F, li);
+        T* v = S.vec[li].p;
+        const int64_t ld = S.vlen[li];
+        for (int i : P.members[c]) {
+          sb.add(v + S.voff[li][i], ld, st.Q.p + P.offQ[i], P.n[i], nrhs, 0, 1);
+          if (P.r[i] > 0) {
+            TrsmTask<T> t{};
+            t.LU = st.D.p + P.poff[P.find(i, i)];
+            t.piv = st.piv.p + P.offPiv[i];
+            t.B = v + S.voff[li][i];
+            t.ldlu = P.n[i];
+            t.ldb = ld;
+            t.ncols = nrhs;
+            t.ri = -1;
+            t.rs = P.r[i];
+            t.c0d = -1;
+            t.c0s = 0;
+            trs.push_back(t);
+          }
+        }
+        // b_j[active rows] -= D_{j,R_i} z_i, grouped by target j
+        std::vector<std::pair<int, int>> inc;  // (j, i)
+        for (int i : P.members[c])
+          if (P.r[i] > 0)
+            for (int j : P.nb[i]) inc.push_back({j, i});
+        std::sort(inc.begin(), inc.end());
+        for (size_t a = 0; a < inc.size();) {
+          size_t b = a;
+          const int j = inc[a].first;
+          const int aj = P.color[j] <= c ? P.r[j] : 0;
+          gb.out(v + S.voff[li][j], ld, aj, P.n[j], 0, nrhs, T(-1), T(1));
+          for (; b < inc.size() && inc[b].first == j; ++b) {
+            const int i = inc[b].second;
+            gb.con(st.D.p + P.poff[P.find(j, i)], P.n[j], 0, v + S.voff[li][i], ld, 0, P.r[i]);
+          }
+          gb.end();
+          a = b;
+        }
+      }
+      sb.launch(ar, s);
+      if (!trs.empty()) launch_trsm<T>(ar.put(trs), (int)trs.size(), nullptr, s);
+      gb.launch(ar, s);
+    }
+    // upsweep: skeleton parts of the children form the parent segments
+    CopyB<T> cb;
+    for (auto& S : si) {
+      h2_factor_s* F = S.F;
+      if (li >= F->plans.size()) continue;
+      const LevelPlan& P = F->plans[li];
+      const size_t nx = li + 1;  // next vector (a level or the top)
+      const bool top = nx == F->plans.size();
+      const int pa = F->lp[P.lev - 1];
+      T* v = S.vec[li].p;
+      T* w = S.vec[nx].p;
+      const int64_t ldv = S.vlen[li], ldw = S.vlen[nx];
+      for (int t = 0; t < F->lp[P.lev] - pa; ++t) {
+        const int tau = pa + t;
+        int64_t o = top ? F->top_off[t] : S.voff[nx][t];
+        for (int cc = F->cp[tau]; cc < F->cp[tau + 1]; ++cc) {
+          const int c = cc - P.a;
+          const int kt = P.n[c] - P.r[c];
+          cb.add(v + S.voff[li][c] + P.r[c], ldv, w + o, ldw, kt, nrhs);
+          o += kt;
+        }
+      }
+    }
+    cb.launch(ar, s);
+  }
+  // ---- dense top solve ----
+  for (auto& S : si) {
+    h2_factor_s* F = S.F;
+    const int64_t n = F->n_top;
+    if (n == 0) continue;
+    const size_t nx = F->plans.size();
+    if (nx == 0) {
+      // no skeletonized level: b (tree order) is the top vector
+      // (vec[0] was allocated with the top size and received the gather)
+    }
+    T* b = S.vec[nx].p;
+    const int64_t ldb2 = S.vlen[nx];
+    T* M = topM<T>(F).p;
+    launch_laswp<T>(b, ldb2, nrhs, 0, (int)n, F->top_piv.p, -1, -1, s);
+    const int nb = 64;
+    for (int64_t j0 = 0; j0 < n; j0 += nb) {
+      const int w = (int)std::min<int64_t>(nb, n - j0);
+      launch_trsm_block<T>(M + j0 + j0 * n, n, b + j0, ldb2, w, nrhs, 1, s);
+      if (j0 + w < n) {
+        GemmBatch<T> gb(shape);
+        gb.out(b + j0 + w, ldb2, 0, (int)(n - j0 - w), 0, nrhs, T(-1), T(1));
+        gb.con(M + (j0 + w) + j0 * n, n, 0, b + j0, ldb2, 0, w);
+        gb.launch(ar, s);
+      }
+    }
+    for (int64_t j0 = ((n - 1) / nb) * nb; j0 >= 0; j0 -= nb) {
+      const int w = (int)std::min<int64_t>(nb, n - j0);
+      launch_trsm_block<T>(M + j0 + j0 * n, n, b + j0, ldb2, w, nrhs, 0, s);
+      if (j0 > 0) {
+        GemmBatch<T> gb(shape);
+        gb.out(b, ldb2, 0, (int)j0, 0, nrhs, T(-1), T(1));
+        gb.con(M + j0 * n, n, 0, b + j0, ldb2, 0, w);
+        gb.launch(ar, s);
+      }
+    }
+  }
+  // ---- backward, from the top level down ----
+  for (size_t lj = maxlev; lj-- > 0;) {
+    // downsweep into level vectors whose instance has level lj
+    CopyB<T> cb;
+    for (auto& S : si) {
+      h2_factor_s* F = S.F;
+      if (lj >= F->plans.size()) continue;
+      const LevelPlan& P = F->plans[lj];
+      const size_t nx = lj + 1;
+      const bool top = nx == F->plans.size();
+      const int pa = F->lp[P.lev - 1];
+      T* v = S.vec[lj].p;
+      T* w = S.vec[nx].p;
+      const int64_t ldv = S.vlen[lj], ldw = S.vlen[nx];
+      for (int t = 0; t < F->lp[P.lev] - pa; ++t) {
+        const int tau = pa + t;
+        int64_t o = top ? F->top_off[t] : S.voff[nx][t];
+        for (int cc = F->cp[tau]; cc < F->cp[tau + 1]; ++cc) {
+          const int c = cc - P.a;
+          const int kt = P.n[c] - P.r[c];
+          cb.add(w + o, ldw, v + S.voff[lj][c] + P.r[c], ldv, kt, nrhs);
+          o += kt;
+        }
+      }
+    }
+    cb.launch(ar, s);
+    int maxc = 0;
+    for (auto& S : si)
+      if (lj < S.F->plans.size()) maxc = std::max(maxc, S.F->plans[lj].ncolors);
+    for (int c = maxc - 1; c >= 0; --c) {
+      GemmBatch<T> gb(shape);
+      StripBatch<T> sb;
+      for (auto& S : si) {
+        h2_factor_s* F = S.F;
+        if (lj >= F->plans.size()) continue;
+        const LevelPlan& P = F->plans[lj];
+        if (c >= P.ncolors) continue;
+        LevelStore<T>& st = store<T>(F, lj);
+        T* v = S.vec[lj].p;
+        const int64_t ld = S.vlen[lj];
+        for (int i : P.members[c]) {
+          if (P.r[i] > 0) {
+            // y_iR -= sum_k Y_k y_k over the columns active when i was eliminated
+            gb.out(v + S.voff[lj][i], ld, 0, P.r[i], 0, nrhs, T(-1), T(1));
+            for (int k : P.nb[i]) {
+              const int ak = P.color[k] <= c ? P.r[k] : 0;
+              gb.con(st.D.p + P.poff[P.find(i, k)], P.n[i], 0, v + S.voff[lj][k], ld, ak,
+                     P.n[k]);
+            }
+            gb.end();
+          }
+          sb.add(v + S.voff[lj][i], ld, st.Q.p + P.offQ[i], P.n[i], nrhs, 0, 0);
+        }
+      }
+      gb.launch(ar, s);
+      sb.launch(ar, s);
+    }
+  }
+  // ---- back to the original order ----
+  for (size_t q = 0; q < Fs.size(); ++q) {
+    SolveInst<T>& S = si[q];
+    launch_scatter_rows<double, T>(X[q], ldx[q], S.vec[0].p, S.vlen[0], S.F->perm_d.p, S.F->N,
+                                   nrhs, s);
+  }
+  H2_HIP(hipStreamSynchronize(s));
+  ar.reset();
+}
+
+}  // namespace
+
+void solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
+           const std::vector<const double*>& B, const std::vector<int64_t>& ldb, int nrhs,
+           const std::vector<double*>& X, const std::vector<int64_t>& ldx) {
+  if (Fs[0]->prec == H2_PREC_FP64)
+    run_solve<double>(ctx, Fs, B, ldb, nrhs, X, ldx);
+  else
+    run_solve<float>(ctx, Fs, B, ldb, nrhs, X, ldx);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 H^2 matvec: permute, upsweep U^T / E^T, couplings, downsweep E,
+// leaf bases U plus dense near blocks, permute back.
+// ---------------------------------------------------------------------------
+void matvec(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int nrhs, double* Y,
+            int64_t ldy) {
+  hipStream_t s = ctx->stream;
+  DescArena& ar = ctx->arena;
+  ar.s = s;
+  const int shape = nrhs > 16 ? 0 : 1;
+  if (!H->mv_ready) {
+    H->hat_off.assign(H->nn, 0);
+    int64_t o = 0;
+    for (int q = 0; q < H->nn; ++q) {
+      H->hat_off[q] = o;
+      o += H->rank[q];
+    }
+    H->hat_total = o;
+    H->mv_ready = true;
+  }
+  const int64_t N = H->N;
+  DevArray<double> xt, yt, xh, yh;
+  xt.alloc(N * nrhs, nullptr);
+  yt.alloc(N * nrhs, nullptr);
+  xh.alloc(std::max<int64_t>(H->hat_total, 1) * nrhs, nullptr);
+  yh.alloc(std::max<int64_t>(H->hat_total, 1) * nrhs, nullptr);
+  const double* d = H->data.p;
+  auto hx = [&](int q) { return xh.p + H->hat_off[q] * nrhs; };
+  auto hy = [&](int q) { return yh.p + H->hat_off[q] * nrhs; };
+  launch_gather_rows<double, double>(xt.p, N, X, ldx, H->perm_d.p, N, nrhs, s);
+  const int L = H->L;
+  if (H->top >= 0) {
+    // leaves: xh = U^T x
+    GemmBatch<double> gb(shape);
+    for (int q = H->lp[L]; q < H->nn; ++q) {
+      if (!H->rank[q]) continue;
+      gb.out(hx(q), H->rank[q], 0, H->rank[q], 0, nrhs, 1.0, 0.0);
+      gb.con(d + H->offU[q], H->size(q), 1, xt.p + H->ib[q], N, 0, H->size(q));
+      gb.end();
+    }
+    gb.launch(ar, s);
+    for (int l = L - 1; l >= H->top; --l) {
+      for (int q = H->lp[l]; q < H->lp[l + 1]; ++q) {
+        if (!H->rank[q]) continue;
+        gb.out(hx(q), H->rank[q], 0, H->rank[q], 0, nrhs, 1.0, 0.0);
+        for (int c = H->cp[q]; c < H->cp[q + 1]; ++c)
+          if (H->rank[c]) gb.con(d + H->offE[c], H->rank[c], 1, hx(c), H->rank[c], 0, H->rank[c]);
+        gb.end();
+      }
+      gb.launch(ar, s);
+    }
+    // couplings
+    for (int q = 0; q < H->nn; ++q) {
+      if (!H->rank[q]) continue;
+      gb.out(hy(q), H->rank[q], 0, H->rank[q], 0, nrhs, 1.0, 0.0);
+      for (int64_t e = H->far_ptr[q]; e < H->far_ptr[q + 1]; ++e) {
+        const int j = H->far_col[e];
+        if (H->rank[j]) gb.con(d + H->offS[e], H->rank[q], 0, hx(j), H->rank[j], 0, H->rank[j]);
+      }
+      gb.end();
+    }
+    gb.launch(ar, s);
+    for (int l = H->top + 1; l <= L; ++l) {
+      for (int q = H->lp[l]; q < H->lp[l + 1]; ++q) {
+        const int p = H->parent[q];
+        if (!H->rank[q] || !H->rank[p]) continue;
+        gb.out(hy(q), H->rank[q], 0, H->rank[q], 0, nrhs, 1.0, 1.0);
+        gb.con(d + H->offE[q], H->rank[q], 0, hy(p), H->rank[p], 0, H->rank[p]);
+        gb.end();
+      }
+      gb.launch(ar, s);
+    }
+  }
+  {
+    GemmBatch<double> gb(shape);
+    for (int q = H->lp[L]; q < H->nn; ++q) {
+      gb.out(yt.p + H->ib[q], N, 0, H->size(q), 0, nrhs, 1.0, 0.0);
+      if (H->top >= 0 && H->rank[q])
+        gb.con(d + H->offU[q], H->size(q), 0, hy(q), H->rank[q], 0, H->rank[q]);
+      for (int64_t e = H->near_ptr[q]; e < H->near_ptr[q + 1]; ++e) {
+        const int j = H->near_col[e];
+        gb.con(d + H->offD[e], H->size(q), 0, xt.p + H->ib[j], N, 0, H->size(j));
+      }
+      gb.end();
+    }
+    gb.launch(ar, s);
+  }
+  launch_scatter_rows<double, double>(Y, ldy, yt.p, N, H->perm_d.p, N, nrhs, s);
+  H2_HIP(hipStreamSynchronize(s));
+  ar.reset();
+}
+
+// ---------------------------------------------------------------------------
+// GMRES-IR: residuals, Krylov basis and updates in FP64; the preconditioner is
+// the factor's solve (FP32 or FP64).  Columns share the iteration.
+// ---------------------------------------------------------------------------
+bool solve_ir(h2_context_s* ctx, h2_matrix_s* H, h2_factor_s* F, const double* B, int64_t ldb,
+              int nrhs, double* X, int64_t ldx, const h2_ir_opts& o, h2_ir_report& rep) {
+  hipStream_t s = ctx->stream;
+  const int64_t N = H->N;
+  const int m = o.restart;
+  auto precond = [&](const double* in, double* out) {
+    solve(ctx, {F}, {in}, {N}, nrhs, {out}, {N});
+  };
+  auto A = [&](const double* in, double* out) { matvec(ctx, H, in, in == X ? ldx : N, nrhs, out, N); };
+  DevArray<double> R, T1, Vb, coef, nrm;
+  R.alloc(N * nrhs, nullptr);
+  T1.alloc(N * nrhs, nullptr);
+  Vb.alloc((int64_t)(m + 1) * N * nrhs, nullptr);
+  coef.alloc((int64_t)(m + 2) * nrhs, nullptr);
+  nrm.alloc(2 * (int64_t)nrhs, nullptr);
+  const int64_t vs = N * nrhs;  // stride between basis vectors
+  std::vector<double> bnorm(nrhs), h(nrhs), hcol((size_t)(m + 1) * nrhs);
+  // x0 = M^{-1} b
+  DevArray<double> Bc;
+  Bc.alloc(N * nrhs, nullptr);
+  H2_HIP(hipMemcpy2DAsync(Bc.p, N * 8, B, ldb * 8, N * 8, nrhs, hipMemcpyDeviceToDevice, s));
+  precond(Bc.p, T1.p);
+  H2_HIP(hipMemcpy2DAsync(X, ldx * 8, T1.p, N * 8, N * 8, nrhs, hipMemcpyDeviceToDevice, s));
+  launch_colnorms(Bc.p, N, N, nrhs, nrm.p, s);
+  H2_HIP(hipMemcpyAsync(bnorm.data(), nrm.p, 8 * nrhs, hipMemcpyDeviceToHost, s));
+  H2_HIP(hipStreamSynchronize(s));
+  rep = h2_ir_report{};
+  auto residual = [&]() {
+    // R = B - A X; returns max backward error
+    A(X, T1.p);
+    launch_sub(R.p, N, Bc.p, N, T1.p, N, N, nrhs, s);
+    launch_colnorms(R.p, N, N, nrhs, nrm.p, s);
+    std::vector<double> rn(nrhs);
+    H2_HIP(hipMemcpyAsync(rn.data(), nrm.p, 8 * nrhs, hipMemcpyDeviceToHost, s));
+    H2_HIP(hipStreamSynchronize(s));
+    double e = 0;
+    for (int c = 0; c < nrhs; ++c) e = std::max(e, bnorm[c] > 0 ? rn[c] / bnorm[c] : rn[c]);
+    return e;
+  };
+  double eb = residual();
+  int outer = 0;
+  while (eb > o.target_bkwd && outer < o.max_outer) {
+    ++outer;
+    // z = M^{-1} r, beta = ||z||, v0 = z / beta
+    precond(R.p, T1.p);
+    launch_colnorms(T1.p, N, N, nrhs, nrm.p, s);
+    std::vector<double> beta(nrhs);
+    H2_HIP(hipMemcpyAsync(beta.data(), nrm.p, 8 * nrhs, hipMemcpyDeviceToHost, s));
+    launch_scale_cols(Vb.p, N, T1.p, N, nrm.p, N, nrhs, 1, s);
+    H2_HIP(hipStreamSynchronize(s));
+    // per-column Hessenberg / Givens state
+    std::vector<std::vector<double>> Hh(nrhs, std::vector<double>((size_t)(m + 1) * m, 0.0));
+    std::vector<std::vector<double>> g(nrhs, std::vector<double>(m + 1, 0.0)), cs(nrhs), sn(nrhs);
+    for (int c = 0; c < nrhs; ++c) {
+      g[c][0] = beta[c];
+      cs[c].assign(m, 0);
+      sn[c].assign(m, 0);
+    }
+    int kdone = 0;
+    for (int k = 0; k < m; ++k) {
+      double* vk = Vb.p + k * vs;
+      double* w = Vb.p + (k + 1) * vs;
+      A(vk, T1.p);
+      precond(T1.p, w);
+      // CGS2 against v_0..v_k
+      std::vector<double> hk((size_t)(k + 1) * nrhs, 0.0), tmp((size_t)(k + 1) * nrhs);
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_dots(Vb.p, N, vs, k + 1, w, N, N, nrhs, coef.p, s);
+        launch_update(w, N, Vb.p, N, vs, k + 1, coef.p, -1.0, N, nrhs, s);
+        H2_HIP(hipMemcpyAsync(tmp.data(), coef.p, 8 * (k + 1) * nrhs, hipMemcpyDeviceToHost, s));
+        H2_HIP(hipStreamSynchronize(s));
+        for (size_t e = 0; e < tmp.size(); ++e) hk[e] += tmp[e];
+      }
+      launch_colnorms(w, N, N, nrhs, nrm.p, s);
+      std::vector<double> hn(nrhs);
+      H2_HIP(hipMemcpyAsync(hn.data(), nrm.p, 8 * nrhs, hipMemcpyDeviceToHost, s));
+      launch_scale_cols(w, N, w, N, nrm.p, N, nrhs, 1, s);
+      H2_HIP(hipStreamSynchronize(s));
+      bool all_done = true;
+      for (int c = 0; c < nrhs; ++c) {
+        double* col = &Hh[c][(size_t)k * (m + 1)];
+        for (int i = 0; i <= k; ++i) col[i] = hk[i + (size_t)c * (k + 1)];
+        col[k + 1] = hn[c];
+        for (int i = 0; i < k; ++i) {
+          const double a = col[i], b = col[i + 1];
+          col[i] = cs[c][i] * a + sn[c][i] * b;
+          col[i + 1] = -sn[c][i] * a + cs[c][i] * b;
+        }
+        const double a = col[k], b = col[k + 1];
+        const double den = std::hypot(a, b);
+        cs[c][k] = den == 0 ? 1.0 : a / den;
+        sn[c][k] = den == 0 ? 0.0 : b / den;
+        col[k] = cs[c][k] * a + sn[c][k] * b;
+        col[k + 1] = 0;
+        g[c][k + 1] = -sn[c][k] * g[c][k];
+        g[c][k] = cs[c][k] * g[c][k];
+        if (std::fabs(g[c][k + 1]) > o.inner_rtol * beta[c] && hn[c] > 0) all_done = false;
+      }
+      kdone = k + 1;
+      rep.inner_iterations++;
+      if (all_done) break;
+    }
+    // back substitution per column, then x += V y
+    std::vector<double> y((size_t)kdone * nrhs, 0.0);
+    for (int c = 0; c < nrhs; ++c) {
+      for (int i = kdone - 1; i >= 0; --i) {
+        double acc = g[c][i];
+        for (int j = i + 1; j < kdone; ++j) acc -= Hh[c][(size_t)j * (m + 1) + i] * y[j + (size_t)c * kdone];
+        const double dii = Hh[c][(size_t)i * (m + 1) + i];
+        y[i + (size_t)c * kdone] = dii != 0 ? acc / dii : 0.0;
+      }
+    }
+    H2_HIP(hipMemcpyAsync(coef.p, y.data(), 8 * y.size(), hipMemcpyHostToDevice, s));
+    launch_update(X, ldx, Vb.p, N, vs, kdone, coef.p, 1.0, N, nrhs, s);
+    H2_HIP(hipStreamSynchronize(s));
+    eb = residual();
+  }
+  rep.outer_iterations = outer;
+  rep.max_bkwd = eb;
+  return eb <= o.target_bkwd;
+}
+
+}  // namespace h2drv

@@ -1,0 +1,132 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Integer outputs (per-level sizes, augmented ranks, colours, fill pattern,
+order of the dense top block) must be identical; FP64 products and solutions
+must agree to the stated tolerances; the FP32 factor with FP64 GMRES-IR must
+reach a backward error of 1e-12 measured with the oracle's FP64 product.
+"""
+import numpy as np
+import pytest
+
+from conftest import EXP3D_4096, NOFAR_256, oracle_factor, oracle_matrix, workload
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("exp2d_1024", None),
+    ("exp2d_4096", None),
+    ("exp3d_4096", EXP3D_4096),
+    ("nofar_256", NOFAR_256),
+    ("gauss2d_3000", None),
+]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2509_11152_amd as h2
+
+    return h2
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context(0)
+
+
+_MATS = {}
+
+
+def gpu_matrix(lib, ctx, name, spec):
+    if name not in _MATS:
+        _MATS[name] = lib.Matrix(ctx, workload(name, spec)["blob"])
+    return _MATS[name]
+
+
+def _cuda(a):
+    import torch
+
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("name,spec", CASES)
+def test_matvec(lib, ctx, name, spec):
+    from oracle import h2ops
+
+    print(f"[gpu] matvec {name}", flush=True)
+    H = gpu_matrix(lib, ctx, name, spec)
+    Ho = oracle_matrix(name, spec)
+    X = np.random.default_rng(3).standard_normal((Ho.N, 5))
+    Y = H.matvec(_cuda(X)).cpu().numpy()
+    Yo = h2ops.matvec(Ho, X)
+    assert np.linalg.norm(Y - Yo) <= 1e-13 * np.linalg.norm(Yo)
+
+
+@pytest.mark.parametrize("name,spec", CASES)
+def test_factor_integer_outputs(lib, ctx, name, spec):
+    print(f"[gpu] factor integers {name}", flush=True)
+    H = gpu_matrix(lib, ctx, name, spec)
+    tol = workload(name, spec)["spec"]["tol"]
+    F = lib.Factor(ctx, H, tol)
+    Fo = oracle_factor(name, spec=spec)
+    assert F.levels() == [Lf.level for Lf in Fo.levels]
+    for Lf in Fo.levels:
+        lev = Lf.level
+        assert F.ints(lev, lib.INT_SIZES).tolist() == [Lf.n[q] for q in Lf.nodes]
+        assert F.ints(lev, lib.INT_COLORS).tolist() == [Lf.color[q] for q in Lf.nodes]
+        fill = F.ints(lev, lib.INT_FILL).reshape(-1, 2)
+        assert [tuple(x) for x in fill.tolist()] == Lf.fpat
+        assert F.ints(lev, lib.INT_RANKS).tolist() == [Lf.kt[q] for q in Lf.nodes]
+    assert int(F.ints(0, lib.INT_NTOP)[0]) == Fo.n_top
+
+
+@pytest.mark.parametrize("name,spec", CASES)
+def test_solve_fp64(lib, ctx, name, spec):
+    from oracle import factor as of
+    from oracle import h2ops
+
+    print(f"[gpu] solve fp64 {name}", flush=True)
+    w = workload(name, spec)
+    H = gpu_matrix(lib, ctx, name, spec)
+    Ho = oracle_matrix(name, spec)
+    F = lib.Factor(ctx, H, w["spec"]["tol"])
+    B = w["B"]
+    X = F.solve(_cuda(B)).cpu().numpy()
+    Xo = of.solve(oracle_factor(name, spec=spec), B)
+    rel = np.linalg.norm(X - Xo) / np.linalg.norm(Xo)
+    res = np.linalg.norm(h2ops.matvec(Ho, X - Xo)) / np.linalg.norm(B)
+    print(f"[gpu] {name}: |X - Xo| / |Xo| = {rel:.3e}, |A (X - Xo)| / |B| = {res:.3e}", flush=True)
+    assert rel <= 1e-10 and res <= 1e-10
+
+
+@pytest.mark.parametrize("name,spec", [("exp2d_4096", None), ("exp3d_4096", EXP3D_4096)])
+def test_fp32_factor_with_fp64_refinement(lib, ctx, name, spec):
+    from oracle import h2ops
+
+    print(f"[gpu] fp32 + GMRES-IR {name}", flush=True)
+    w = workload(name, spec)
+    H = gpu_matrix(lib, ctx, name, spec)
+    Ho = oracle_matrix(name, spec)
+    F32 = lib.Factor(ctx, H, w["spec"]["tol"], lib.H2_PREC_FP32)
+    X, rep = lib.solve_ir(ctx, H, F32, _cuda(w["B"]), target=1e-12)
+    X = X.cpu().numpy()
+    eb = h2ops.backward_error(Ho, X, w["B"])
+    assert rep["converged"] and eb.max() <= 1e-12, (rep, eb)
+
+
+def test_batched_equals_single(lib, ctx):
+    print("[gpu] batched factor/solve", flush=True)
+    names = [("exp2d_1024", None), ("exp3d_4096", EXP3D_4096), ("gauss2d_3000", None)]
+    Hs = [gpu_matrix(lib, ctx, n, s) for n, s in names]
+    tol = 1e-8
+    Fb = lib.factor_batched(ctx, Hs, tol)
+    Bs = [_cuda(workload(n, s)["B"][:, :2]) for n, s in names]
+    Xb = lib.solve_batched(ctx, Fb, Bs)
+    for (n, s), H, F, B, X in zip(names, Hs, Fb, Bs, Xb):
+        Fs = lib.Factor(ctx, H, tol)
+        Xs = Fs.solve(B)
+        for lev in Fs.levels():
+            assert (F.ints(lev, lib.INT_RANKS) == Fs.ints(lev, lib.INT_RANKS)).all()
+        assert np.array_equal(X.cpu().numpy(), Xs.cpu().numpy()), n

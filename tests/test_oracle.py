@@ -38,10 +38,15 @@ def test_matvec_against_kernel_matrix(name, spec):
     assert np.linalg.norm(AH @ X - Y) <= 1e-13 * np.linalg.norm(Y)
 
 
-def test_factor_without_truncation_is_dense_solve():
-    H = oracle_matrix("exp2d_1024")
-    B = workload("exp2d_1024")["B"]
+@pytest.mark.parametrize("name,spec", [("exp2d_1024", None), ("exp2d_4096", None),
+                                       ("exp3d_4096", EXP3D_4096)])
+def test_factor_without_truncation_is_dense_solve(name, spec):
+    """With eps_lu -> 0 nothing is truncated and every level (one level for the
+    first case, two for the others) is an exact block elimination."""
+    H = oracle_matrix(name, spec)
+    B = workload(name, spec)["B"]
     Fz = of.factor(H, 1e-15)
+    assert len(Fz.levels) >= 1
     X = of.solve(Fz, B)
     Xd = np.linalg.solve(h2ops.dense(H), B)
     assert np.linalg.norm(X - Xd) <= 1e-9 * np.linalg.norm(Xd)
