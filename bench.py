@@ -39,6 +39,42 @@ def parse():
     return p.parse_args()
 
 
+PHASES = ["augment", "project", "lu_multipliers", "schur", "close_out", "top_lu"]
+KERNEL_OF = {"augment": "k_augment", "project": "k_strip", "lu_multipliers": "k_lu + k_trsm",
+             "schur": "k_gemm (64x64 MFMA tiles)", "close_out": "k_copy",
+             "top_lu": "k_panel_lu + k_laswp + k_trsm_block + k_gemm"}
+
+
+def roofline(st, dt):
+    """Per-phase achieved rate from the library's algorithmic counts and the
+    device time of the phase (HIP events around its launches)."""
+    peak_f = PEAK[dt]
+    out = {}
+    best = None
+    for i, name in enumerate(PHASES):
+        t = st["time_ms"][i] * 1e-3
+        fl, by = st["phase_flops"][i], st["phase_bytes"][i]
+        if t <= 0 or (fl <= 0 and by <= 0):
+            continue
+        f_time = fl / (peak_f * 1e12)
+        b_time = by / (HBM_PEAK * 1e9)
+        if name == "augment":
+            bound, ach, peak, unit = "alu", fl / t / 1e12, peak_f, "TFLOP/s"
+        elif f_time >= b_time:
+            bound, ach, peak, unit = "mfma", fl / t / 1e12, peak_f, "TFLOP/s"
+        else:
+            bound, ach, peak, unit = "hbm", by / t / 1e9, HBM_PEAK, "GB/s"
+        out[name] = {"kernel": KERNEL_OF[name], "ms": t * 1e3, "launches": st["launches"][i],
+                     "flops": fl, "bytes": by, "bound": bound, "achieved": ach, "peak": peak,
+                     "unit": unit, "frac": ach / peak}
+        if best is None or t > out[best]["ms"] * 1e-3:
+            best = name
+    r = out[best]
+    roof = {"bound": r["bound"], "achieved": r["achieved"], "peak": r["peak"], "unit": r["unit"],
+            "frac": r["frac"], "traffic": None, "kernel": r["kernel"], "phase": best}
+    return roof, out
+
+
 def cpu_baseline(spec_name):
     """The oracle (single-threaded numpy FP64) on a bounded sample of the same
     recipe, extrapolated linearly in N (the method is O(N) in time)."""
@@ -148,21 +184,8 @@ def main():
     s64 = F64.stats()
     med = lambda v: float(np.median(v))
     value = med(t32)
-    # roofline of the dominant kernel class: the Schur-complement MFMA GEMM
-    # (phase 3); algorithmic flops per launch = its share of the flop model
-    sch_ms = s32["time_ms"][3]
-    roof = {
-        "bound": "mfma",
-        "achieved": None,
-        "peak": PEAK["f32"],
-        "unit": "TFLOP/s",
-        "frac": None,
-        "traffic": None,
-    }
-    if "schur_flops" in s32 and sch_ms > 0:
-        ach = s32["schur_flops"] / (sch_ms * 1e-3) / 1e12
-        roof["achieved"] = ach
-        roof["frac"] = ach / roof["peak"]
+    roof, phases = roofline(s32, "f32")
+    _, phases64 = roofline(s64, "f64")
     out = {
         "metric": METRIC,
         "value": value,
@@ -189,6 +212,8 @@ def main():
         "fp64_plain": {"total_s": med(t64p), "bkwd": eb64p},
         "n_top": s32["n_top"],
         "roofline": roof,
+        "phases_fp32": phases,
+        "phases_fp64": phases64,
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")

@@ -266,7 +266,10 @@ def construct(pts, kernel, leaf_size=64, tree_kind="kd", eta=0.7, adm_kind=0,
             Z = TE.reshape(Lv.n, arity * Lc.T.shape[1], Lv.k1)
             Lv.Z = Z
             M = torch.bmm(Z, Lv.W)
-        Pm, sv, _ = torch.linalg.svd(M, full_matrices=False)
+        # small batched SVDs run on the host (LAPACK); the device path of some
+        # builds fails to converge on strongly graded spectra
+        Pm, sv, _ = torch.linalg.svd(M.cpu(), full_matrices=False)
+        Pm, sv = Pm.to(dev), sv.to(dev)
         k2 = (sv > thr).sum(1).cpu().numpy()
         Lv.k2 = k2
         k2max = max(int(k2.max()), 0)

@@ -186,6 +186,9 @@ typedef struct {
   double time_ms[8];       /* device time per phase of the last h2_factor:
                               0 augment, 1 project, 2 LU+multipliers, 3 Schur,
                               4 close-out, 5 top LU, 6 host planning, 7 total */
+  double phase_flops[8];   /* algorithmic flops per phase (same indices) */
+  double phase_bytes[8];   /* algorithmic HBM bytes per phase (each operand once) */
+  int64_t launches[8];     /* kernel launches per phase */
 } h2_stats;
 h2_status h2_factor_get_stats(h2_factor_t F, h2_stats* stats);
 

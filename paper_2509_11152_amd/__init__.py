@@ -47,7 +47,9 @@ class _Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("max_colors", ctypes.c_int32),
                 ("n_top", ctypes.c_int64), ("factor_bytes", ctypes.c_int64),
                 ("peak_bytes", ctypes.c_int64), ("factor_flops", ctypes.c_double),
-                ("solve_flops_per_rhs", ctypes.c_double), ("time_ms", ctypes.c_double * 8)]
+                ("solve_flops_per_rhs", ctypes.c_double), ("time_ms", ctypes.c_double * 8),
+                ("phase_flops", ctypes.c_double * 8), ("phase_bytes", ctypes.c_double * 8),
+                ("launches", ctypes.c_int64 * 8)]
 
 
 class _Info(ctypes.Structure):
@@ -230,7 +232,9 @@ class Factor:
         _check(lib.h2_factor_get_stats(self.ptr, ctypes.byref(s)))
         return {"levels": s.levels, "max_colors": s.max_colors, "n_top": s.n_top,
                 "factor_bytes": s.factor_bytes, "peak_bytes": s.peak_bytes,
-                "factor_flops": s.factor_flops, "time_ms": list(s.time_ms)}
+                "factor_flops": s.factor_flops, "time_ms": list(s.time_ms),
+                "phase_flops": list(s.phase_flops), "phase_bytes": list(s.phase_bytes),
+                "launches": list(s.launches)}
 
     def __del__(self):
         try:

@@ -195,6 +195,8 @@ template <class T> struct Inst {
   DevArray<T> Fbuf;          // fill blocks of the current level
   DevArray<T> Vbuf;          // bases of the current level
   double flops = 0;
+  double pflops[8] = {0}, pbytes[8] = {0};
+  std::vector<int32_t> slot;  // planning scratch: pattern entry -> output of the colour
 };
 
 template <class T> int64_t copy_tiles(int rows, int cols) {
@@ -270,6 +272,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     return e;
   };
   double phase_ms[8] = {0};
+  int64_t launches[8] = {0};
 
   // ---- leaf level plans ----
   {
@@ -455,55 +458,75 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           }
         }
         // ---- Schur complement / fill-in targets, owner-computes ----
-        // target (j, k) collects every i of the colour with j, k in N(i)
-        std::vector<std::pair<int64_t, int>> inc;  // (target entry, contributor i)
-        for (int i : P.members[c])
-          for (int j : P.nb[i])
-            for (int k : P.nb[i]) inc.push_back({P.find(j, k), i});
-        std::sort(inc.begin(), inc.end());
-        for (size_t a = 0; a < inc.size();) {
-          size_t b = a;
-          while (b < inc.size() && inc[b].first == inc[a].first) ++b;
-          const int64_t e = inc[a].first;
-          // row of entry e
-          const int j = (int)(std::upper_bound(P.pptr.begin(), P.pptr.end(), e) - P.pptr.begin()) - 1;
-          const int k = P.pcol[e];
-          GOut<T> o{};
-          o.C = blk(e);
-          o.ldc = P.n[j];
-          o.m = P.n[j];
-          o.n = P.n[k];
-          o.m0d = wdyn(j, true);
-          o.m0s = 0;
-          o.m1d = -1;
-          o.n0d = wdyn(k, true);
-          o.n0s = 0;
-          o.cbeg = (int)cons.size();
-          for (size_t q = a; q < b; ++q) {
-            const int i = inc[q].second;
-            GCon<T> g{};
-            g.A = S.D.p + P.poff[P.find(j, i)];
-            g.lda = P.n[j];
-            g.B = S.D.p + P.poff[P.find(i, k)];
-            g.ldb = P.n[i];
-            g.k = P.n[i];
-            g.k0d = -1;
-            g.k0s = 0;
-            g.k1d = rb + i;
-            g.transA = 0;
-            cons.push_back(g);
+        // target (j, k) collects every i of the colour with j, k in N(i);
+        // outputs in first-touch order, contributors in ascending i
+        {
+          std::vector<int32_t>& slot = I->slot;
+          if ((int64_t)slot.size() < (int64_t)P.pcol.size()) slot.assign(P.pcol.size(), -1);
+          std::vector<int64_t> ent;      // output -> pattern entry
+          std::vector<int32_t> cnt;
+          std::vector<int64_t> incs;     // pattern entry of every incidence, in loop order
+          for (int i : P.members[c])
+            for (int j : P.nb[i])
+              for (int k : P.nb[i]) {
+                const int64_t e = P.find(j, k);
+                incs.push_back(e);
+                if (slot[e] < 0) {
+                  slot[e] = (int32_t)ent.size();
+                  ent.push_back(e);
+                  cnt.push_back(0);
+                }
+                cnt[slot[e]]++;
+              }
+          std::vector<int32_t> beg(ent.size() + 1, 0);
+          for (size_t o = 0; o < ent.size(); ++o) beg[o + 1] = beg[o] + cnt[o];
+          const int cbase = (int)cons.size();
+          cons.resize(cons.size() + incs.size());
+          std::vector<int32_t> fillpos(beg.begin(), beg.end() - 1);
+          size_t q = 0;
+          for (int i : P.members[c])
+            for (int j : P.nb[i])
+              for (int k : P.nb[i]) {
+                const int64_t e = incs[q++];
+                GCon<T>& g = cons[cbase + fillpos[slot[e]]++];
+                g = GCon<T>{};
+                g.A = S.D.p + P.poff[P.find(j, i)];
+                g.lda = P.n[j];
+                g.B = S.D.p + P.poff[P.find(i, k)];
+                g.ldb = P.n[i];
+                g.k = P.n[i];
+                g.k0d = -1;
+                g.k0s = 0;
+                g.k1d = rb + i;
+                g.transA = 0;
+              }
+          for (size_t o = 0; o < ent.size(); ++o) {
+            const int64_t e = ent[o];
+            slot[e] = -1;
+            const int j = (int)(std::upper_bound(P.pptr.begin(), P.pptr.end(), e) - P.pptr.begin()) - 1;
+            const int k = P.pcol[e];
+            GOut<T> ou{};
+            ou.C = blk(e);
+            ou.ldc = P.n[j];
+            ou.m = P.n[j];
+            ou.n = P.n[k];
+            ou.m0d = wdyn(j, true);
+            ou.m0s = 0;
+            ou.m1d = -1;
+            ou.n0d = wdyn(k, true);
+            ou.n0s = 0;
+            ou.cbeg = cbase + beg[o];
+            ou.cend = cbase + beg[o + 1];
+            ou.tm = (ou.m + 63) / 64;
+            ou.tn = (ou.n + 63) / 64;
+            ou.tile0 = gtiles;
+            ou.alpha = T(-1);
+            ou.beta = T(1);
+            if (ou.tm > 0 && ou.tn > 0) {
+              gtiles += (int64_t)ou.tm * ou.tn;
+              outs.push_back(ou);
+            }
           }
-          o.cend = (int)cons.size();
-          o.tm = (o.m + 63) / 64;
-          o.tn = (o.n + 63) / 64;
-          o.tile0 = gtiles;
-          o.alpha = T(-1);
-          o.beta = T(1);
-          if (o.tm > 0 && o.tn > 0) {
-            gtiles += (int64_t)o.tm * o.tn;
-            outs.push_back(o);
-          }
-          a = b;
         }
       }
       plan_ms += ms_since(tc);
@@ -513,13 +536,14 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       // by scaling? keep one threshold per launch group of equal norm.
       bool same_norm = true;
       for (auto* I : act) same_norm &= (I->H->norm2 == act[0]->H->norm2);
-      int maxn = 1;
+      int maxn = 1, maxn_aug = 1;
+      for (auto& t : aug) maxn_aug = std::max(maxn_aug, t.n);
       for (auto& t : sl) maxn = std::max(maxn, t.n);
       for (auto& t : sr) maxn = std::max(maxn, t.n);
       const int32_t* dyn = rdev.p;
       if (same_norm) {
         launch_augment<T>(ar.put(aug), (int)aug.size(), ar.put(refs), rdev.p, eps_fill,
-                          ctx->d_err, s);
+                          ctx->d_err, maxn_aug, s);
       } else {
         // launch per instance with its own threshold
         size_t pos = 0;
@@ -529,10 +553,14 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           const size_t cnt = P.members[c].size();
           std::vector<AugTask<T>> part(aug.begin() + pos, aug.begin() + pos + cnt);
           launch_augment<T>(ar.put(part), (int)cnt, ar.put(refs), rdev.p,
-                            T(tol * I->H->norm2), ctx->d_err, s);
+                            T(tol * I->H->norm2), ctx->d_err, maxn_aug, s);
           pos += cnt;
         }
       }
+      launches[0] += same_norm ? 1 : (int64_t)act.size();
+      launches[1] += 2;
+      launches[2] += 2;
+      launches[3] += 1;
       hipEvent_t e1 = new_event();
       H2_HIP(hipEventRecord(e1, s));
       marks.push_back({0, e1});
@@ -599,10 +627,24 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           // augmentation: projection of the fill row, Householder QR of its
           // transpose (f x n), SVD of the n x n factor (reported as 4 n^3)
           const double qr = f >= n ? 2 * f * n * n - 2 * n * n * n / 3 : 2 * n * f * f - 2 * f * f * f / 3;
-          I->flops += (4 * n * k * f + qr + 4 * n * n * n) * (f > 0);
-          I->flops += 2 * n * kt * kt - 2 * kt * kt * kt / 3 + 4 * (n * n * kt - n * kt * kt + kt * kt * kt / 3);
-          I->flops += 4 * n * n * n + 4 * n * n * Wn + 4 * n * kt * f;
-          I->flops += 2 * r * r * r / 3 + 2 * r * r * W + 2 * r * W * W;
+          const double f_aug = (4 * n * k * f + qr + 4 * n * n * n) * (f > 0) +
+                               2 * n * kt * kt - 2 * kt * kt * kt / 3 +
+                               4 * (n * n * kt - n * kt * kt + kt * kt * kt / 3);
+          const double f_proj = 4 * n * n * n + 4 * n * n * Wn + 4 * n * kt * f;
+          const double f_lu = 2 * r * r * r / 3 + 2 * r * r * W;
+          const double f_schur = 2 * r * W * W;
+          I->flops += f_aug + f_proj + f_lu + f_schur;
+          const double b = (double)sizeof(T);
+          I->pflops[0] += f_aug;
+          I->pflops[1] += f_proj;
+          I->pflops[2] += f_lu;
+          I->pflops[3] += f_schur;
+          // compulsory bytes: fill row read; projected blocks read + written;
+          // panels read; Schur targets read + written once per contributor group
+          I->pbytes[0] += b * (n * f + n * k + n * n);
+          I->pbytes[1] += b * 2 * (n * n + n * Wn + n * f);
+          I->pbytes[2] += b * (r * r + 2 * r * W);
+          I->pbytes[3] += b * (2 * r * W + 2 * W * W);
         }
       }
       const int lev = P.lev;
@@ -852,6 +894,9 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         }
       }
       I.flops += 2.0 * (double)n * n * n / 3.0;
+      I.pflops[5] += 2.0 * (double)n * n * n / 3.0;
+      I.pbytes[5] += 2.0 * sizeof(T) * (double)n * n;
+      launches[5] += 4 * ((n + 63) / 64);
     }
     hipEvent_t et1 = new_event();
     H2_HIP(hipEventRecord(et1, s));
@@ -869,7 +914,12 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
   for (auto e : evpool) (void)hipEventDestroy(e);
   for (auto& I : insts) {
     h2_factor_s* F = I.F;
-    for (int p = 0; p < 8; ++p) F->stats.time_ms[p] = phase_ms[p];
+    for (int p = 0; p < 8; ++p) {
+      F->stats.time_ms[p] = phase_ms[p];
+      F->stats.phase_flops[p] = I.pflops[p];
+      F->stats.phase_bytes[p] = I.pbytes[p];
+      F->stats.launches[p] = launches[p];
+    }
     F->stats.n_top = F->n_top;
     F->stats.factor_flops = I.flops;
     F->stats.factor_bytes = F->tr.cur;

@@ -106,6 +106,13 @@ constexpr int kStrip = 16;
 constexpr int kCopyTile = 4096;
 constexpr int kAugChunk = 64;
 
+// row chunk and LDS elements of the in-LDS reduction of the fill row of order n:
+// R (n x (n+1)), chunk (n x (chunk+1)), reflector parameters
+__host__ __device__ inline int aug_lds_chunk(int n) { return n <= 64 ? 64 : 16; }
+__host__ __device__ inline int64_t aug_lds_elems(int n) {
+  return (int64_t)n * (n + 1) + (int64_t)n * (aug_lds_chunk(n) + 1) + 8;
+}
+
 // scratch elements needed by one augmentation task of order n
 inline int64_t aug_work_elems(int n) {
   return (int64_t)(n + kAugChunk) * n + 3 * (int64_t)n * n + 4 * (int64_t)n + 64;
@@ -120,7 +127,7 @@ void launch_strip(const STask<T>* tasks, int ntasks, const int32_t* dyn, int64_t
                   int maxn, hipStream_t s);
 template <class T>
 void launch_augment(const AugTask<T>* tasks, int ntasks, const FillRef<T>* refs,
-                    int32_t* r, T eps_fill, int* err, hipStream_t s);
+                    int32_t* r, T eps_fill, int* err, int maxn, hipStream_t s);
 template <class T>
 void launch_lu(const LUTask<T>* tasks, int ntasks, const int32_t* dyn, int* err, hipStream_t s);
 template <class T>

@@ -311,11 +311,56 @@ __device__ void structured_qr(T* R, T* C, int ldw, int n, int m, T* red) {
   (void)red;
 }
 
+// Same reduction with R (ld n+1) and the chunk (ld ch+1) in LDS, one thread
+// per column (n <= blockDim).  The reflector of column j+1 is formed by its
+// owner right after its update in step j, so every column costs one barrier.
+template <class T>
+__device__ void structured_qr_lds(T* R, int ldr, T* C, int ldc, int n, int m, T* par) {
+  const int c = threadIdx.x;
+  // par[3*(j&1) + {0,1,2}] = tau, beta, scale of reflector j
+  auto reflector = [&](int j) {
+    T s2 = 0;
+    for (int t = 0; t < m; ++t) s2 += C[t + j * ldc] * C[t + j * ldc];
+    const T alpha = R[j + j * ldr];
+    T* q = par + 3 * (j & 1);
+    if (s2 == T(0)) {
+      q[0] = 0;
+      q[1] = alpha;
+      q[2] = 0;
+    } else {
+      const T nrm = sqrt(alpha * alpha + s2);
+      const T beta = alpha >= T(0) ? -nrm : nrm;
+      q[0] = (beta - alpha) / beta;
+      q[1] = beta;
+      q[2] = T(1) / (alpha - beta);
+    }
+  };
+  if (c == 0 && n > 0) reflector(0);
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const T* q = par + 3 * (j & 1);
+    const T tau = q[0], beta = q[1], scale = q[2];
+    if (c > j && c < n && tau != T(0)) {
+      T d = 0;
+      for (int t = 0; t < m; ++t) d += C[t + j * ldc] * C[t + c * ldc];
+      const T w = R[j + c * ldr] + scale * d;
+      const T tw = tau * w;
+      R[j + c * ldr] -= tw;
+      const T f = tw * scale;
+      for (int t = 0; t < m; ++t) C[t + c * ldc] -= f * C[t + j * ldc];
+    }
+    if (c == j + 1 && c < n) reflector(c);
+    if (c == j) R[j + j * ldr] = beta;
+    __syncthreads();
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ tasks,
                                                  const FillRef<T>* __restrict__ refs,
                                                  int32_t* __restrict__ rout, T eps_fill,
-                                                 int* err) {
+                                                 int* err, int lds_elems) {
+  extern __shared__ char aug_smem[];
   const AugTask<T> tk = tasks[blockIdx.x];
   const int n = tk.n, k = tk.k;
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -337,31 +382,68 @@ __global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ 
   T* Q = tk.Q;
 
   // ---- 1. R of the fill row ----
+  const int ch_lds = aug_lds_chunk(n);
+  const bool use_lds = n <= nthr && aug_lds_elems(n) <= lds_elems;
   for (int e = tid; e < n * n; e += nthr) R[(e % n) + (int64_t)(e / n) * ldw] = 0;
-  __syncthreads();
-  int fill = 0;
-  for (int f = tk.fbeg; f < tk.fend; ++f) {
-    const FillRef<T> fr = refs[f];
-    int c = fr.d0 >= 0 ? rout[fr.d0] : 0;
-    // rout doubles as the level's r array: processed neighbours were written
-    // by earlier launches of this level.
-    while (c < fr.ncols) {
-      const int take = min(kAugChunk - fill, fr.ncols - c);
-      for (int e = tid; e < take * n; e += nthr) {
-        const int tt = e / n, col = e % n;
-        C[(fill + tt) + (int64_t)col * ldw] = fr.F[col + (int64_t)(c + tt) * fr.ld];
-      }
-      fill += take;
-      c += take;
-      __syncthreads();
-      if (fill == kAugChunk) {
-        structured_qr(R, C, ldw, n, fill, red);
-        fill = 0;
+  if (use_lds) {
+    T* Rs = reinterpret_cast<T*>(aug_smem);
+    const int ldr = n + 1, ldc = ch_lds + 1;
+    T* Cs = Rs + (int64_t)n * ldr;
+    T* par = Cs + (int64_t)n * ldc;
+    for (int e = tid; e < n * ldr; e += nthr) Rs[e] = 0;
+    __syncthreads();
+    int fill = 0;
+    for (int f = tk.fbeg; f < tk.fend; ++f) {
+      const FillRef<T> fr = refs[f];
+      int c = fr.d0 >= 0 ? rout[fr.d0] : 0;
+      while (c < fr.ncols) {
+        const int take = min(ch_lds - fill, fr.ncols - c);
+        for (int e = tid; e < take * n; e += nthr) {
+          const int tt = e / n, col = e % n;
+          Cs[(fill + tt) + col * ldc] = fr.F[col + (int64_t)(c + tt) * fr.ld];
+        }
+        fill += take;
+        c += take;
+        __syncthreads();
+        if (fill == ch_lds) {
+          structured_qr_lds(Rs, ldr, Cs, ldc, n, fill, par);
+          fill = 0;
+        }
       }
     }
+    if (fill > 0) structured_qr_lds(Rs, ldr, Cs, ldc, n, fill, par);
+    __syncthreads();
+    for (int e = tid; e < n * n; e += nthr) {
+      const int row = e % n, col = e / n;
+      R[row + (int64_t)col * ldw] = row <= col ? Rs[row + col * ldr] : T(0);
+    }
+    __syncthreads();
+  } else {
+    __syncthreads();
+    int fill = 0;
+    for (int f = tk.fbeg; f < tk.fend; ++f) {
+      const FillRef<T> fr = refs[f];
+      int c = fr.d0 >= 0 ? rout[fr.d0] : 0;
+      // rout doubles as the level's r array: processed neighbours were written
+      // by earlier launches of this level.
+      while (c < fr.ncols) {
+        const int take = min(kAugChunk - fill, fr.ncols - c);
+        for (int e = tid; e < take * n; e += nthr) {
+          const int tt = e / n, col = e % n;
+          C[(fill + tt) + (int64_t)col * ldw] = fr.F[col + (int64_t)(c + tt) * fr.ld];
+        }
+        fill += take;
+        c += take;
+        __syncthreads();
+        if (fill == kAugChunk) {
+          structured_qr(R, C, ldw, n, fill, red);
+          fill = 0;
+        }
+      }
+    }
+    if (fill > 0) structured_qr(R, C, ldw, n, fill, red);
+    __syncthreads();
   }
-  if (fill > 0) structured_qr(R, C, ldw, n, fill, red);
-  __syncthreads();
 
   // ---- 2. M = R (I - V V^T) = G^T, G = (I - V V^T) R^T ----
   // Hm[c + a*n] = (R V)[c, a]   (n x k)
@@ -577,9 +659,22 @@ __global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ 
 
 template <class T>
 void launch_augment(const AugTask<T>* tasks, int ntasks, const FillRef<T>* refs, int32_t* r,
-                    T eps_fill, int* err, hipStream_t s) {
+                    T eps_fill, int* err, int maxn, hipStream_t s) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(k_augment<T>, dim3(ntasks), dim3(256), 0, s, tasks, refs, r, eps_fill, err);
+  // LDS for the largest cluster of the launch that fits (R plus a row chunk)
+  const int64_t cap = (150 * 1024) / (int64_t)sizeof(T);
+  int64_t need = aug_lds_elems(std::min(maxn, 64));
+  if (maxn > 64 && aug_lds_elems(maxn) <= cap) need = std::max(need, aug_lds_elems(maxn));
+  if (need > cap) need = 0;
+  const int lds_bytes = (int)(need * (int64_t)sizeof(T));
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_augment<T>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_augment<T>, dim3(ntasks), dim3(256), lds_bytes, s, tasks, refs, r,
+                     eps_fill, err, (int)(lds_bytes / sizeof(T)));
 }
 
 // ---------------------------------------------------------------------------
@@ -1049,7 +1144,7 @@ void launch_check_finite(const double* X, int64_t n, int* flag, hipStream_t s) {
   template void launch_strip<T>(const STask<T>*, int, const int32_t*, int64_t, int,           \
                                 hipStream_t);                                                 \
   template void launch_augment<T>(const AugTask<T>*, int, const FillRef<T>*, int32_t*, T,     \
-                                  int*, hipStream_t);                                         \
+                                  int*, int, hipStream_t);                                    \
   template void launch_lu<T>(const LUTask<T>*, int, const int32_t*, int*, hipStream_t);       \
   template void launch_trsm<T>(const TrsmTask<T>*, int, const int32_t*, hipStream_t);         \
   template void launch_copy<T, double>(const CTask<T, double>*, int, int64_t, hipStream_t);   \
