@@ -252,6 +252,41 @@ template <class T> void alloc_level(Inst<T>& I, LevelPlan& P) {
 
 }  // namespace
 
+// Reduction groups of a fill row: consecutive fill blocks holding at most
+// `cap` rows of Y^T together (at least one block each; one empty group for an
+// empty fill row).
+static std::vector<std::pair<int, int>> rf_groups(const std::vector<int>& rows, int cap) {
+  std::vector<std::pair<int, int>> g;
+  if (rows.empty()) {
+    g.push_back({0, 0});
+    return g;
+  }
+  size_t a = 0;
+  while (a < rows.size()) {
+    size_t b = a;
+    int64_t acc = 0;
+    while (b < rows.size() && (b == a || acc + rows[b] <= cap)) acc += rows[b++];
+    g.push_back({(int)a, (int)b});
+    a = b;
+  }
+  return g;
+}
+
+// Scratch elements of the tall-skinny QR of a fill row of order n whose
+// blocks have the given widths: one n x n factor per group of every stage
+// (plus the global-memory reduction space when R does not fit in LDS).
+template <class T> static int64_t rf_scratch(int n, std::vector<int> rows) {
+  const int cap = rf_group_rows(n);
+  const int64_t per = (int64_t)n * n + (rf_in_lds<T>(n) ? 0 : (int64_t)(n + kAugChunk) * n);
+  int64_t tot = 0;
+  for (;;) {
+    const size_t g = rf_groups(rows, cap).size();
+    tot += (int64_t)g * per;
+    if (g == 1) return tot;
+    rows.assign(g, n);
+  }
+}
+
 template <class T>
 static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double tol) {
   hipStream_t s = ctx->stream;
@@ -331,8 +366,13 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       int64_t w = 0;
       for (auto* I : act) {
         LevelPlan& P = I->F->plans[I->li];
-        if (c < P.ncolors)
-          for (int i : P.members[c]) w += aug_work_elems(P.n[i]);
+        if (c >= P.ncolors) continue;
+        for (int i : P.members[c]) {
+          std::vector<int> rows;
+          for (int64_t e = P.pptr[i]; e < P.pptr[i + 1]; ++e)
+            if (P.isF[e] && P.firstc[e] < c) rows.push_back(P.n[P.pcol[e]]);
+          w += aug_work_elems(P.n[i]) + rf_scratch<T>(P.n[i], rows);
+        }
       }
       wmax = std::max(wmax, w);
     }
@@ -346,7 +386,9 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     for (int c = 0; c < maxc; ++c) {
       const auto tc = std::chrono::steady_clock::now();
       std::vector<AugTask<T>> aug;
-      std::vector<FillRef<T>> refs;
+      std::vector<std::vector<RTask<T>>> rst;       // per stage of the fill-row QR
+      std::vector<std::vector<FillRef<T>>> rrefs;
+      std::vector<int> rmaxn;
       std::vector<STask<T>> sl, sr;
       int64_t nsl = 0, nsr = 0;
       std::vector<LUTask<T>> lus;
@@ -375,7 +417,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           woff += aug_work_elems(ni);
           at.n = ni;
           at.k = P.k[i];
-          at.fbeg = (int)refs.size();
+          std::vector<FillRef<T>> cur;
           for (int64_t e = P.pptr[i]; e < P.pptr[i + 1]; ++e) {
             if (!P.isF[e] || P.firstc[e] >= c) continue;  // zero until a later colour
             const int j = P.pcol[e];
@@ -384,9 +426,48 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
             fr.ld = ni;
             fr.ncols = P.n[j];
             fr.d0 = wdyn(j, false);
-            refs.push_back(fr);
+            cur.push_back(fr);
           }
-          at.fend = (int)refs.size();
+          // stages of the tall-skinny QR: groups of fill blocks, then groups of
+          // the previous stage's factors, until one factor remains
+          const bool rf_glob = !rf_in_lds<T>(ni);
+          for (size_t st = 0;; ++st) {
+            std::vector<int> rows(cur.size());
+            for (size_t q = 0; q < cur.size(); ++q) rows[q] = cur[q].ncols;
+            const auto groups = rf_groups(rows, rf_group_rows(ni));
+            if (rst.size() <= st) {
+              rst.emplace_back();
+              rrefs.emplace_back();
+              rmaxn.push_back(1);
+            }
+            std::vector<FillRef<T>> next;
+            for (const auto& g : groups) {
+              RTask<T> t{};
+              t.out = work.p + woff;
+              woff += (int64_t)ni * ni;
+              if (rf_glob) {
+                t.work = work.p + woff;
+                woff += (int64_t)(ni + kAugChunk) * ni;
+              }
+              t.n = ni;
+              t.fbeg = (int)rrefs[st].size();
+              for (int q = g.first; q < g.second; ++q) rrefs[st].push_back(cur[q]);
+              t.fend = (int)rrefs[st].size();
+              rst[st].push_back(t);
+              rmaxn[st] = std::max(rmaxn[st], ni);
+              FillRef<T> o{};
+              o.F = t.out;
+              o.ld = ni;
+              o.ncols = ni;
+              o.d0 = -1;
+              next.push_back(o);
+            }
+            if (groups.size() == 1) {
+              at.Rt = next[0].F;
+              break;
+            }
+            cur.swap(next);
+          }
           at.ri = rb + i;
           aug.push_back(at);
           // ---- projection: row i (left, Q^T X) and column i (right, X Q) ----
@@ -541,9 +622,12 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       for (auto& t : sl) maxn = std::max(maxn, t.n);
       for (auto& t : sr) maxn = std::max(maxn, t.n);
       const int32_t* dyn = rdev.p;
+      for (size_t st = 0; st < rst.size(); ++st)
+        launch_rfactor<T>(ar.put(rst[st]), (int)rst[st].size(), ar.put(rrefs[st]), rdev.p,
+                          rmaxn[st], s);
       if (same_norm) {
-        launch_augment<T>(ar.put(aug), (int)aug.size(), ar.put(refs), rdev.p, eps_fill,
-                          ctx->d_err, maxn_aug, s);
+        launch_augment<T>(ar.put(aug), (int)aug.size(), rdev.p, eps_fill, ctx->d_err, maxn_aug,
+                          s);
       } else {
         // launch per instance with its own threshold
         size_t pos = 0;
@@ -552,12 +636,12 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           if (c >= P.ncolors) continue;
           const size_t cnt = P.members[c].size();
           std::vector<AugTask<T>> part(aug.begin() + pos, aug.begin() + pos + cnt);
-          launch_augment<T>(ar.put(part), (int)cnt, ar.put(refs), rdev.p,
-                            T(tol * I->H->norm2), ctx->d_err, maxn_aug, s);
+          launch_augment<T>(ar.put(part), (int)cnt, rdev.p, T(tol * I->H->norm2), ctx->d_err,
+                            maxn_aug, s);
           pos += cnt;
         }
       }
-      launches[0] += same_norm ? 1 : (int64_t)act.size();
+      launches[0] += (int64_t)rst.size() + (same_norm ? 1 : (int64_t)act.size());
       launches[1] += 2;
       launches[2] += 2;
       launches[3] += 1;

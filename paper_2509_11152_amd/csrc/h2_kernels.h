@@ -60,13 +60,26 @@ template <class T> struct FillRef {
   int32_t ncols, d0;
 };
 
-// Basis augmentation + complement of one cluster (Algorithm 2, first loop).
+// One stage of the tall-skinny QR of a fill row Y (Section 3, QR-based
+// augmentation): the R factor of the rows of Y^T held by a group of fill
+// blocks.  It is written as an n x n fill block, out[col + t n] = R[t][col],
+// so a later stage reduces the groups' factors like any other fill blocks.
+template <class T> struct RTask {
+  T* out;               // n x n, ld n
+  T* work;              // (n + kAugChunk) x n, used only when R does not fit in LDS
+  int32_t n;
+  int32_t fbeg, fend;   // FillRef range
+  int32_t pad0;
+};
+
+// Basis augmentation + complement of one cluster (Algorithm 2, first loop),
+// given the R factor of the cluster's fill row.
 template <class T> struct AugTask {
   const T* V;           // n x k input basis
+  const T* Rt;          // n x n, Rt[b + a n] = R[a][b] (R upper triangular, R^T R = Y Y^T)
   T* Q;                 // n x n output Q~ = [V~perp, V~]
   T* work;              // scratch
   int32_t n, k;
-  int32_t fbeg, fend;   // FillRef range
   int32_t ri;           // index into the r array (output)
   int32_t pad0;
 };
@@ -106,17 +119,28 @@ constexpr int kStrip = 16;
 constexpr int kCopyTile = 4096;
 constexpr int kAugChunk = 64;
 
-// row chunk and LDS elements of the in-LDS reduction of the fill row of order n:
-// R (n x (n+1)), chunk (n x (chunk+1)), reflector parameters
-__host__ __device__ inline int aug_lds_chunk(int n) { return n <= 64 ? 64 : 16; }
-__host__ __device__ inline int64_t aug_lds_elems(int n) {
-  return (int64_t)n * (n + 1) + (int64_t)n * (aug_lds_chunk(n) + 1) + 8;
-}
+constexpr int kLdsBytes = 150 * 1024;  // dynamic LDS a workgroup may request
 
-// scratch elements needed by one augmentation task of order n
-inline int64_t aug_work_elems(int n) {
-  return (int64_t)(n + kAugChunk) * n + 3 * (int64_t)n * n + 4 * (int64_t)n + 64;
+// Row chunk of the in-LDS fill-row reduction of order n for an LDS capacity
+// of `cap` elements: R packed upper triangular (n (n + 1) / 2), a chunk of
+// rows (n x (chunk + 1)) and 8 reflector parameters; 0 when even an 8-row
+// chunk does not fit.
+__host__ __device__ inline int rf_lds_chunk(int n, int64_t cap) {
+  for (int ch = 128; ch >= 8; ch >>= 1)
+    if ((int64_t)n * (n + 1) / 2 + (int64_t)n * (ch + 1) + 8 <= cap) return ch;
+  return 0;
 }
+// whether the fill-row reduction of order n runs in LDS
+template <class T> inline bool rf_in_lds(int n) {
+  return n <= 256 && rf_lds_chunk(n, kLdsBytes / (int64_t)sizeof(T)) > 0;
+}
+// rows of Y^T one reduction group takes (whole fill blocks, at least two
+// factors of a previous stage)
+inline int rf_group_rows(int n) { return n > 128 ? 2 * n : 256; }
+
+// scratch elements of one augmentation task of order n: V_perp (n^2),
+// reflectors or M' and W' (2 n^2), singular values, reflector scalars, ranks
+inline int64_t aug_work_elems(int n) { return 3 * (int64_t)n * n + 3 * (int64_t)n + 64; }
 
 // ---- launchers (stream-ordered; descriptor arrays are device pointers) ----
 template <class T>
@@ -126,8 +150,11 @@ template <class T>
 void launch_strip(const STask<T>* tasks, int ntasks, const int32_t* dyn, int64_t nstrips,
                   int maxn, hipStream_t s);
 template <class T>
-void launch_augment(const AugTask<T>* tasks, int ntasks, const FillRef<T>* refs,
-                    int32_t* r, T eps_fill, int* err, int maxn, hipStream_t s);
+void launch_rfactor(const RTask<T>* tasks, int ntasks, const FillRef<T>* refs,
+                    const int32_t* dyn, int maxn, hipStream_t s);
+template <class T>
+void launch_augment(const AugTask<T>* tasks, int ntasks, int32_t* r, T eps_fill, int* err,
+                    int maxn, hipStream_t s);
 template <class T>
 void launch_lu(const LUTask<T>* tasks, int ntasks, const int32_t* dyn, int* err, hipStream_t s);
 template <class T>

@@ -252,17 +252,21 @@ void launch_strip(const STask<T>* tasks, int ntasks, const int32_t* dyn, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// Basis augmentation and complement, one workgroup per cluster.
-//  1. R = R-factor of Y^T, Y = [F_ij] the fill row, by Householder on stacked
-//     [R; next chunk of Y^T rows] (triangle-on-top structured reflectors);
-//  2. M = R (I - V V^T): the projected fill row is (I - V V^T) Y = M^T Q_Y^T;
-//  3. one-sided Jacobi (Hestenes) on the columns of M with the rotations
-//     accumulated in W: the column norms are the singular values of
-//     (I - V V^T) Y and the columns of W its left singular vectors;
-//  4. Vbar = vectors with sigma > eps_fill (largest first), re-orthogonalised
-//     against V (twice) and among themselves (twice);
-//  5. Householder QR of V~ = [V, Vbar]; the complement is H_0...H_{k~-1} [0; I];
-//     Q~ = [V~perp, V~], r = n - k~.
+// Basis augmentation and complement (Section 3, QR-based augmentation).
+//  1. R = R-factor of Y^T, Y = [F_ij] the fill row, as a tall-skinny QR: the
+//     workgroups of k_rfactor reduce groups of fill blocks (Householder on
+//     stacked [R; next chunk of Y^T rows], triangle-on-top structured
+//     reflectors) and later stages reduce the groups' factors alike;
+// then, one workgroup per cluster (k_augment):
+//  2. Householder QR of V; its reflectors give V_perp = H_0..H_{k-1} [0; I],
+//     an orthonormal basis of the complement of V;
+//  3. M' = R V_perp: the projected fill row (I - V V^T) Y equals
+//     V_perp M'^T Q_Y^T, so one-sided Jacobi (Hestenes) on the columns of M'
+//     with the rotations accumulated in W' yields its singular values (column
+//     norms) and left singular vectors V_perp W';
+//  4. Vbar = V_perp W'_sel for sigma > eps_fill (largest first) and the
+//     complement of V~ = [V, Vbar] is V_perp W'_rest, so
+//     Q~ = [V_perp W'_rest, V, V_perp W'_sel] with r = n - k~.
 // ---------------------------------------------------------------------------
 template <class T>
 __device__ void structured_qr(T* R, T* C, int ldw, int n, int m, T* red) {
@@ -311,28 +315,41 @@ __device__ void structured_qr(T* R, T* C, int ldw, int n, int m, T* red) {
   (void)red;
 }
 
-// Same reduction with R (ld n+1) and the chunk (ld ch+1) in LDS, one thread
-// per column (n <= blockDim).  The reflector of column j+1 is formed by its
-// owner right after its update in step j, so every column costs one barrier.
+// Same reduction with R packed upper triangular in LDS (column c at
+// c (c + 1) / 2) and the chunk in LDS (ld ldc), tpc threads per column
+// (tpc in {1, 2, 4}, n * tpc <= blockDim): each thread owns the chunk rows
+// t = s, s + tpc, ... of its column and partial sums meet by lane shuffles.
+// The reflector of column j+1 is formed by its owners right after their
+// update in step j, so every column costs one barrier.
+__host__ __device__ inline int pk(int c) { return c * (c + 1) / 2; }
+
 template <class T>
-__device__ void structured_qr_lds(T* R, int ldr, T* C, int ldc, int n, int m, T* par) {
-  const int c = threadIdx.x;
+__device__ void structured_qr_lds(T* Rp, T* C, int ldc, int n, int m, T* par, int tpc) {
+  const int c = threadIdx.x / tpc, sl = threadIdx.x % tpc;
+  auto gsum = [&](T v) {
+    for (int o = 1; o < tpc; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+  };
   // par[3*(j&1) + {0,1,2}] = tau, beta, scale of reflector j
   auto reflector = [&](int j) {
+    const T* cj = C + j * ldc;
     T s2 = 0;
-    for (int t = 0; t < m; ++t) s2 += C[t + j * ldc] * C[t + j * ldc];
-    const T alpha = R[j + j * ldr];
-    T* q = par + 3 * (j & 1);
-    if (s2 == T(0)) {
-      q[0] = 0;
-      q[1] = alpha;
-      q[2] = 0;
-    } else {
-      const T nrm = sqrt(alpha * alpha + s2);
-      const T beta = alpha >= T(0) ? -nrm : nrm;
-      q[0] = (beta - alpha) / beta;
-      q[1] = beta;
-      q[2] = T(1) / (alpha - beta);
+    for (int t = sl; t < m; t += tpc) s2 += cj[t] * cj[t];
+    s2 = gsum(s2);
+    if (sl == 0) {
+      const T alpha = Rp[pk(j) + j];
+      T* q = par + 3 * (j & 1);
+      if (s2 == T(0)) {
+        q[0] = 0;
+        q[1] = alpha;
+        q[2] = 0;
+      } else {
+        const T nrm = sqrt(alpha * alpha + s2);
+        const T beta = alpha >= T(0) ? -nrm : nrm;
+        q[0] = (beta - alpha) / beta;
+        q[1] = beta;
+        q[2] = T(1) / (alpha - beta);
+      }
     }
   };
   if (c == 0 && n > 0) reflector(0);
@@ -341,63 +358,57 @@ __device__ void structured_qr_lds(T* R, int ldr, T* C, int ldc, int n, int m, T*
     const T* q = par + 3 * (j & 1);
     const T tau = q[0], beta = q[1], scale = q[2];
     if (c > j && c < n && tau != T(0)) {
+      const T* cj = C + j * ldc;
+      T* cc = C + c * ldc;
       T d = 0;
-      for (int t = 0; t < m; ++t) d += C[t + j * ldc] * C[t + c * ldc];
-      const T w = R[j + c * ldr] + scale * d;
-      const T tw = tau * w;
-      R[j + c * ldr] -= tw;
+      for (int t = sl; t < m; t += tpc) d += cj[t] * cc[t];
+      d = gsum(d);
+      T* rjc = Rp + pk(c) + j;
+      const T tw = tau * (*rjc + scale * d);
       const T f = tw * scale;
-      for (int t = 0; t < m; ++t) C[t + c * ldc] -= f * C[t + j * ldc];
+      for (int t = sl; t < m; t += tpc) cc[t] -= f * cj[t];
+      if (sl == 0) *rjc -= tw;
     }
     if (c == j + 1 && c < n) reflector(c);
-    if (c == j) R[j + j * ldr] = beta;
+    if (c == j && sl == 0) Rp[pk(j) + j] = beta;
     __syncthreads();
   }
 }
 
+// ---------------------------------------------------------------------------
+// One stage of the tall-skinny QR of fill rows: workgroup = group of fill
+// blocks of one cluster, output its R factor as out[col + t n] = R[t][col].
+// The fill block of a neighbour already skeletonized at this level is read
+// from its active window (first column dyn[d0]).
+// ---------------------------------------------------------------------------
 template <class T>
-__global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ tasks,
+__global__ __launch_bounds__(256) void k_rfactor(const RTask<T>* __restrict__ tasks,
                                                  const FillRef<T>* __restrict__ refs,
-                                                 int32_t* __restrict__ rout, T eps_fill,
-                                                 int* err, int lds_elems) {
-  extern __shared__ char aug_smem[];
-  const AugTask<T> tk = tasks[blockIdx.x];
-  const int n = tk.n, k = tk.k;
+                                                 const int32_t* __restrict__ dyn,
+                                                 int lds_elems) {
+  extern __shared__ char rf_smem[];
+  const RTask<T> tk = tasks[blockIdx.x];
+  const int n = tk.n;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int wave = tid >> 6, lane = tid & 63;
   __shared__ T red[8];
-  __shared__ int sh_flag;
-  if (n == 0) {
-    if (tid == 0) rout[tk.ri] = 0;
-    return;
-  }
-  const int ldw = n + kAugChunk;
-  T* R = tk.work;                               // (n + chunk) x n, ld ldw; rows 0..n-1 = R
-  T* C = R + n;                                 // chunk rows
-  T* G = tk.work + (int64_t)ldw * n;            // n x n
-  T* Hm = G + (int64_t)n * n;                   // n x n (Householder of V~ / V^T R^T scratch)
-  T* sig = Hm + (int64_t)n * n;                 // n
-  T* tau = sig + n;                             // n
-  int* rank = reinterpret_cast<int*>(tau + n);  // n ints (fits in n T's)
-  T* Q = tk.Q;
-
-  // ---- 1. R of the fill row ----
-  const int ch_lds = aug_lds_chunk(n);
-  const bool use_lds = n <= nthr && aug_lds_elems(n) <= lds_elems;
-  for (int e = tid; e < n * n; e += nthr) R[(e % n) + (int64_t)(e / n) * ldw] = 0;
-  if (use_lds) {
-    T* Rs = reinterpret_cast<T*>(aug_smem);
-    const int ldr = n + 1, ldc = ch_lds + 1;
-    T* Cs = Rs + (int64_t)n * ldr;
+  if (n == 0) return;
+  // same test as the host's (which gives `work` to the others); the launch
+  // provides enough LDS for every task of the launch that passes it
+  if (n <= nthr && rf_lds_chunk(n, kLdsBytes / (int64_t)sizeof(T)) > 0) {
+    const int ch = rf_lds_chunk(n, lds_elems);
+    const int tpc = n * 4 <= nthr ? 4 : n * 2 <= nthr ? 2 : 1;
+    T* Rp = reinterpret_cast<T*>(rf_smem);
+    const int ldc = ch + 1;
+    T* Cs = Rp + pk(n);
     T* par = Cs + (int64_t)n * ldc;
-    for (int e = tid; e < n * ldr; e += nthr) Rs[e] = 0;
+    for (int e = tid; e < pk(n); e += nthr) Rp[e] = 0;
     __syncthreads();
     int fill = 0;
     for (int f = tk.fbeg; f < tk.fend; ++f) {
       const FillRef<T> fr = refs[f];
-      int c = fr.d0 >= 0 ? rout[fr.d0] : 0;
+      int c = fr.d0 >= 0 ? dyn[fr.d0] : 0;
       while (c < fr.ncols) {
-        const int take = min(ch_lds - fill, fr.ncols - c);
+        const int take = min(ch - fill, fr.ncols - c);
         for (int e = tid; e < take * n; e += nthr) {
           const int tt = e / n, col = e % n;
           Cs[(fill + tt) + col * ldc] = fr.F[col + (int64_t)(c + tt) * fr.ld];
@@ -405,27 +416,28 @@ __global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ 
         fill += take;
         c += take;
         __syncthreads();
-        if (fill == ch_lds) {
-          structured_qr_lds(Rs, ldr, Cs, ldc, n, fill, par);
+        if (fill == ch) {
+          structured_qr_lds(Rp, Cs, ldc, n, fill, par, tpc);
           fill = 0;
         }
       }
     }
-    if (fill > 0) structured_qr_lds(Rs, ldr, Cs, ldc, n, fill, par);
+    if (fill > 0) structured_qr_lds(Rp, Cs, ldc, n, fill, par, tpc);
     __syncthreads();
     for (int e = tid; e < n * n; e += nthr) {
-      const int row = e % n, col = e / n;
-      R[row + (int64_t)col * ldw] = row <= col ? Rs[row + col * ldr] : T(0);
+      const int col = e % n, t = e / n;
+      tk.out[e] = t <= col ? Rp[pk(col) + t] : T(0);
     }
-    __syncthreads();
   } else {
+    const int ldw = n + kAugChunk;
+    T* R = tk.work;  // rows 0..n-1 = R, rows n..n+63 = chunk
+    T* C = R + n;
+    for (int e = tid; e < n * n; e += nthr) R[(e % n) + (int64_t)(e / n) * ldw] = 0;
     __syncthreads();
     int fill = 0;
     for (int f = tk.fbeg; f < tk.fend; ++f) {
       const FillRef<T> fr = refs[f];
-      int c = fr.d0 >= 0 ? rout[fr.d0] : 0;
-      // rout doubles as the level's r array: processed neighbours were written
-      // by earlier launches of this level.
+      int c = fr.d0 >= 0 ? dyn[fr.d0] : 0;
       while (c < fr.ncols) {
         const int take = min(kAugChunk - fill, fr.ncols - c);
         for (int e = tid; e < take * n; e += nthr) {
@@ -443,35 +455,141 @@ __global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ 
     }
     if (fill > 0) structured_qr(R, C, ldw, n, fill, red);
     __syncthreads();
+    for (int e = tid; e < n * n; e += nthr) {
+      const int col = e % n, t = e / n;
+      tk.out[e] = t <= col ? R[t + (int64_t)col * ldw] : T(0);
+    }
   }
+}
 
-  // ---- 2. M = R (I - V V^T) = G^T, G = (I - V V^T) R^T ----
-  // Hm[c + a*n] = (R V)[c, a]   (n x k)
-  for (int e = tid; e < n * k; e += nthr) {
-    const int c = e % n, a = e / n;
-    T s = 0;
-    for (int b = c; b < n; ++b) s += R[c + (int64_t)b * ldw] * tk.V[b + (int64_t)a * n];
-    Hm[e] = s;
+template <class T>
+void launch_rfactor(const RTask<T>* tasks, int ntasks, const FillRef<T>* refs,
+                    const int32_t* dyn, int maxn, hipStream_t s) {
+  if (ntasks <= 0) return;
+  const int64_t cap = kLdsBytes / (int64_t)sizeof(T);
+  const int ch = rf_lds_chunk(maxn, cap);
+  const int64_t need =
+      rf_in_lds<T>(maxn) ? (int64_t)pk(maxn) + (int64_t)maxn * (ch + 1) + 8 : cap;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_rfactor<T>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_rfactor<T>, dim3(ntasks), dim3(256), (size_t)(need * sizeof(T)), s, tasks,
+                     refs, dyn, (int)need);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ tasks,
+                                                 int32_t* __restrict__ rout, T eps_fill,
+                                                 int* err, int lds_elems) {
+  extern __shared__ char aug_smem[];
+  const AugTask<T> tk = tasks[blockIdx.x];
+  const int n = tk.n, k = tk.k;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  __shared__ T red[8];
+  __shared__ int sh_flag;
+  if (n == 0) {
+    if (tid == 0) rout[tk.ri] = 0;
+    return;
+  }
+  const T* Rt = tk.Rt;                          // Rt[b + a n] = R[a][b]
+  T* G = tk.work;                               // n x n (V_perp)
+  T* Hm = G + (int64_t)n * n;                   // 2 n^2 (reflectors of V, or M' and W')
+  T* sig = Hm + 2 * (int64_t)n * n;             // n
+  T* tau = sig + n;                             // n
+  int* rank = reinterpret_cast<int*>(tau + n);  // n ints (fit in n T's)
+  T* Q = tk.Q;
+
+  // ---- 2. Householder QR of V (n x k): reflectors H_0 .. H_{k-1} ----
+  const int mp = n - k;  // dimension of the complement of V
+  const int64_t cap = lds_elems;
+  T* smem = reinterpret_cast<T*>(aug_smem);
+  const bool bc_lds = (int64_t)n * n + 8 <= cap;
+  T* Hv = bc_lds ? smem : Hm;                          // n x k reflectors, ld n
+  T* Xp = bc_lds ? smem + (int64_t)n * k : G;          // n x mp complement, ld n
+  for (int e = tid; e < n * k; e += nthr) Hv[e] = tk.V[e];
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    T* hj = Hv + (int64_t)j * n;
+    T sq = 0;
+    for (int t = j + 1 + tid; t < n; t += nthr) sq += hj[t] * hj[t];
+    sq = block_sum(sq, red);
+    const T alpha = hj[j];
+    T tj = 0, beta = alpha;
+    if (sq != T(0)) {
+      const T nrm = sqrt(alpha * alpha + sq);
+      beta = alpha >= T(0) ? -nrm : nrm;
+      tj = (beta - alpha) / beta;
+    }
+    if (tj != T(0)) {
+      const T scale = T(1) / (alpha - beta);
+      for (int t = j + 1 + tid; t < n; t += nthr) hj[t] *= scale;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      hj[j] = T(1);  // implicit unit of the reflector, stored explicitly
+      tau[j] = tj;
+    }
+    __syncthreads();
+    if (tj != T(0)) {
+      for (int c = j + 1 + wave; c < k; c += 4) {
+        T* hc = Hv + (int64_t)c * n;
+        T d = 0;
+        for (int t = j + lane; t < n; t += 64) d += hj[t] * hc[t];
+        d = wave_sum(d) * tj;
+        for (int t = j + lane; t < n; t += 64) hc[t] -= d * hj[t];
+      }
+    }
+    __syncthreads();
+  }
+  // ---- 3. V_perp = H_0 ... H_{k-1} [0; I_mp], the complement of V ----
+  for (int e = tid; e < n * mp; e += nthr) {
+    const int row = e % n, c = e / n;
+    Xp[e] = (row == k + c) ? T(1) : T(0);
   }
   __syncthreads();
-  for (int e = tid; e < n * n; e += nthr) {
-    const int c = e % n, b = e / n;
-    T s = (b >= c) ? R[c + (int64_t)b * ldw] : T(0);
-    for (int a = 0; a < k; ++a) s -= Hm[c + (int64_t)a * n] * tk.V[b + (int64_t)a * n];
-    G[e] = s;  // M[c, b]
+  for (int j = k - 1; j >= 0; --j) {
+    const T tj = tau[j];
+    if (tj == T(0)) continue;
+    const T* hj = Hv + (int64_t)j * n;
+    for (int c = wave; c < mp; c += 4) {
+      T* xc = Xp + (int64_t)c * n;
+      T d = 0;
+      for (int t = j + lane; t < n; t += 64) d += hj[t] * xc[t];
+      d = wave_sum(d) * tj;
+      for (int t = j + lane; t < n; t += 64) xc[t] -= d * hj[t];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  // W = I accumulates the rotations: M W = U S  =>  G = M^T = W S U^T, so the
-  // columns of W are the left singular vectors of G, i.e. of (I - V V^T) Y,
-  // orthonormal to working precision whatever the size of sigma.
-  T* W = Hm;
-  for (int e = tid; e < n * n; e += nthr) W[e] = (e % n == e / n) ? T(1) : T(0);
+  T* Vp = G;  // keep V_perp in global scratch (n x mp, ld n)
+  if (bc_lds)
+    for (int e = tid; e < n * mp; e += nthr) Vp[e] = Xp[e];
   __syncthreads();
 
-  // ---- 3. one-sided Jacobi on the columns of M ----
-  const int ne = (n + 1) & ~1;
+  // ---- 4. M' = R V_perp (n x mp) and W' = I (mp x mp) ----
+  // The projected fill row is (I - V V^T) Y = V_perp V_perp^T R^T Q_Y^T, so its
+  // nonzero singular values and left singular vectors are those of M'^T
+  // mapped by V_perp: one-sided Jacobi on the columns of M' with the rotations
+  // accumulated in W' gives them (W' orthonormal to working precision).
+  const bool de_lds = (int64_t)n * mp + (int64_t)mp * mp + 8 <= cap;
+  T* Ms = de_lds ? smem : Hm;                          // n x mp, ld n
+  T* Ws = de_lds ? smem + (int64_t)n * mp : Hm + (int64_t)n * mp;  // mp x mp
+  for (int e = tid; e < n * mp; e += nthr) {
+    const int a = e % n, c = e / n;
+    T acc = 0;
+    for (int b = a; b < n; ++b) acc += Rt[b + (int64_t)a * n] * Vp[b + (int64_t)c * n];
+    Ms[e] = acc;
+  }
+  for (int e = tid; e < mp * mp; e += nthr) Ws[e] = (e % mp == e / mp) ? T(1) : T(0);
+  __syncthreads();
+
+  // ---- 5. one-sided Jacobi on the columns of M' ----
+  const int ne = (mp + 1) & ~1;
   const T tolj = eps_of<T>() * T(n);
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  for (int sweep = 0; sweep < 40 && mp > 1; ++sweep) {
     if (tid == 0) sh_flag = 0;
     __syncthreads();
     for (int rnd = 0; rnd < ne - 1; ++rnd) {
@@ -484,30 +602,32 @@ __global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ 
           a = (rnd + p) % (ne - 1);
           b = (rnd - p + ne - 1) % (ne - 1);
         }
-        if (a >= n || b >= n) continue;
-        T* ga = G + (int64_t)a * n;
-        T* gb = G + (int64_t)b * n;
-        T al = 0, be = 0, ga_b = 0;
+        if (a >= mp || b >= mp) continue;
+        T* ga = Ms + (int64_t)a * n;
+        T* gb = Ms + (int64_t)b * n;
+        T al = 0, be = 0, gab = 0;
         for (int t = lane; t < n; t += 64) {
           const T x = ga[t], y = gb[t];
           al += x * x;
           be += y * y;
-          ga_b += x * y;
+          gab += x * y;
         }
         al = wave_sum(al);
         be = wave_sum(be);
-        ga_b = wave_sum(ga_b);
-        if (ga_b != T(0) && fabs(ga_b) > tolj * sqrt(al * be)) {
-          const T zeta = (be - al) / (T(2) * ga_b);
+        gab = wave_sum(gab);
+        if (gab != T(0) && fabs(gab) > tolj * sqrt(al * be)) {
+          const T zeta = (be - al) / (T(2) * gab);
           const T tt = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
           const T cs = T(1) / sqrt(T(1) + tt * tt);
           const T sn = cs * tt;
-          T* wa = W + (int64_t)a * n;
-          T* wb = W + (int64_t)b * n;
           for (int t = lane; t < n; t += 64) {
             const T x = ga[t], y = gb[t];
             ga[t] = cs * x - sn * y;
             gb[t] = sn * x + cs * y;
+          }
+          T* wa = Ws + (int64_t)a * mp;
+          T* wb = Ws + (int64_t)b * mp;
+          for (int t = lane; t < mp; t += 64) {
             const T u = wa[t], v = wb[t];
             wa[t] = cs * u - sn * v;
             wb[t] = sn * u + cs * v;
@@ -521,19 +641,19 @@ __global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ 
     __syncthreads();
     if (!fl) break;
   }
-  for (int c = wave; c < n; c += 4) {
-    T s = 0;
-    for (int t = lane; t < n; t += 64) s += G[t + (int64_t)c * n] * G[t + (int64_t)c * n];
-    s = wave_sum(s);
-    if (lane == 0) sig[c] = sqrt(s);
+  for (int c = wave; c < mp; c += 4) {
+    T sq = 0;
+    for (int t = lane; t < n; t += 64) sq += Ms[t + (int64_t)c * n] * Ms[t + (int64_t)c * n];
+    sq = wave_sum(sq);
+    if (lane == 0) sig[c] = sqrt(sq);
   }
   __syncthreads();
 
-  // ---- 4. select, order and orthonormalise Vbar ----
-  for (int c = tid; c < n; c += nthr) {
+  // ---- 6. selection and Q~ = [V_perp W'_rest, V, V_perp W'_sel] ----
+  for (int c = tid; c < mp; c += nthr) {
     int pos = 0;
     const T sc = sig[c];
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < mp; ++i) {
       const T si = sig[i];
       pos += (si > sc) || (si == sc && i < c);
     }
@@ -541,140 +661,46 @@ __global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ 
   }
   if (tid == 0) {
     int cnt = 0;
-    for (int i = 0; i < n; ++i) cnt += sig[i] > eps_fill;
-    if (cnt > n - k) cnt = n - k;
+    for (int i = 0; i < mp; ++i) cnt += sig[i] > eps_fill;
     sh_flag = cnt;
   }
   __syncthreads();
   const int rbar = sh_flag;
   const int kt = k + rbar;
   const int r = n - kt;
-  T* Vt = Q + (int64_t)r * n;  // V~ occupies the last kt columns of Q~
-  for (int e = tid; e < n * k; e += nthr) Vt[e] = tk.V[e];
-  for (int e = tid; e < n * n; e += nthr) {
-    const int row = e % n, c = e / n;
+  // column of Q~ receiving the rotated complement vector c: the rbar largest
+  // singular directions (in decreasing order) follow V, the others come first
+  for (int e = tid; e < n * mp; e += nthr) {
+    const int t = e % n, c = e / n;
     const int pos = rank[c];
-    if (pos < rbar) Vt[row + (int64_t)(k + pos) * n] = W[e];
+    const int qcol = pos < rbar ? kt - rbar + pos + r : pos - rbar;
+    T acc = 0;
+    for (int b = 0; b < mp; ++b) acc += Vp[t + (int64_t)b * n] * Ws[b + (int64_t)c * mp];
+    Q[t + (int64_t)qcol * n] = acc;
   }
-  __syncthreads();
-  for (int pass = 0; pass < 2; ++pass) {
-    // Vbar -= V (V^T Vbar)
-    for (int e = tid; e < k * rbar; e += nthr) {
-      const int a = e % k, b = e / k;
-      T s = 0;
-      for (int t = 0; t < n; ++t) s += Vt[t + (int64_t)a * n] * Vt[t + (int64_t)(k + b) * n];
-      Hm[e] = s;
-    }
-    __syncthreads();
-    for (int e = tid; e < n * rbar; e += nthr) {
-      const int t = e % n, b = e / n;
-      T s = Vt[t + (int64_t)(k + b) * n];
-      for (int a = 0; a < k; ++a) s -= Vt[t + (int64_t)a * n] * Hm[a + (int64_t)b * k];
-      Vt[t + (int64_t)(k + b) * n] = s;
-    }
-    __syncthreads();
-  }
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int b = 0; b < rbar; ++b) {
-      T* vb = Vt + (int64_t)(k + b) * n;
-      T s = 0;
-      for (int t = tid; t < n; t += nthr) s += vb[t] * vb[t];
-      s = block_sum(s, red);
-      const T inv = s > T(0) ? T(1) / sqrt(s) : T(0);
-      for (int t = tid; t < n; t += nthr) vb[t] *= inv;
-      __syncthreads();
-      for (int c = b + 1 + wave; c < rbar; c += 4) {
-        T* vc = Vt + (int64_t)(k + c) * n;
-        T d = 0;
-        for (int t = lane; t < n; t += 64) d += vb[t] * vc[t];
-        d = wave_sum(d);
-        for (int t = lane; t < n; t += 64) vc[t] -= d * vb[t];
-      }
-      __syncthreads();
-    }
-  }
-
-  // ---- 5. complement by Householder QR of V~ ----
-  for (int e = tid; e < n * kt; e += nthr) Hm[e] = Vt[e];
-  __syncthreads();
-  for (int j = 0; j < kt; ++j) {
-    T* hj = Hm + (int64_t)j * n;
-    T s = 0;
-    for (int t = j + 1 + tid; t < n; t += nthr) s += hj[t] * hj[t];
-    s = block_sum(s, red);
-    const T alpha = hj[j];
-    T tj = 0, beta = alpha;
-    if (s != T(0)) {
-      const T nrm = sqrt(alpha * alpha + s);
-      beta = alpha >= T(0) ? -nrm : nrm;
-      tj = (beta - alpha) / beta;
-    }
-    __syncthreads();
-    if (tj != T(0)) {
-      const T scale = T(1) / (alpha - beta);
-      for (int t = j + 1 + tid; t < n; t += nthr) hj[t] *= scale;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      hj[j] = T(1);  // implicit unit of the reflector, stored explicitly
-      tau[j] = tj;
-    }
-    __syncthreads();
-    if (tj != T(0)) {
-      for (int c = j + 1 + wave; c < kt; c += 4) {
-        T* hc = Hm + (int64_t)c * n;
-        T d = 0;
-        for (int t = j + lane; t < n; t += 64) d += hj[t] * hc[t];
-        d = wave_sum(d) * tj;
-        for (int t = j + lane; t < n; t += 64) hc[t] -= d * hj[t];
-      }
-    }
-    __syncthreads();
-  }
-  // X = [0; I_r] then X <- H_j X for j = kt-1 .. 0, written into Q[:, 0:r]
-  for (int e = tid; e < n * r; e += nthr) {
-    const int row = e % n, c = e / n;
-    Q[e] = (row == kt + c) ? T(1) : T(0);
-  }
-  __syncthreads();
-  for (int j = kt - 1; j >= 0; --j) {
-    const T tj = tau[j];
-    if (tj == T(0)) continue;
-    const T* hj = Hm + (int64_t)j * n;
-    for (int c = wave; c < r; c += 4) {
-      T* qc = Q + (int64_t)c * n;
-      T d = 0;
-      for (int t = j + lane; t < n; t += 64) d += hj[t] * qc[t];
-      d = wave_sum(d) * tj;
-      for (int t = j + lane; t < n; t += 64) qc[t] -= d * hj[t];
-    }
-    __syncthreads();
-  }
+  for (int e = tid; e < n * k; e += nthr) Q[(int64_t)r * n + e] = tk.V[e];
   if (tid == 0) {
     rout[tk.ri] = r;
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < mp; ++i)
       if (!(sig[i] == sig[i])) atomicOr(err, 2);
   }
 }
 
 template <class T>
-void launch_augment(const AugTask<T>* tasks, int ntasks, const FillRef<T>* refs, int32_t* r,
-                    T eps_fill, int* err, int maxn, hipStream_t s) {
+void launch_augment(const AugTask<T>* tasks, int ntasks, int32_t* r, T eps_fill, int* err,
+                    int maxn, hipStream_t s) {
   if (ntasks <= 0) return;
-  // LDS for the largest cluster of the launch that fits (R plus a row chunk)
-  const int64_t cap = (150 * 1024) / (int64_t)sizeof(T);
-  int64_t need = aug_lds_elems(std::min(maxn, 64));
-  if (maxn > 64 && aug_lds_elems(maxn) <= cap) need = std::max(need, aug_lds_elems(maxn));
-  if (need > cap) need = 0;
-  const int lds_bytes = (int)(need * (int64_t)sizeof(T));
+  // LDS: the reflectors of V and V_perp (n^2), then M' and W' (at most 2 n^2)
+  const int64_t cap = kLdsBytes / (int64_t)sizeof(T);
+  const int64_t need = std::min<int64_t>(cap, 2 * (int64_t)maxn * maxn + 8);
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)k_augment<T>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_augment<T>, dim3(ntasks), dim3(256), lds_bytes, s, tasks, refs, r,
-                     eps_fill, err, (int)(lds_bytes / sizeof(T)));
+  hipLaunchKernelGGL(k_augment<T>, dim3(ntasks), dim3(256), (size_t)(need * sizeof(T)), s, tasks,
+                     r, eps_fill, err, (int)need);
 }
 
 // ---------------------------------------------------------------------------
@@ -1143,8 +1169,9 @@ void launch_check_finite(const double* X, int64_t n, int* flag, hipStream_t s) {
                                int, hipStream_t);                                             \
   template void launch_strip<T>(const STask<T>*, int, const int32_t*, int64_t, int,           \
                                 hipStream_t);                                                 \
-  template void launch_augment<T>(const AugTask<T>*, int, const FillRef<T>*, int32_t*, T,     \
-                                  int*, int, hipStream_t);                                    \
+  template void launch_rfactor<T>(const RTask<T>*, int, const FillRef<T>*, const int32_t*, int, \
+                                  hipStream_t);                                               \
+  template void launch_augment<T>(const AugTask<T>*, int, int32_t*, T, int*, int, hipStream_t); \
   template void launch_lu<T>(const LUTask<T>*, int, const int32_t*, int*, hipStream_t);       \
   template void launch_trsm<T>(const TrsmTask<T>*, int, const int32_t*, hipStream_t);         \
   template void launch_copy<T, double>(const CTask<T, double>*, int, int64_t, hipStream_t);   \
