@@ -124,7 +124,7 @@ def main():
     spec = workloads.WORKLOADS[args.workload]
     log(f"[bench] constructing {args.workload} (N={spec['N']}) on {args.construct_device}")
     t0 = time.perf_counter()
-    w = workloads.make(spec, device=args.construct_device)
+    w = workloads.make(spec, device=args.construct_device, verbose=True)
     log(f"[bench] construction {time.perf_counter() - t0:.1f} s, blob {w['blob'].nbytes / 1e9:.2f} GB")
     dev = torch.device("cuda:0")
     ctx = h2.Context(0)

@@ -84,12 +84,21 @@ def _lagrange_nd(nodes1d, digits, X):
     return out
 
 
+def _bqr(A, mode, chunk=512):
+    """Batched QR in slices of at most `chunk` matrices (large device batches
+    exhaust the solver's workspace)."""
+    if A.shape[0] <= chunk:
+        return torch.linalg.qr(A, mode=mode)
+    parts = [torch.linalg.qr(A[i:i + chunk], mode=mode) for i in range(0, A.shape[0], chunk)]
+    return tuple(torch.cat([p[k] for p in parts], 0) for k in range(2))
+
+
 def _qr_r(A):
     """R factor of batched A (b, m, n); returns (b, n, n) (zero padded when m < n)."""
     b, m, n = A.shape
     if m < n:
         A = torch.cat([A, torch.zeros(b, n - m, n, dtype=A.dtype, device=A.device)], 1)
-    return torch.linalg.qr(A, mode="r")[1][:, :n, :n]
+    return _bqr(A, "r")[1][:, :n, :n]
 
 
 def construct(pts, kernel, leaf_size=64, tree_kind="kd", eta=0.7, adm_kind=0,
@@ -100,11 +109,20 @@ def construct(pts, kernel, leaf_size=64, tree_kind="kd", eta=0.7, adm_kind=0,
     (transfers), D (leaf near blocks) and S (far couplings) as float64 numpy
     arrays, plus norm2 (power-iteration estimate of ||A_H||_2).
     """
+    import sys
+    import time as _time
+    _t0 = _time.perf_counter()
+
+    def say(msg):
+        if verbose:
+            print(f"[construct {_time.perf_counter() - _t0:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
     dev = torch.device(device)
     pts = np.asarray(pts, dtype=np.float64)
     N, dim = pts.shape
     if p0 is None:
         p0 = 8 if dim == 2 else 4
+    say(f"tree of {N} points")
     t = treemod.build_tree(pts, leaf_size, tree_kind)
     near_ptr, near_col, far_ptr, far_col = treemod.dual_traversal(t, eta, adm_kind)
     L = t.L
@@ -113,6 +131,7 @@ def construct(pts, kernel, leaf_size=64, tree_kind="kd", eta=0.7, adm_kind=0,
     P = torch.as_tensor(pts[t.perm], dtype=torch.float64, device=dev)
     sizes = (t.idx_end - t.idx_begin).astype(np.int64)
 
+    say(f"tree: {L} levels, {len(near_col)} near and {len(far_col)} far pairs")
     # ---- dense near field (leaf level) ----
     leaf0 = lp[L]
     nleaf = lp[L + 1] - lp[L]
@@ -144,6 +163,7 @@ def construct(pts, kernel, leaf_size=64, tree_kind="kd", eta=0.7, adm_kind=0,
         h["norm2"] = power_norm(h)
         return h
 
+    say("near field done")
     # ---- step 1: interpolation sample points per level (levels top..L) ----
     lev = {}
     for l in range(top, L + 1):
@@ -165,6 +185,7 @@ def construct(pts, kernel, leaf_size=64, tree_kind="kd", eta=0.7, adm_kind=0,
             Lv.mask = torch.ones(Lv.n, k0, dtype=torch.float64, device=dev)
         lev[l] = Lv
 
+    say("interpolation points done")
     # ---- step 2: orthogonalisation upsweep ----
     # Leaf: U0 (mmax x k0) -> Q, R
     Lv = lev[L]
@@ -174,7 +195,7 @@ def construct(pts, kernel, leaf_size=64, tree_kind="kd", eta=0.7, adm_kind=0,
         Lv.k1 = mmax
     else:
         U0 = _lagrange_nd(Lv.nodes1d, Lv.digits, leafpts) * leafmask.unsqueeze(-1)
-        Q, R = torch.linalg.qr(U0, mode="reduced")
+        Q, R = _bqr(U0, "reduced")
         Lv.Uq, Lv.R = Q, R
         Lv.k1 = R.shape[1]
     for l in range(L - 1, top - 1, -1):
@@ -186,7 +207,7 @@ def construct(pts, kernel, leaf_size=64, tree_kind="kd", eta=0.7, adm_kind=0,
         E0 = _lagrange_nd(Lv.nodes1d[par], Lv.digits, Lc.xi) * Lc.mask.unsqueeze(-1)
         RE = torch.bmm(Lc.R, E0)  # (nchild, kc1, kp0)
         Z = RE.reshape(Lv.n, arity * Lc.k1, Lv.k0)
-        Q, R = torch.linalg.qr(Z, mode="reduced")
+        Q, R = _bqr(Z, "reduced")
         Lv.k1 = R.shape[1]
         Lv.R = R
         Lc.E1 = Q.reshape(Lv.n * arity, Lc.k1, Lv.k1)  # orthonormal stacked transfers
@@ -216,8 +237,10 @@ def construct(pts, kernel, leaf_size=64, tree_kind="kd", eta=0.7, adm_kind=0,
     norm_pre = acc / ns
     thr = eps * norm_pre
 
+    say("orthogonalisation done")
     # ---- step 3: total-weight downsweep ----
     for l in range(top, L + 1):
+        say(f"weights, level {l}")
         Lv = lev[l]
         e, fi, fj = far_of_level(l)
         k1 = Lv.k1
@@ -254,8 +277,10 @@ def construct(pts, kernel, leaf_size=64, tree_kind="kd", eta=0.7, adm_kind=0,
             W[n0:n1] = R.transpose(1, 2)
         Lv.W = W
 
+    say("weights done")
     # ---- step 4: truncation upsweep ----
     for l in range(L, top - 1, -1):
+        say(f"truncation, level {l}")
         Lv = lev[l]
         if l == L:
             M = Lv.W
@@ -293,7 +318,9 @@ def construct(pts, kernel, leaf_size=64, tree_kind="kd", eta=0.7, adm_kind=0,
         h["Et"][l] = Lp.Pk.reshape(Lp.n, arity, k2c, kpm).reshape(Lv.n, k2c, kpm)
 
     # couplings: S'' = (T R) K (T R)^T, padded per level
+    say("bases done")
     for l in range(top, L + 1):
+        say(f"couplings, level {l}")
         Lv = lev[l]
         B = torch.bmm(Lv.T, Lv.R)  # (n, k2max, k0)
         e, fi, fj = far_of_level(l)
@@ -304,7 +331,9 @@ def construct(pts, kernel, leaf_size=64, tree_kind="kd", eta=0.7, adm_kind=0,
             Sl[c0:c0 + len(ii)] = coupling(l, ii, jj, B[ii], B[jj])
         h["St"][l] = (e, fi, fj, Sl)
         lev[l] = None
+    say("norm estimate")
     h["norm2"] = power_norm(h)
+    say("done")
     return h
 
 

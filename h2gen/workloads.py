@@ -56,7 +56,7 @@ def batch_workload(i, n, leaf=64):
                 leaf=leaf, eta=0.7, tol=1e-8, nrhs=16, rhs_seed=4000 + i, p0=10)
 
 
-def make(spec, device="cpu", want_blob=True):
+def make(spec, device="cpu", want_blob=True, verbose=False):
     """Points, constructor output, serialized blob and right-hand sides of a workload."""
     if isinstance(spec, str):
         spec = WORKLOADS[spec]
@@ -64,7 +64,7 @@ def make(spec, device="cpu", want_blob=True):
     kname, kpar, alpha = spec["kernel"]
     K = kernels.Kernel(kname, kpar, alpha)
     h = cons.construct(pts, K, spec["leaf"], spec["tree"], spec["eta"], 0, spec["tol"] / 10,
-                       p0=spec["p0"], device=device)
+                       p0=spec["p0"], device=device, verbose=verbose)
     B = rng.rhs(spec["rhs_seed"], spec["N"], spec["nrhs"])
     buf = blobmod.write_blob(h) if want_blob else None
     return dict(spec=spec, points=pts, kernel=K, h=h, blob=buf, B=B)

@@ -360,6 +360,10 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     if ((int64_t)maxn_all * kStrip * (int64_t)sizeof(T) > 160 * 1024)
       throw H2Error(H2_ERROR_UNSUPPORTED, "cluster of order " + std::to_string(maxn_all) +
                                               " exceeds the strip kernel's LDS capacity");
+    if (maxn_all > kMaxAugOrder)
+      throw H2Error(H2_ERROR_UNSUPPORTED, "cluster of order " + std::to_string(maxn_all) +
+                                              " exceeds the augmentation's limit of " +
+                                              std::to_string(kMaxAugOrder));
     // augmentation workspace: max over colours of the sum of per-task scratch
     int64_t wmax = 0;
     for (int c = 0; c < maxc; ++c) {
@@ -653,8 +657,19 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       hipEvent_t e2 = new_event();
       H2_HIP(hipEventRecord(e2, s));
       marks.push_back({1, e2});
-      launch_lu<T>(ar.put(lus), (int)lus.size(), dyn, ctx->d_err, s);
-      launch_trsm<T>(ar.put(trs), (int)trs.size(), dyn, s);
+      {
+        int maxr = 1;  // r <= n of the cluster (its D block's leading dimension)
+        for (auto& t : lus) maxr = std::max(maxr, (int)t.lda);
+        launch_lu<T>(ar.put(lus), (int)lus.size(), dyn, ctx->d_err, maxr, s);
+      }
+      {
+        int maxr = 1, maxcols = 1;
+        for (auto& t : trs) {
+          maxr = std::max(maxr, (int)t.ldlu);
+          maxcols = std::max(maxcols, t.ncols);
+        }
+        launch_trsm<T>(ar.put(trs), (int)trs.size(), dyn, maxr, maxcols, s);
+      }
       hipEvent_t e3 = new_event();
       H2_HIP(hipEventRecord(e3, s));
       marks.push_back({2, e3});

@@ -82,42 +82,55 @@ template <class T> struct DevArray {
   int64_t bytes() const { return (int64_t)sizeof(T) * n; }
 };
 
-// Pinned staging + device arena for task descriptors.  Regions are reused
-// only after the stream has been synchronised.
+// Descriptor arrays staged through pinned host memory into device memory.
+// Chunks are only ever added: every array put since the last reset() stays
+// valid (several puts feed one launch, and launches queue behind each other),
+// so reset() may be called only once the stream has finished all work that
+// reads them.
 struct DescArena {
-  char* h = nullptr;
-  char* d = nullptr;
-  size_t cap = 0, used = 0;
+  struct Chunk {
+    char* h = nullptr;
+    char* d = nullptr;
+    size_t cap = 0;
+  };
+  std::vector<Chunk> chunks;
+  size_t cur = 0, used = 0;  // chunk being filled and bytes used in it
   hipStream_t s = nullptr;
   ~DescArena() { free_all(); }
   void free_all() {
-    if (h) (void)hipHostFree(h);
-    if (d) (void)hipFree(d);
-    h = d = nullptr;
-    cap = used = 0;
+    for (auto& c : chunks) {
+      if (c.h) (void)hipHostFree(c.h);
+      if (c.d) (void)hipFree(c.d);
+    }
+    chunks.clear();
+    cur = used = 0;
   }
-  void reserve(size_t bytes) {
-    if (bytes <= cap) return;
-    H2_HIP(hipStreamSynchronize(s));
-    free_all();
-    cap = bytes;
-    H2_HIP(hipHostMalloc((void**)&h, cap, hipHostMallocDefault));
-    H2_HIP(hipMalloc((void**)&d, cap));
-    used = 0;
-  }
-  void reset() { used = 0; }
+  void reset() { cur = used = 0; }
   template <class X> X* put(const std::vector<X>& v) {
     if (v.empty()) return nullptr;
-    size_t bytes = sizeof(X) * v.size();
-    size_t need = (bytes + 255) & ~(size_t)255;
-    if (need > cap) reserve(std::max(need, cap * 2 + ((size_t)64 << 20)));
-    if (used + need > cap) {
-      H2_HIP(hipStreamSynchronize(s));
+    const size_t bytes = sizeof(X) * v.size();
+    const size_t need = (bytes + 255) & ~(size_t)255;
+    while (cur < chunks.size() && used + need > chunks[cur].cap) {
+      ++cur;
       used = 0;
     }
-    std::memcpy(h + used, v.data(), bytes);
-    H2_HIP(hipMemcpyAsync(d + used, h + used, bytes, hipMemcpyHostToDevice, s));
-    X* out = reinterpret_cast<X*>(d + used);
+    if (cur == chunks.size()) {
+      Chunk c;
+      c.cap = std::max(need, (size_t)64 << 20);
+      H2_HIP(hipHostMalloc((void**)&c.h, c.cap, hipHostMallocDefault));
+      hipError_t e = hipMalloc((void**)&c.d, c.cap);
+      if (e != hipSuccess) {
+        (void)hipHostFree(c.h);
+        (void)hipGetLastError();
+        throw H2Error(H2_ERROR_OUT_OF_MEMORY, "descriptor arena allocation failed");
+      }
+      chunks.push_back(c);
+      used = 0;
+    }
+    Chunk& c = chunks[cur];
+    std::memcpy(c.h + used, v.data(), bytes);
+    H2_HIP(hipMemcpyAsync(c.d + used, c.h + used, bytes, hipMemcpyHostToDevice, s));
+    X* out = reinterpret_cast<X*>(c.d + used);
     used += need;
     return out;
   }

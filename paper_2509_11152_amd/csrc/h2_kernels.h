@@ -121,19 +121,26 @@ constexpr int kAugChunk = 64;
 
 constexpr int kLdsBytes = 150 * 1024;  // dynamic LDS a workgroup may request
 
-// Row chunk of the in-LDS fill-row reduction of order n for an LDS capacity
-// of `cap` elements: R packed upper triangular (n (n + 1) / 2), a chunk of
-// rows (n x (chunk + 1)) and 8 reflector parameters; 0 when even an 8-row
-// chunk does not fit.
-__host__ __device__ inline int rf_lds_chunk(int n, int64_t cap) {
-  for (int ch = 128; ch >= 8; ch >>= 1)
-    if ((int64_t)n * (n + 1) / 2 + (int64_t)n * (ch + 1) + 8 <= cap) return ch;
-  return 0;
+// Fill-row reduction in LDS: tpc threads per column (4, 2 or 1 by order),
+// kRfRows chunk rows per thread in registers; LDS holds R packed upper
+// triangular (n (n + 1) / 2), the current reflector (double-buffered chunk
+// column) and the reflector parameters.
+constexpr int kRfRows = 32;
+__host__ __device__ inline int rf_tpc(int n) { return n <= 64 ? 4 : n <= 128 ? 2 : 1; }
+__host__ __device__ inline int64_t rf_lds_elems(int n) {
+  return (int64_t)n * (n + 1) / 2 + 2 * (int64_t)rf_tpc(n) * kRfRows + 8;
 }
-// whether the fill-row reduction of order n runs in LDS
-template <class T> inline bool rf_in_lds(int n) {
-  return n <= 256 && rf_lds_chunk(n, kLdsBytes / (int64_t)sizeof(T)) > 0;
+// whether the fill-row reduction of order n runs in LDS (else in `work`)
+template <class T> __host__ __device__ inline bool rf_in_lds(int n) {
+  return n <= 256 && rf_lds_elems(n) <= kLdsBytes / (int64_t)sizeof(T);
 }
+// LDS elements enough for every in-LDS order <= maxn
+__host__ __device__ inline int64_t rf_lds_bound(int maxn) {
+  return (int64_t)maxn * (maxn + 1) / 2 + 8 * (int64_t)kRfRows + 8;
+}
+// largest cluster order the augmentation supports (lanes x registers of a
+// Jacobi pair)
+constexpr int kMaxAugOrder = 1024;
 // rows of Y^T one reduction group takes (whole fill blocks, at least two
 // factors of a previous stage)
 inline int rf_group_rows(int n) { return n > 128 ? 2 * n : 256; }
@@ -156,9 +163,11 @@ template <class T>
 void launch_augment(const AugTask<T>* tasks, int ntasks, int32_t* r, T eps_fill, int* err,
                     int maxn, hipStream_t s);
 template <class T>
-void launch_lu(const LUTask<T>* tasks, int ntasks, const int32_t* dyn, int* err, hipStream_t s);
+void launch_lu(const LUTask<T>* tasks, int ntasks, const int32_t* dyn, int* err, int maxr,
+               hipStream_t s);
 template <class T>
-void launch_trsm(const TrsmTask<T>* tasks, int ntasks, const int32_t* dyn, hipStream_t s);
+void launch_trsm(const TrsmTask<T>* tasks, int ntasks, const int32_t* dyn, int maxr, int maxcols,
+                 hipStream_t s);
 template <class T, class S>
 void launch_copy(const CTask<T, S>* tasks, int ntasks, int64_t ntiles, hipStream_t s);
 template <class T>

@@ -315,26 +315,32 @@ __device__ void structured_qr(T* R, T* C, int ldw, int n, int m, T* red) {
   (void)red;
 }
 
-// Same reduction with R packed upper triangular in LDS (column c at
-// c (c + 1) / 2) and the chunk in LDS (ld ldc), tpc threads per column
-// (tpc in {1, 2, 4}, n * tpc <= blockDim): each thread owns the chunk rows
-// t = s, s + tpc, ... of its column and partial sums meet by lane shuffles.
-// The reflector of column j+1 is formed by its owners right after their
-// update in step j, so every column costs one barrier.
+// Same reduction for one chunk of at most tpc * RPT rows held in registers:
+// thread (c, sl) = (tid / tpc, tid % tpc) holds rows t = sl + tpc u of
+// column c.  R is packed upper triangular in LDS (column c at c (c + 1) / 2);
+// the reflector vector (the chunk column j) is published in LDS by its owners
+// (double-buffered) and partial sums meet by lane shuffles.  Column j+1's
+// owners form its reflector right after their update in step j, so every
+// column costs one barrier.
 __host__ __device__ inline int pk(int c) { return c * (c + 1) / 2; }
 
-template <class T>
-__device__ void structured_qr_lds(T* Rp, T* C, int ldc, int n, int m, T* par, int tpc) {
+template <class T, int RPT>
+__device__ void structured_qr_regs(T (&cr)[RPT], T* Rp, T* vbuf, T* par, int n, int tpc) {
   const int c = threadIdx.x / tpc, sl = threadIdx.x % tpc;
+  const int ch = tpc * RPT;
   auto gsum = [&](T v) {
     for (int o = 1; o < tpc; o <<= 1) v += __shfl_xor(v, o, 64);
     return v;
   };
   // par[3*(j&1) + {0,1,2}] = tau, beta, scale of reflector j
   auto reflector = [&](int j) {
-    const T* cj = C + j * ldc;
+    T* v = vbuf + (j & 1) * ch;
     T s2 = 0;
-    for (int t = sl; t < m; t += tpc) s2 += cj[t] * cj[t];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      v[sl + tpc * u] = cr[u];
+      s2 += cr[u] * cr[u];
+    }
     s2 = gsum(s2);
     if (sl == 0) {
       const T alpha = Rp[pk(j) + j];
@@ -352,22 +358,28 @@ __device__ void structured_qr_lds(T* Rp, T* C, int ldc, int n, int m, T* par, in
       }
     }
   };
-  if (c == 0 && n > 0) reflector(0);
+  if (c == 0) reflector(0);
   __syncthreads();
   for (int j = 0; j < n; ++j) {
     const T* q = par + 3 * (j & 1);
     const T tau = q[0], beta = q[1], scale = q[2];
     if (c > j && c < n && tau != T(0)) {
-      const T* cj = C + j * ldc;
-      T* cc = C + c * ldc;
+      const T* v = vbuf + (j & 1) * ch;
+      T vv[RPT];
       T d = 0;
-      for (int t = sl; t < m; t += tpc) d += cj[t] * cc[t];
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+        vv[u] = v[sl + tpc * u];
+        d += vv[u] * cr[u];
+      }
       d = gsum(d);
       T* rjc = Rp + pk(c) + j;
-      const T tw = tau * (*rjc + scale * d);
+      const T r0 = *rjc;
+      const T tw = tau * (r0 + scale * d);
       const T f = tw * scale;
-      for (int t = sl; t < m; t += tpc) cc[t] -= f * cj[t];
-      if (sl == 0) *rjc -= tw;
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) cr[u] -= f * vv[u];
+      if (sl == 0) *rjc = r0 - tw;
     }
     if (c == j + 1 && c < n) reflector(c);
     if (c == j && sl == 0) Rp[pk(j) + j] = beta;
@@ -384,8 +396,7 @@ __device__ void structured_qr_lds(T* Rp, T* C, int ldc, int n, int m, T* par, in
 template <class T>
 __global__ __launch_bounds__(256) void k_rfactor(const RTask<T>* __restrict__ tasks,
                                                  const FillRef<T>* __restrict__ refs,
-                                                 const int32_t* __restrict__ dyn,
-                                                 int lds_elems) {
+                                                 const int32_t* __restrict__ dyn) {
   extern __shared__ char rf_smem[];
   const RTask<T> tk = tasks[blockIdx.x];
   const int n = tk.n;
@@ -393,36 +404,44 @@ __global__ __launch_bounds__(256) void k_rfactor(const RTask<T>* __restrict__ ta
   __shared__ T red[8];
   if (n == 0) return;
   // same test as the host's (which gives `work` to the others); the launch
-  // provides enough LDS for every task of the launch that passes it
-  if (n <= nthr && rf_lds_chunk(n, kLdsBytes / (int64_t)sizeof(T)) > 0) {
-    const int ch = rf_lds_chunk(n, lds_elems);
-    const int tpc = n * 4 <= nthr ? 4 : n * 2 <= nthr ? 2 : 1;
+  // provides rf_lds_bound(max order) elements of LDS
+  if (rf_in_lds<T>(n)) {
+    constexpr int RPT = kRfRows;
+    const int tpc = rf_tpc(n);
+    const int ch = tpc * RPT;
+    const int c = tid / tpc, sl = tid % tpc;
     T* Rp = reinterpret_cast<T*>(rf_smem);
-    const int ldc = ch + 1;
-    T* Cs = Rp + pk(n);
-    T* par = Cs + (int64_t)n * ldc;
+    T* vbuf = Rp + pk(n);
+    T* par = vbuf + 2 * ch;
     for (int e = tid; e < pk(n); e += nthr) Rp[e] = 0;
     __syncthreads();
+    T cr[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) cr[u] = 0;
     int fill = 0;
     for (int f = tk.fbeg; f < tk.fend; ++f) {
       const FillRef<T> fr = refs[f];
-      int c = fr.d0 >= 0 ? dyn[fr.d0] : 0;
-      while (c < fr.ncols) {
-        const int take = min(ch - fill, fr.ncols - c);
-        for (int e = tid; e < take * n; e += nthr) {
-          const int tt = e / n, col = e % n;
-          Cs[(fill + tt) + col * ldc] = fr.F[col + (int64_t)(c + tt) * fr.ld];
+      int col0 = fr.d0 >= 0 ? dyn[fr.d0] : 0;
+      while (col0 < fr.ncols) {
+        const int take = min(ch - fill, fr.ncols - col0);
+        if (c < n) {
+#pragma unroll
+          for (int u = 0; u < RPT; ++u) {
+            const int t = sl + tpc * u;
+            if (t >= fill && t < fill + take) cr[u] = fr.F[c + (int64_t)(col0 + t - fill) * fr.ld];
+          }
         }
         fill += take;
-        c += take;
-        __syncthreads();
+        col0 += take;
         if (fill == ch) {
-          structured_qr_lds(Rp, Cs, ldc, n, fill, par, tpc);
+          structured_qr_regs<T, RPT>(cr, Rp, vbuf, par, n, tpc);
+#pragma unroll
+          for (int u = 0; u < RPT; ++u) cr[u] = 0;
           fill = 0;
         }
       }
     }
-    if (fill > 0) structured_qr_lds(Rp, Cs, ldc, n, fill, par, tpc);
+    if (fill > 0) structured_qr_regs<T, RPT>(cr, Rp, vbuf, par, n, tpc);
     __syncthreads();
     for (int e = tid; e < n * n; e += nthr) {
       const int col = e % n, t = e / n;
@@ -467,9 +486,7 @@ void launch_rfactor(const RTask<T>* tasks, int ntasks, const FillRef<T>* refs,
                     const int32_t* dyn, int maxn, hipStream_t s) {
   if (ntasks <= 0) return;
   const int64_t cap = kLdsBytes / (int64_t)sizeof(T);
-  const int ch = rf_lds_chunk(maxn, cap);
-  const int64_t need =
-      rf_in_lds<T>(maxn) ? (int64_t)pk(maxn) + (int64_t)maxn * (ch + 1) + 8 : cap;
+  const int64_t need = std::min(cap, rf_lds_bound(maxn));
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)k_rfactor<T>,
@@ -477,7 +494,7 @@ void launch_rfactor(const RTask<T>* tasks, int ntasks, const FillRef<T>* refs,
     attr_set = true;
   }
   hipLaunchKernelGGL(k_rfactor<T>, dim3(ntasks), dim3(256), (size_t)(need * sizeof(T)), s, tasks,
-                     refs, dyn, (int)need);
+                     refs, dyn);
 }
 
 template <class T>
@@ -587,13 +604,32 @@ __global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ 
   __syncthreads();
 
   // ---- 5. one-sided Jacobi on the columns of M' ----
+  // Round-robin ordering: every round rotates ne/2 disjoint column pairs.  A
+  // group of LG lanes takes a pair (rows t = gl + LG u staged in registers);
+  // LG is chosen per cluster so the pairs of a round spread over the groups.
+  constexpr int RJ = 16;
   const int ne = (mp + 1) & ~1;
+  const int npair = ne / 2;
+  int LG = 8;
+  {
+    int best = 1 << 30;
+    for (int g = 8; g <= 64; g <<= 1) {
+      if ((n + g - 1) / g > RJ) continue;
+      const int passes = (npair + nthr / g - 1) / (nthr / g);
+      const int cost = passes * ((n + g - 1) / g + 2 * __builtin_ctz(g));
+      if (cost < best) {
+        best = cost;
+        LG = g;
+      }
+    }
+  }
+  const int grp = tid / LG, gl = tid % LG, ngrp = nthr / LG;
   const T tolj = eps_of<T>() * T(n);
   for (int sweep = 0; sweep < 40 && mp > 1; ++sweep) {
     if (tid == 0) sh_flag = 0;
     __syncthreads();
     for (int rnd = 0; rnd < ne - 1; ++rnd) {
-      for (int p = wave; p < ne / 2; p += 4) {
+      for (int p = grp; p < npair; p += ngrp) {
         int a, b;
         if (p == 0) {
           a = rnd;
@@ -605,34 +641,47 @@ __global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ 
         if (a >= mp || b >= mp) continue;
         T* ga = Ms + (int64_t)a * n;
         T* gb = Ms + (int64_t)b * n;
+        T x[RJ], y[RJ];
         T al = 0, be = 0, gab = 0;
-        for (int t = lane; t < n; t += 64) {
-          const T x = ga[t], y = gb[t];
-          al += x * x;
-          be += y * y;
-          gab += x * y;
+#pragma unroll
+        for (int u = 0; u < RJ; ++u) {
+          const int t = gl + LG * u;
+          x[u] = t < n ? ga[t] : T(0);
+          y[u] = t < n ? gb[t] : T(0);
+          al += x[u] * x[u];
+          be += y[u] * y[u];
+          gab += x[u] * y[u];
         }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        gab = wave_sum(gab);
+        for (int o = 1; o < LG; o <<= 1) {
+          al += __shfl_xor(al, o, 64);
+          be += __shfl_xor(be, o, 64);
+          gab += __shfl_xor(gab, o, 64);
+        }
         if (gab != T(0) && fabs(gab) > tolj * sqrt(al * be)) {
           const T zeta = (be - al) / (T(2) * gab);
           const T tt = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
           const T cs = T(1) / sqrt(T(1) + tt * tt);
           const T sn = cs * tt;
-          for (int t = lane; t < n; t += 64) {
-            const T x = ga[t], y = gb[t];
-            ga[t] = cs * x - sn * y;
-            gb[t] = sn * x + cs * y;
+#pragma unroll
+          for (int u = 0; u < RJ; ++u) {
+            const int t = gl + LG * u;
+            if (t < n) {
+              ga[t] = cs * x[u] - sn * y[u];
+              gb[t] = sn * x[u] + cs * y[u];
+            }
           }
           T* wa = Ws + (int64_t)a * mp;
           T* wb = Ws + (int64_t)b * mp;
-          for (int t = lane; t < mp; t += 64) {
-            const T u = wa[t], v = wb[t];
-            wa[t] = cs * u - sn * v;
-            wb[t] = sn * u + cs * v;
+#pragma unroll
+          for (int u = 0; u < RJ; ++u) {
+            const int t = gl + LG * u;
+            const T wu = t < mp ? wa[t] : T(0), wv = t < mp ? wb[t] : T(0);
+            if (t < mp) {
+              wa[t] = cs * wu - sn * wv;
+              wb[t] = sn * wu + cs * wv;
+            }
           }
-          if (lane == 0) sh_flag = 1;
+          if (gl == 0) sh_flag = 1;
         }
       }
       __syncthreads();
@@ -708,7 +757,9 @@ void launch_augment(const AugTask<T>* tasks, int ntasks, int32_t* r, T eps_fill,
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ __launch_bounds__(256) void k_lu(const LUTask<T>* __restrict__ tasks,
-                                            const int32_t* __restrict__ dyn, int* err) {
+                                            const int32_t* __restrict__ dyn, int* err,
+                                            int lds_elems) {
+  extern __shared__ char lu_smem[];
   const LUTask<T> tk = tasks[blockIdx.x];
   const int r = dyn[tk.ri];
   T* A = tk.A;
@@ -718,6 +769,59 @@ __global__ __launch_bounds__(256) void k_lu(const LUTask<T>* __restrict__ tasks,
   __shared__ T wv[4];
   __shared__ int wi[4];
   __shared__ int sh_p;
+  if ((int64_t)r * r <= lds_elems) {
+    // the r x r block in LDS (ld r); wave 0 takes the pivot, the row swap and
+    // the column scaling, all waves the trailing update: two barriers a column
+    T* S = reinterpret_cast<T*>(lu_smem);
+    for (int e = tid; e < r * r; e += nthr) S[e] = A[(e % r) + (int64_t)(e / r) * ld];
+    __syncthreads();
+    for (int j = 0; j < r; ++j) {
+      if (wave == 0) {
+        T best = -1;
+        int bi = j;
+        for (int i = j + lane; i < r; i += 64) {
+          const T v = fabs(S[i + j * r]);
+          if (v > best) {
+            best = v;
+            bi = i;
+          }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+          const T ov = __shfl_xor(best, o, 64);
+          const int oi = __shfl_xor(bi, o, 64);
+          if (ov > best || (ov == best && oi < bi)) {
+            best = ov;
+            bi = oi;
+          }
+        }
+        const int p = bi;
+        if (lane == 0) {
+          tk.piv[j] = p;
+          if (!(best > T(0))) atomicOr(err, 1);
+        }
+        if (p != j)
+          for (int c = lane; c < r; c += 64) {
+            const T x = S[j + c * r];
+            S[j + c * r] = S[p + c * r];
+            S[p + c * r] = x;
+          }
+        // the swap and the scaling touch different rows except through the
+        // pivot S[j][j], read after the swap by every lane (same wave)
+        const T d = S[j + j * r];
+        const T inv = d != T(0) ? T(1) / d : T(0);
+        for (int i = j + 1 + lane; i < r; i += 64) S[i + j * r] *= inv;
+      }
+      __syncthreads();
+      const int m = r - j - 1;
+      for (int e = tid; e < m * m; e += nthr) {
+        const int i = j + 1 + e % m, c = j + 1 + e / m;
+        S[i + c * r] -= S[i + j * r] * S[j + c * r];
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < r * r; e += nthr) A[(e % r) + (int64_t)(e / r) * ld] = S[e];
+    return;
+  }
   for (int j = 0; j < r; ++j) {
     T best = -1;
     int bi = j;
@@ -776,50 +880,104 @@ __global__ __launch_bounds__(256) void k_lu(const LUTask<T>* __restrict__ tasks,
 }
 
 template <class T>
-void launch_lu(const LUTask<T>* tasks, int ntasks, const int32_t* dyn, int* err, hipStream_t s) {
+void launch_lu(const LUTask<T>* tasks, int ntasks, const int32_t* dyn, int* err, int maxr,
+               hipStream_t s) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(k_lu<T>, dim3(ntasks), dim3(256), 0, s, tasks, dyn, err);
+  // blocks of order <= maxr factor in LDS when maxr^2 fits, else in place
+  const int64_t cap = kLdsBytes / (int64_t)sizeof(T);
+  const int64_t need = (int64_t)maxr * maxr <= cap ? (int64_t)maxr * maxr : 0;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_lu<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kLdsBytes);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_lu<T>, dim3(ntasks), dim3(256), (size_t)(need * sizeof(T)), s, tasks, dyn,
+                     err, (int)need);
 }
 
 // ---------------------------------------------------------------------------
-// B <- A_RR^{-1} B with the pivoted LU of the leading r x r block; one column
-// per thread, the factor staged in LDS when it fits.
+// B[0:r, c0:ncols] <- U^{-1} L^{-1} P B with the pivoted LU of the leading
+// r x r block (Algorithm 2, the multipliers of the partial LU; Algorithm 3,
+// the solves with D_RR).  Workgroup = (task, tile of tc columns): the row-
+// permuted tile sits in LDS and every step of the two column-oriented
+// substitutions updates rows x columns of the tile in parallel with one
+// barrier; row j of the result is final after backward step j and goes
+// straight to global memory.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ __launch_bounds__(64) void k_trsm(const TrsmTask<T>* __restrict__ tasks,
-                                             const int32_t* __restrict__ dyn) {
+__global__ __launch_bounds__(256) void k_trsm(const TrsmTask<T>* __restrict__ tasks,
+                                              const int32_t* __restrict__ dyn, int tc) {
+  extern __shared__ char trsm_smem[];
   const TrsmTask<T> tk = tasks[blockIdx.x];
   const int r = tk.ri >= 0 ? dyn[tk.ri] : tk.rs;
   if (r == 0) return;
   const int c0 = tk.c0d >= 0 ? dyn[tk.c0d] : tk.c0s;
+  const int cb = c0 + (int)blockIdx.y * tc;
+  if (cb >= tk.ncols) return;
+  const int ncol = min(tc, tk.ncols - cb);
+  T* Bs = reinterpret_cast<T*>(trsm_smem);  // r x ncol, ld r
+  int* perm = reinterpret_cast<int*>(Bs + (int64_t)r * tc);
   const T* LU = tk.LU;
   const int64_t ld = tk.ldlu;
-  for (int col = c0 + threadIdx.x; col < tk.ncols; col += blockDim.x) {
-    T* b = tk.B + (int64_t)col * tk.ldb;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  if (tid == 0) {
+    for (int i = 0; i < r; ++i) perm[i] = i;
     for (int j = 0; j < r; ++j) {
       const int p = tk.piv[j];
-      if (p != j) {
-        const T x = b[j];
-        b[j] = b[p];
-        b[p] = x;
-      }
+      const int x = perm[j];
+      perm[j] = perm[p];
+      perm[p] = x;
     }
-    for (int j = 0; j < r; ++j) {
-      const T bj = b[j];
-      for (int i = j + 1; i < r; ++i) b[i] -= LU[i + (int64_t)j * ld] * bj;
+  }
+  __syncthreads();
+  T* B = tk.B + (int64_t)cb * tk.ldb;
+  for (int e = tid; e < r * ncol; e += nthr) {
+    const int i = e % r, c = e / r;
+    Bs[e] = B[perm[i] + (int64_t)c * tk.ldb];
+  }
+  __syncthreads();
+  // thread = (row lane, column): rows rl, rl + RL, ...
+  const int RL = nthr / ncol;
+  const int rl = tid % RL, col = tid / RL;
+  const bool act = col < ncol;
+  T* bc = Bs + (int64_t)col * r;
+  for (int j = 0; j + 1 < r; ++j) {
+    if (act) {
+      const T bj = bc[j];
+      if (bj != T(0))
+        for (int i = j + 1 + rl; i < r; i += RL) bc[i] -= LU[i + (int64_t)j * ld] * bj;
     }
-    for (int j = r - 1; j >= 0; --j) {
-      const T bj = b[j] / LU[j + (int64_t)j * ld];
-      b[j] = bj;
-      for (int i = 0; i < j; ++i) b[i] -= LU[i + (int64_t)j * ld] * bj;
+    __syncthreads();
+  }
+  T* Bg = B + (int64_t)col * tk.ldb;
+  for (int j = r - 1; j >= 0; --j) {
+    if (act) {
+      const T xj = bc[j] / LU[j + (int64_t)j * ld];
+      if (xj != T(0))
+        for (int i = rl; i < j; i += RL) bc[i] -= LU[i + (int64_t)j * ld] * xj;
+      if (rl == j % RL) Bg[j] = xj;
     }
+    __syncthreads();
   }
 }
 
 template <class T>
-void launch_trsm(const TrsmTask<T>* tasks, int ntasks, const int32_t* dyn, hipStream_t s) {
-  if (ntasks <= 0) return;
-  hipLaunchKernelGGL(k_trsm<T>, dim3(ntasks), dim3(64), 0, s, tasks, dyn);
+void launch_trsm(const TrsmTask<T>* tasks, int ntasks, const int32_t* dyn, int maxr, int maxcols,
+                 hipStream_t s) {
+  if (ntasks <= 0 || maxr <= 0 || maxcols <= 0) return;
+  int tc = 32;
+  while (tc > 1 && (int64_t)maxr * tc * (int64_t)sizeof(T) > 96 * 1024) tc >>= 1;
+  tc = std::min(tc, maxcols);
+  const size_t lds = (size_t)maxr * tc * sizeof(T) + (size_t)maxr * sizeof(int);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_trsm<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kLdsBytes);
+    attr_set = true;
+  }
+  const int tiles = (maxcols + tc - 1) / tc;
+  hipLaunchKernelGGL(k_trsm<T>, dim3(ntasks, tiles), dim3(256), lds, s, tasks, dyn, tc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1172,8 +1330,8 @@ void launch_check_finite(const double* X, int64_t n, int* flag, hipStream_t s) {
   template void launch_rfactor<T>(const RTask<T>*, int, const FillRef<T>*, const int32_t*, int, \
                                   hipStream_t);                                               \
   template void launch_augment<T>(const AugTask<T>*, int, int32_t*, T, int*, int, hipStream_t); \
-  template void launch_lu<T>(const LUTask<T>*, int, const int32_t*, int*, hipStream_t);       \
-  template void launch_trsm<T>(const TrsmTask<T>*, int, const int32_t*, hipStream_t);         \
+  template void launch_lu<T>(const LUTask<T>*, int, const int32_t*, int*, int, hipStream_t);  \
+  template void launch_trsm<T>(const TrsmTask<T>*, int, const int32_t*, int, int, hipStream_t); \
   template void launch_copy<T, double>(const CTask<T, double>*, int, int64_t, hipStream_t);   \
   template void launch_copy<T, float>(const CTask<T, float>*, int, int64_t, hipStream_t);     \
   template void launch_fill<T>(T*, int64_t, T, hipStream_t);                                  \

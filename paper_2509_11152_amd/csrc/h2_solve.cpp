@@ -243,7 +243,11 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
         }
       }
       sb.launch(ar, s);
-      if (!trs.empty()) launch_trsm<T>(ar.put(trs), (int)trs.size(), nullptr, s);
+      if (!trs.empty()) {
+        int maxr = 1;
+        for (auto& t : trs) maxr = std::max(maxr, t.rs);
+        launch_trsm<T>(ar.put(trs), (int)trs.size(), nullptr, maxr, nrhs, s);
+      }
       gb.launch(ar, s);
     }
     // upsweep: skeleton parts of the children form the parent segments
