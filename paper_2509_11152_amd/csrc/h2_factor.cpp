@@ -12,6 +12,8 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <deque>
+#include <future>
 #include <memory>
 #include <numeric>
 
@@ -196,7 +198,6 @@ template <class T> struct Inst {
   DevArray<T> Vbuf;          // bases of the current level
   double flops = 0;
   double pflops[8] = {0}, pbytes[8] = {0};
-  std::vector<int32_t> slot;  // planning scratch: pattern entry -> output of the colour
 };
 
 template <class T> int64_t copy_tiles(int rows, int cols) {
@@ -286,6 +287,27 @@ template <class T> static int64_t rf_scratch(int n, std::vector<int> rows) {
     rows.assign(g, n);
   }
 }
+
+// Launch descriptors of one colour of one level (all instances).  They are
+// built on worker threads from the level's static structure only (window
+// starts that depend on earlier colours are read on the device through the
+// r array) and consumed in colour order by the launching thread.
+template <class T> struct ColourPlan {
+  std::vector<AugTask<T>> aug;
+  std::vector<std::vector<RTask<T>>> rst;  // per stage of the fill-row QR
+  std::vector<std::vector<FillRef<T>>> rrefs;
+  std::vector<int> rmaxn;
+  std::vector<STask<T>> sl, sr;
+  int64_t nsl = 0, nsr = 0;
+  std::vector<LUTask<T>> lus;
+  std::vector<TrsmTask<T>> trs;
+  std::vector<GOut<T>> outs;
+  std::vector<GCon<T>> cons;
+  int64_t gtiles = 0;
+};
+
+// colours planned ahead of the launches
+constexpr int kPlanAhead = 8;
 
 template <class T>
 static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double tol) {
@@ -387,20 +409,23 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     hipEvent_t ev_level0 = new_event();
     H2_HIP(hipEventRecord(ev_level0, s));
     std::vector<std::pair<int, hipEvent_t>> marks;  // (phase, event at phase end)
-    for (int c = 0; c < maxc; ++c) {
-      const auto tc = std::chrono::steady_clock::now();
-      std::vector<AugTask<T>> aug;
-      std::vector<std::vector<RTask<T>>> rst;       // per stage of the fill-row QR
-      std::vector<std::vector<FillRef<T>>> rrefs;
-      std::vector<int> rmaxn;
-      std::vector<STask<T>> sl, sr;
-      int64_t nsl = 0, nsr = 0;
-      std::vector<LUTask<T>> lus;
-      std::vector<TrsmTask<T>> trs;
-      std::vector<GOut<T>> outs;
-      std::vector<GCon<T>> cons;
-      int64_t gtiles = 0;
+    auto plan_colour = [&](int c) {
+      ColourPlan<T> cp;
+      auto& aug = cp.aug;
+      auto& rst = cp.rst;
+      auto& rrefs = cp.rrefs;
+      auto& rmaxn = cp.rmaxn;
+      auto& sl = cp.sl;
+      auto& sr = cp.sr;
+      int64_t& nsl = cp.nsl;
+      int64_t& nsr = cp.nsr;
+      auto& lus = cp.lus;
+      auto& trs = cp.trs;
+      auto& outs = cp.outs;
+      auto& cons = cp.cons;
+      int64_t& gtiles = cp.gtiles;
       int64_t woff = 0;
+      std::vector<int32_t> slotbuf;  // pattern entry -> output of the colour
       for (auto* I : act) {
         LevelPlan& P = I->F->plans[I->li];
         if (c >= P.ncolors) continue;
@@ -546,16 +571,38 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         // target (j, k) collects every i of the colour with j, k in N(i);
         // outputs in first-touch order, contributors in ascending i
         {
-          std::vector<int32_t>& slot = I->slot;
-          if ((int64_t)slot.size() < (int64_t)P.pcol.size()) slot.assign(P.pcol.size(), -1);
+          std::vector<int32_t>& slot = slotbuf;  // entries are reset after use
+          if (slot.size() != P.pcol.size()) slot.assign(P.pcol.size(), -1);
           std::vector<int64_t> ent;      // output -> pattern entry
           std::vector<int32_t> cnt;
-          std::vector<int64_t> incs;     // pattern entry of every incidence, in loop order
-          for (int i : P.members[c])
-            for (int j : P.nb[i])
-              for (int k : P.nb[i]) {
-                const int64_t e = P.find(j, k);
+          // every incidence (i, j, k) in loop order: target (j, k), operands (j, i), (i, k)
+          std::vector<int64_t> incs, incA, incB;
+          std::vector<int32_t> inci, incj;
+          std::vector<int64_t> eji, eik;
+          for (int i : P.members[c]) {
+            const std::vector<int>& nbi = P.nb[i];  // sorted
+            const size_t m = nbi.size();
+            eji.resize(m);
+            eik.resize(m);
+            for (size_t q = 0; q < m; ++q) {
+              eji[q] = P.find(nbi[q], i);
+              eik[q] = P.find(i, nbi[q]);
+            }
+            for (size_t qj = 0; qj < m; ++qj) {
+              const int j = nbi[qj];
+              // (j, k) for every k of nbi: merge the sorted pattern row of j
+              int64_t e = P.pptr[j];
+              const int64_t e1 = P.pptr[j + 1];
+              for (size_t qk = 0; qk < m; ++qk) {
+                const int k = nbi[qk];
+                while (e < e1 && P.pcol[e] < k) ++e;
+                if (e == e1 || P.pcol[e] != k)
+                  throw H2Error(H2_ERROR_FORMAT, "fill pattern misses a Schur target");
                 incs.push_back(e);
+                incA.push_back(eji[qj]);
+                incB.push_back(eik[qk]);
+                inci.push_back(i);
+                incj.push_back(j);
                 if (slot[e] < 0) {
                   slot[e] = (int32_t)ent.size();
                   ent.push_back(e);
@@ -563,28 +610,28 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
                 }
                 cnt[slot[e]]++;
               }
+            }
+          }
           std::vector<int32_t> beg(ent.size() + 1, 0);
           for (size_t o = 0; o < ent.size(); ++o) beg[o + 1] = beg[o] + cnt[o];
           const int cbase = (int)cons.size();
           cons.resize(cons.size() + incs.size());
           std::vector<int32_t> fillpos(beg.begin(), beg.end() - 1);
-          size_t q = 0;
-          for (int i : P.members[c])
-            for (int j : P.nb[i])
-              for (int k : P.nb[i]) {
-                const int64_t e = incs[q++];
-                GCon<T>& g = cons[cbase + fillpos[slot[e]]++];
-                g = GCon<T>{};
-                g.A = S.D.p + P.poff[P.find(j, i)];
-                g.lda = P.n[j];
-                g.B = S.D.p + P.poff[P.find(i, k)];
-                g.ldb = P.n[i];
-                g.k = P.n[i];
-                g.k0d = -1;
-                g.k0s = 0;
-                g.k1d = rb + i;
-                g.transA = 0;
-              }
+          for (size_t q = 0; q < incs.size(); ++q) {
+            const int64_t e = incs[q];
+            const int i = inci[q];
+            GCon<T>& g = cons[cbase + fillpos[slot[e]]++];
+            g = GCon<T>{};
+            g.A = S.D.p + P.poff[incA[q]];
+            g.lda = P.n[incj[q]];
+            g.B = S.D.p + P.poff[incB[q]];
+            g.ldb = P.n[i];
+            g.k = P.n[i];
+            g.k0d = -1;
+            g.k0s = 0;
+            g.k1d = rb + i;
+            g.transA = 0;
+          }
           for (size_t o = 0; o < ent.size(); ++o) {
             const int64_t e = ent[o];
             slot[e] = -1;
@@ -614,7 +661,34 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           }
         }
       }
-      plan_ms += ms_since(tc);
+      return cp;
+    };
+    // planners run up to kPlanAhead colours ahead of the launches
+    std::deque<std::future<ColourPlan<T>>> ahead;
+    int next_c = 0;
+    auto refill = [&]() {
+      while (next_c < maxc && (int)ahead.size() < kPlanAhead)
+        ahead.push_back(std::async(std::launch::async, plan_colour, next_c++));
+    };
+    refill();
+    for (int c = 0; c < maxc; ++c) {
+      const auto tc = std::chrono::steady_clock::now();
+      ColourPlan<T> cp = ahead.front().get();
+      ahead.pop_front();
+      refill();
+      plan_ms += ms_since(tc);  // planning the launching thread waited for
+      auto& aug = cp.aug;
+      auto& rst = cp.rst;
+      auto& rrefs = cp.rrefs;
+      auto& rmaxn = cp.rmaxn;
+      auto& sl = cp.sl;
+      auto& sr = cp.sr;
+      const int64_t nsl = cp.nsl, nsr = cp.nsr;
+      auto& lus = cp.lus;
+      auto& trs = cp.trs;
+      auto& outs = cp.outs;
+      auto& cons = cp.cons;
+      const int64_t gtiles = cp.gtiles;
       if (aug.empty()) continue;
       const T eps_fill = T(tol * act[0]->H->norm2);
       // every instance shares tol but has its own norm: fold the norm in per task

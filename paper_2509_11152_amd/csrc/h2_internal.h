@@ -142,7 +142,14 @@ struct h2_context_s {
   std::string err;
   int* d_err = nullptr;  // device error word: bit0 zero pivot, bit1 non-finite
   DescArena arena;
+  // partial tiles of split skinny GEMMs (grown on demand, after a stream sync)
+  DevArray<float> parts32;
+  DevArray<double> parts64;
 };
+
+template <class T> DevArray<T>& parts_of(h2_context_s* ctx);
+template <> inline DevArray<float>& parts_of<float>(h2_context_s* ctx) { return ctx->parts32; }
+template <> inline DevArray<double>& parts_of<double>(h2_context_s* ctx) { return ctx->parts64; }
 
 struct h2_matrix_s {
   h2_context_s* ctx = nullptr;

@@ -21,10 +21,13 @@ template <class T> struct GOut {
   int32_t m, n;         // static row / column end (m is replaced by dyn[m1d] when m1d >= 0)
   int32_t m0d, m0s;     // row start
   int32_t m1d, n0d;     // row end (dynamic), column start (dynamic)
-  int32_t n0s, pad0;    // column start (static)
+  int32_t n0s;          // column start (static)
+  int32_t nsplit;       // skinny kernel: contributor chunks (<= 1: none)
   int32_t cbeg, cend;   // contributor range
   int32_t tm, tn;       // tile counts over the static extent
   int64_t tile0;        // first tile of this output in the launch
+  int64_t part0;        // split outputs: first partial tile in the scratch
+  int64_t rtile0;       // split outputs: first tile in the reduction launch
   T alpha, beta;
 };
 
@@ -150,9 +153,17 @@ inline int rf_group_rows(int n) { return n > 128 ? 2 * n : 256; }
 inline int64_t aug_work_elems(int n) { return 3 * (int64_t)n * n + 3 * (int64_t)n + 64; }
 
 // ---- launchers (stream-ordered; descriptor arrays are device pointers) ----
+// shape 0: 64 x 64 tiles; shape 1: 64 x 16 tiles (at most 16 columns), where
+// outputs with nsplit > 1 leave their chunks' partial tiles in `parts`
+// (64 x 16 each) for launch_gemm_reduce
 template <class T>
 void launch_gemm(const GOut<T>* outs, int nouts, const GCon<T>* cons, const int32_t* dyn,
-                 int64_t ntiles, int shape, hipStream_t s);
+                 int64_t ntiles, int shape, hipStream_t s, T* parts = nullptr);
+// C = beta C + alpha (sum of the chunks' partial tiles, in chunk order) for the
+// split outputs `routs` (tiles numbered by rtile0)
+template <class T>
+void launch_gemm_reduce(const GOut<T>* routs, int nouts, const T* parts, int64_t ntiles,
+                        hipStream_t s);
 template <class T>
 void launch_strip(const STask<T>* tasks, int ntasks, const int32_t* dyn, int64_t nstrips,
                   int maxn, hipStream_t s);

@@ -145,16 +145,138 @@ __global__ __launch_bounds__(256) void k_gemm(const GOut<T>* __restrict__ outs, 
     }
 }
 
+// Skinny variant for outputs of at most 16 columns (the solves' right-hand
+// sides): the 64 x 16 tile is computed by all four waves, each taking every
+// fourth k-step with four row fragments in flight, and the waves' partial
+// tiles are summed through LDS.  An output with nsplit > 1 has its
+// contributor list cut into nsplit chunks, one workgroup each; their partial
+// tiles go to `parts` and k_gemm_reduce adds them in chunk order.
+template <class T>
+__global__ __launch_bounds__(256) void k_gemm_skinny(const GOut<T>* __restrict__ outs, int nouts,
+                                                     const GCon<T>* __restrict__ cons,
+                                                     const int32_t* __restrict__ dyn,
+                                                     T* __restrict__ parts) {
+  constexpr int TM = 64, TN = 16;
+  __shared__ T part[4][TM * TN];
+  const int64_t tile = blockIdx.x;
+  int lo = 0, hi = nouts - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (outs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+  }
+  const GOut<T>& o = outs[lo];
+  const int ns = o.nsplit > 1 ? o.nsplit : 1;
+  const int64_t trel = tile - o.tile0;
+  const int sidx = (int)(trel % ns);
+  const int64_t tt = trel / ns;
+  const int ti = (int)(tt % o.tm), tj = (int)(tt / o.tm);
+  const int m0 = o.m0d >= 0 ? dyn[o.m0d] : o.m0s;
+  const int m1 = o.m1d >= 0 ? dyn[o.m1d] : o.m;
+  const int n0 = o.n0d >= 0 ? dyn[o.n0d] : o.n0s;
+  const int n1 = o.n;
+  const int r0 = m0 + ti * TM, c0 = n0 + tj * TN;
+  if (ns == 1 && (r0 >= m1 || c0 >= n1)) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, kq = lane >> 4;
+  typename Acc<T>::type acc[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) acc[a] = (typename Acc<T>::type){0, 0, 0, 0};
+  const int col = c0 + l16;
+  const bool cok = col < n1;
+  const int ncon = o.cend - o.cbeg;
+  const int cps = (ncon + ns - 1) / ns;
+  const int cb = o.cbeg + sidx * cps;
+  const int ce = min(o.cend, cb + cps);
+  for (int ci = cb; ci < ce; ++ci) {
+    const GCon<T> g = cons[ci];
+    const int k0 = g.k0d >= 0 ? dyn[g.k0d] : g.k0s;
+    const int k1 = g.k1d >= 0 ? dyn[g.k1d] : g.k;
+    for (int kk = k0 + 4 * wave; kk < k1; kk += 16) {
+      const int kx = kk + kq;
+      const bool kok = kx < k1;
+      const T bv = (kok && cok) ? g.B[kx + (int64_t)col * g.ldb] : T(0);
+      T av[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int row = r0 + a * 16 + l16;
+        av[a] = (kok && row < m1)
+                    ? (g.transA ? g.A[kx + (int64_t)row * g.lda] : g.A[row + (int64_t)kx * g.lda])
+                    : T(0);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) acc[a] = mfma16(av[a], bv, acc[a]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) part[wave][(a * 16 + acc_row<T>(kq, i)) * TN + l16] = acc[a][i];
+  __syncthreads();
+  if (ns > 1) {
+    T* dst = parts + (o.part0 + tt * ns + sidx) * (int64_t)(TM * TN);
+    for (int e = threadIdx.x; e < TM * TN; e += blockDim.x)
+      dst[e] = part[0][e] + part[1][e] + part[2][e] + part[3][e];
+    return;
+  }
+  const T alpha = o.alpha, beta = o.beta;
+  for (int e = threadIdx.x; e < TM * TN; e += blockDim.x) {
+    const int rr = e / TN, cc = e % TN;
+    const int row = r0 + rr, cl = c0 + cc;
+    if (row < m1 && cl < n1) {
+      const T v = alpha * (part[0][e] + part[1][e] + part[2][e] + part[3][e]);
+      T* p = o.C + row + (int64_t)cl * o.ldc;
+      *p = beta == T(0) ? v : beta * *p + v;
+    }
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_gemm_reduce(const GOut<T>* __restrict__ outs, int nouts,
+                                                     const T* __restrict__ parts) {
+  constexpr int TM = 64, TN = 16;
+  const int64_t tile = blockIdx.x;
+  int lo = 0, hi = nouts - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (outs[mid].rtile0 <= tile) lo = mid; else hi = mid - 1;
+  }
+  const GOut<T>& o = outs[lo];
+  const int ns = o.nsplit;
+  const int64_t tt = tile - o.rtile0;
+  const int ti = (int)(tt % o.tm), tj = (int)(tt / o.tm);
+  const int r0 = o.m0s + ti * TM, c0 = o.n0s + tj * TN;
+  const T* src = parts + (o.part0 + tt * ns) * (int64_t)(TM * TN);
+  const T alpha = o.alpha, beta = o.beta;
+  for (int e = threadIdx.x; e < TM * TN; e += blockDim.x) {
+    const int row = r0 + e / TN, cl = c0 + e % TN;
+    if (row < o.m && cl < o.n) {
+      T sum = 0;
+      for (int q = 0; q < ns; ++q) sum += src[(int64_t)q * (TM * TN) + e];
+      T* p = o.C + row + (int64_t)cl * o.ldc;
+      const T v = alpha * sum;
+      *p = beta == T(0) ? v : beta * *p + v;
+    }
+  }
+}
+
 template <class T>
 void launch_gemm(const GOut<T>* outs, int nouts, const GCon<T>* cons, const int32_t* dyn,
-                 int64_t ntiles, int shape, hipStream_t s) {
+                 int64_t ntiles, int shape, hipStream_t s, T* parts) {
   if (ntiles <= 0 || nouts <= 0) return;
   if (shape == 0)
     hipLaunchKernelGGL((k_gemm<T, 2, 2, 2, 2>), dim3((unsigned)ntiles), dim3(256), 0, s, outs,
                        nouts, cons, dyn);
   else
-    hipLaunchKernelGGL((k_gemm<T, 4, 1, 1, 1>), dim3((unsigned)ntiles), dim3(256), 0, s, outs,
-                       nouts, cons, dyn);
+    hipLaunchKernelGGL((k_gemm_skinny<T>), dim3((unsigned)ntiles), dim3(256), 0, s, outs, nouts,
+                       cons, dyn, parts);
+}
+
+template <class T>
+void launch_gemm_reduce(const GOut<T>* routs, int nouts, const T* parts, int64_t ntiles,
+                        hipStream_t s) {
+  if (ntiles <= 0 || nouts <= 0) return;
+  hipLaunchKernelGGL((k_gemm_reduce<T>), dim3((unsigned)ntiles), dim3(256), 0, s, routs, nouts,
+                     parts);
 }
 
 // ---------------------------------------------------------------------------
@@ -962,10 +1084,95 @@ __global__ __launch_bounds__(256) void k_trsm(const TrsmTask<T>* __restrict__ ta
   }
 }
 
+// Narrow right-hand sides (the solves): one workgroup per task with the r x r
+// factor in LDS; each wave solves whole columns held in registers (row
+// lane + 64 u in x[u], r <= 256), pivot values broadcast by lane shuffles.
+template <class T>
+__global__ __launch_bounds__(256) void k_trsm_wave(const TrsmTask<T>* __restrict__ tasks,
+                                                   const int32_t* __restrict__ dyn) {
+  extern __shared__ char trw_smem[];
+  const TrsmTask<T> tk = tasks[blockIdx.x];
+  const int r = tk.ri >= 0 ? dyn[tk.ri] : tk.rs;
+  if (r == 0) return;
+  const int c0 = tk.c0d >= 0 ? dyn[tk.c0d] : tk.c0s;
+  T* S = reinterpret_cast<T*>(trw_smem);  // r x r, ld r
+  int* perm = reinterpret_cast<int*>(S + (int64_t)r * r);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  for (int e = tid; e < r * r; e += nthr) S[e] = tk.LU[(e % r) + (int64_t)(e / r) * tk.ldlu];
+  if (tid == 0) {
+    for (int i = 0; i < r; ++i) perm[i] = i;
+    for (int j = 0; j < r; ++j) {
+      const int p = tk.piv[j];
+      const int x = perm[j];
+      perm[j] = perm[p];
+      perm[p] = x;
+    }
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
+  const int nu = (r + 63) >> 6;
+  for (int col = c0 + wave; col < tk.ncols; col += 4) {
+    T* b = tk.B + (int64_t)col * tk.ldb;
+    T x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = lane + 64 * u;
+      x[u] = i < r ? b[perm[i]] : T(0);
+    }
+    // L y = P b (unit lower)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (u >= nu) break;
+      const int jn = min(64, r - 64 * u);
+      for (int jj = 0; jj < jn; ++jj) {
+        const int j = 64 * u + jj;
+        const T bj = __shfl(x[u], jj, 64);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = lane + 64 * v;
+          if (v >= u && i > j && i < r) x[v] -= S[i + j * r] * bj;
+        }
+      }
+    }
+    // U x = y
+#pragma unroll
+    for (int u = 3; u >= 0; --u) {
+      if (u >= nu) continue;
+      const int jn = min(64, r - 64 * u);
+      for (int jj = jn - 1; jj >= 0; --jj) {
+        const int j = 64 * u + jj;
+        const T xj = __shfl(x[u], jj, 64) / S[j + j * r];
+        if (lane == jj) x[u] = xj;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = lane + 64 * v;
+          if (v <= u && i < j) x[v] -= S[i + j * r] * xj;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = lane + 64 * u;
+      if (i < r) b[i] = x[u];
+    }
+  }
+}
+
 template <class T>
 void launch_trsm(const TrsmTask<T>* tasks, int ntasks, const int32_t* dyn, int maxr, int maxcols,
                  hipStream_t s) {
   if (ntasks <= 0 || maxr <= 0 || maxcols <= 0) return;
+  const size_t wlds = (size_t)maxr * maxr * sizeof(T) + (size_t)maxr * sizeof(int);
+  if (maxcols <= 16 && maxr <= 256 && wlds <= (size_t)kLdsBytes) {
+    static bool wattr = false;
+    if (!wattr) {
+      (void)hipFuncSetAttribute((const void*)k_trsm_wave<T>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+      wattr = true;
+    }
+    hipLaunchKernelGGL(k_trsm_wave<T>, dim3(ntasks), dim3(256), wlds, s, tasks, dyn);
+    return;
+  }
   int tc = 32;
   while (tc > 1 && (int64_t)maxr * tc * (int64_t)sizeof(T) > 96 * 1024) tc >>= 1;
   tc = std::min(tc, maxcols);
@@ -1171,32 +1378,42 @@ void launch_laswp(T* A, int64_t lda, int64_t ncols, int64_t j0, int nb, const in
 
 // triangular solve with an nb x nb diagonal block for ncols right-hand sides:
 // unit lower (lower_unit = 1) or upper with diagonal (lower_unit = 0)
+// Triangular solve with a diagonal block of order nb <= 64 (the dense top
+// solve and the top factorization's panels): the block is staged in LDS and
+// each wave solves one column, held one row per lane, with the pivot value
+// broadcast by a lane shuffle.
 template <class T>
-__global__ void k_trsm_block(const T* A, int64_t lda, T* B, int64_t ldb, int nb, int64_t ncols,
-                             int lower_unit) {
-  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncols;
-       c += (int64_t)gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(256) void k_trsm_block(const T* A, int64_t lda, T* B, int64_t ldb,
+                                                    int nb, int64_t ncols, int lower_unit) {
+  __shared__ T S[64 * 64];
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x)
+    S[e] = A[(e % nb) + (int64_t)(e / nb) * lda];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int64_t c = (int64_t)blockIdx.x * 4 + wave; c < ncols; c += (int64_t)gridDim.x * 4) {
     T* b = B + c * ldb;
+    T x = lane < nb ? b[lane] : T(0);
     if (lower_unit) {
       for (int j = 0; j < nb; ++j) {
-        const T bj = b[j];
-        for (int i = j + 1; i < nb; ++i) b[i] -= A[i + (int64_t)j * lda] * bj;
+        const T bj = __shfl(x, j, 64);
+        if (lane > j && lane < nb) x -= S[lane + j * nb] * bj;
       }
     } else {
       for (int j = nb - 1; j >= 0; --j) {
-        const T bj = b[j] / A[j + (int64_t)j * lda];
-        b[j] = bj;
-        for (int i = 0; i < j; ++i) b[i] -= A[i + (int64_t)j * lda] * bj;
+        const T xj = __shfl(x, j, 64) / S[j + j * nb];
+        if (lane == j) x = xj;
+        else if (lane < j) x -= S[lane + j * nb] * xj;
       }
     }
+    if (lane < nb) b[lane] = x;
   }
 }
 template <class T>
 void launch_trsm_block(const T* A, int64_t lda, T* B, int64_t ldb, int nb, int64_t ncols,
                        int lower_unit, hipStream_t s) {
   if (ncols <= 0 || nb <= 0) return;
-  const int64_t blocks = std::min<int64_t>((ncols + 63) / 64, 4096);
-  hipLaunchKernelGGL(k_trsm_block<T>, dim3((unsigned)blocks), dim3(64), 0, s, A, lda, B, ldb, nb,
+  const int64_t blocks = std::min<int64_t>((ncols + 3) / 4, 8192);
+  hipLaunchKernelGGL(k_trsm_block<T>, dim3((unsigned)blocks), dim3(256), 0, s, A, lda, B, ldb, nb,
                      ncols, lower_unit);
 }
 
@@ -1324,7 +1541,8 @@ void launch_check_finite(const double* X, int64_t n, int* flag, hipStream_t s) {
 // ---- explicit instantiations ----
 #define H2K_INST(T)                                                                           \
   template void launch_gemm<T>(const GOut<T>*, int, const GCon<T>*, const int32_t*, int64_t,  \
-                               int, hipStream_t);                                             \
+                               int, hipStream_t, T*);                                         \
+  template void launch_gemm_reduce<T>(const GOut<T>*, int, const T*, int64_t, hipStream_t);   \
   template void launch_strip<T>(const STask<T>*, int, const int32_t*, int64_t, int,           \
                                 hipStream_t);                                                 \
   template void launch_rfactor<T>(const RTask<T>*, int, const FillRef<T>*, const int32_t*, int, \

@@ -14,12 +14,17 @@ using namespace h2k;
 
 namespace {
 
+// contributor K per chunk above which a skinny output is split over workgroups
+constexpr int64_t kSplitK = 192;
+
 template <class T> struct GemmBatch {
   std::vector<GOut<T>> outs;
   std::vector<GCon<T>> cons;
-  int64_t tiles = 0;
+  int64_t tiles = 0, ptiles = 0, rtiles = 0;
   int shape, TM, TN;
-  explicit GemmBatch(int sh) : shape(sh), TM(64), TN(sh == 0 ? 64 : 16) {}
+  h2_context_s* ctx;
+  bool pending = false;
+  GemmBatch(int sh, h2_context_s* c) : shape(sh), TM(64), TN(sh == 0 ? 64 : 16), ctx(c) {}
   // begin output C[m0:m, n0:n] = beta C + alpha sum ...
   void out(T* C, int64_t ldc, int m0, int m, int n0, int n, T alpha, T beta) {
     end();
@@ -33,6 +38,7 @@ template <class T> struct GemmBatch {
     o.m1d = -1;
     o.n0d = -1;
     o.n0s = n0;
+    o.nsplit = 1;
     o.cbeg = o.cend = (int)cons.size();
     o.tm = std::max(0, (m - m0 + TM - 1) / TM);
     o.tn = std::max(0, (n - n0 + TN - 1) / TN);
@@ -57,7 +63,8 @@ template <class T> struct GemmBatch {
     cons.push_back(g);
     outs.back().cend = (int)cons.size();
   }
-  // close the current output (drops it when it has no tiles)
+  // close the current output (drops it when it has no tiles); a skinny output
+  // with a long contributor list is split into chunks of about kSplitK
   void end() {
     if (!pending) return;
     pending = false;
@@ -68,17 +75,45 @@ template <class T> struct GemmBatch {
       outs.pop_back();
       return;
     }
-    tiles += t;
+    int ns = 1;
+    if (shape == 1) {
+      int64_t ks = 0;
+      for (int c = o.cbeg; c < o.cend; ++c) ks += cons[c].k - cons[c].k0s;
+      ns = (int)std::max<int64_t>(1, std::min<int64_t>(o.cend - o.cbeg, (ks + kSplitK - 1) / kSplitK));
+    }
+    o.nsplit = ns;
+    tiles += t * ns;
+    if (ns > 1) {
+      o.part0 = ptiles;
+      ptiles += t * ns;
+      o.rtile0 = rtiles;
+      rtiles += t;
+    }
   }
   void launch(DescArena& ar, hipStream_t s) {
     end();
     if (outs.empty()) return;
-    launch_gemm<T>(ar.put(outs), (int)outs.size(), ar.put(cons), nullptr, tiles, shape, s);
+    T* parts = nullptr;
+    if (ptiles > 0) {
+      DevArray<T>& P = parts_of<T>(ctx);
+      const int64_t need = ptiles * TM * TN;
+      if (P.n < need) {
+        H2_HIP(hipStreamSynchronize(s));  // earlier launches may still read it
+        P.alloc(std::max(need, 2 * P.n), nullptr);
+      }
+      parts = P.p;
+    }
+    launch_gemm<T>(ar.put(outs), (int)outs.size(), ar.put(cons), nullptr, tiles, shape, s, parts);
+    if (rtiles > 0) {
+      std::vector<GOut<T>> routs;
+      for (auto& o : outs)
+        if (o.nsplit > 1) routs.push_back(o);
+      launch_gemm_reduce<T>(ar.put(routs), (int)routs.size(), parts, rtiles, s);
+    }
     outs.clear();
     cons.clear();
-    tiles = 0;
+    tiles = ptiles = rtiles = 0;
   }
-  bool pending = false;
 };
 
 template <class T> struct StripBatch {
@@ -197,7 +232,7 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
     for (int c = 0; c < maxc; ++c) {
       StripBatch<T> sb;
       std::vector<TrsmTask<T>> trs;
-      GemmBatch<T> gb(shape);
+      GemmBatch<T> gb(shape, ctx);
       for (auto& S : si) {
         h2_factor_s* F = S.F;
         if (li >= F->plans.size()) continue;
@@ -294,7 +329,7 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
       const int w = (int)std::min<int64_t>(nb, n - j0);
       launch_trsm_block<T>(M + j0 + j0 * n, n, b + j0, ldb2, w, nrhs, 1, s);
       if (j0 + w < n) {
-        GemmBatch<T> gb(shape);
+        GemmBatch<T> gb(shape, ctx);
         gb.out(b + j0 + w, ldb2, 0, (int)(n - j0 - w), 0, nrhs, T(-1), T(1));
         gb.con(M + (j0 + w) + j0 * n, n, 0, b + j0, ldb2, 0, w);
         gb.launch(ar, s);
@@ -304,7 +339,7 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
       const int w = (int)std::min<int64_t>(nb, n - j0);
       launch_trsm_block<T>(M + j0 + j0 * n, n, b + j0, ldb2, w, nrhs, 0, s);
       if (j0 > 0) {
-        GemmBatch<T> gb(shape);
+        GemmBatch<T> gb(shape, ctx);
         gb.out(b, ldb2, 0, (int)j0, 0, nrhs, T(-1), T(1));
         gb.con(M + j0 * n, n, 0, b + j0, ldb2, 0, w);
         gb.launch(ar, s);
@@ -341,7 +376,7 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
     for (auto& S : si)
       if (lj < S.F->plans.size()) maxc = std::max(maxc, S.F->plans[lj].ncolors);
     for (int c = maxc - 1; c >= 0; --c) {
-      GemmBatch<T> gb(shape);
+      GemmBatch<T> gb(shape, ctx);
       StripBatch<T> sb;
       for (auto& S : si) {
         h2_factor_s* F = S.F;
@@ -423,7 +458,7 @@ void matvec(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int
   const int L = H->L;
   if (H->top >= 0) {
     // leaves: xh = U^T x
-    GemmBatch<double> gb(shape);
+    GemmBatch<double> gb(shape, ctx);
     for (int q = H->lp[L]; q < H->nn; ++q) {
       if (!H->rank[q]) continue;
       gb.out(hx(q), H->rank[q], 0, H->rank[q], 0, nrhs, 1.0, 0.0);
@@ -464,7 +499,7 @@ void matvec(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int
     }
   }
   {
-    GemmBatch<double> gb(shape);
+    GemmBatch<double> gb(shape, ctx);
     for (int q = H->lp[L]; q < H->nn; ++q) {
       gb.out(yt.p + H->ib[q], N, 0, H->size(q), 0, nrhs, 1.0, 0.0);
       if (H->top >= 0 && H->rank[q])
