@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -209,6 +210,11 @@ template <class T> struct LevelStore {
   DevArray<int32_t> piv;
 };
 
+// a solve's recorded launch sequence, kept with its factor (h2_solve.cpp)
+struct SolvePlanBase {
+  virtual ~SolvePlanBase() = default;
+};
+
 struct h2_factor_s {
   h2_context_s* ctx = nullptr;
   h2_prec prec = H2_PREC_FP64;
@@ -230,4 +236,5 @@ struct h2_factor_s {
   DevArray<int32_t> top_piv;
   DevTracker tr;
   h2_stats stats{};
+  std::unique_ptr<SolvePlanBase> splan;  // last recorded solve
 };

@@ -49,14 +49,16 @@ __device__ inline float wave_sum(float v) {
   return v;
 }
 
-// block-wide sum over 256 threads (4 waves); `red` holds >= 4 values
+// block-wide sum (same order in every thread); `red` holds >= blockDim.x / 64
+// values
 template <class T> __device__ inline T block_sum(T v, T* red) {
   v = wave_sum(v);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
   __syncthreads();
   if (l == 0) red[w] = v;
   __syncthreads();
-  T s = red[0] + red[1] + red[2] + red[3];
+  T s = 0;
+  for (int i = 0; i < nw; ++i) s += red[i];
   __syncthreads();
   return s;
 }
@@ -620,15 +622,15 @@ void launch_rfactor(const RTask<T>* tasks, int ntasks, const FillRef<T>* refs,
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ tasks,
+__global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__ tasks,
                                                  int32_t* __restrict__ rout, T eps_fill,
                                                  int* err, int lds_elems) {
   extern __shared__ char aug_smem[];
   const AugTask<T> tk = tasks[blockIdx.x];
   const int n = tk.n, k = tk.k;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int wave = tid >> 6, lane = tid & 63;
-  __shared__ T red[8];
+  const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+  __shared__ T red[16];
   __shared__ int sh_flag;
   if (n == 0) {
     if (tid == 0) rout[tk.ri] = 0;
@@ -674,7 +676,7 @@ __global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ 
     }
     __syncthreads();
     if (tj != T(0)) {
-      for (int c = j + 1 + wave; c < k; c += 4) {
+      for (int c = j + 1 + wave; c < k; c += nw) {
         T* hc = Hv + (int64_t)c * n;
         T d = 0;
         for (int t = j + lane; t < n; t += 64) d += hj[t] * hc[t];
@@ -694,7 +696,7 @@ __global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ 
     const T tj = tau[j];
     if (tj == T(0)) continue;
     const T* hj = Hv + (int64_t)j * n;
-    for (int c = wave; c < mp; c += 4) {
+    for (int c = wave; c < mp; c += nw) {
       T* xc = Xp + (int64_t)c * n;
       T d = 0;
       for (int t = j + lane; t < n; t += 64) d += hj[t] * xc[t];
@@ -812,7 +814,7 @@ __global__ __launch_bounds__(256) void k_augment(const AugTask<T>* __restrict__ 
     __syncthreads();
     if (!fl) break;
   }
-  for (int c = wave; c < mp; c += 4) {
+  for (int c = wave; c < mp; c += nw) {
     T sq = 0;
     for (int t = lane; t < n; t += 64) sq += Ms[t + (int64_t)c * n] * Ms[t + (int64_t)c * n];
     sq = wave_sum(sq);
@@ -870,7 +872,7 @@ void launch_augment(const AugTask<T>* tasks, int ntasks, int32_t* r, T eps_fill,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_augment<T>, dim3(ntasks), dim3(256), (size_t)(need * sizeof(T)), s, tasks,
+  hipLaunchKernelGGL(k_augment<T>, dim3(ntasks), dim3(1024), (size_t)(need * sizeof(T)), s, tasks,
                      r, eps_fill, err, (int)need);
 }
 
@@ -1040,18 +1042,22 @@ __global__ __launch_bounds__(256) void k_trsm(const TrsmTask<T>* __restrict__ ta
   const int ncol = min(tc, tk.ncols - cb);
   T* Bs = reinterpret_cast<T*>(trsm_smem);  // r x ncol, ld r
   int* perm = reinterpret_cast<int*>(Bs + (int64_t)r * tc);
+  int* pv = perm + r;  // the pivots, staged
   const T* LU = tk.LU;
   const int64_t ld = tk.ldlu;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  if (tid == 0) {
-    for (int i = 0; i < r; ++i) perm[i] = i;
+  for (int j = tid; j < r; j += nthr) {
+    pv[j] = tk.piv[j];
+    perm[j] = j;
+  }
+  __syncthreads();
+  if (tid == 0)
     for (int j = 0; j < r; ++j) {
-      const int p = tk.piv[j];
+      const int p = pv[j];
       const int x = perm[j];
       perm[j] = perm[p];
       perm[p] = x;
     }
-  }
   __syncthreads();
   T* B = tk.B + (int64_t)cb * tk.ldb;
   for (int e = tid; e < r * ncol; e += nthr) {
@@ -1097,17 +1103,21 @@ __global__ __launch_bounds__(256) void k_trsm_wave(const TrsmTask<T>* __restrict
   const int c0 = tk.c0d >= 0 ? dyn[tk.c0d] : tk.c0s;
   T* S = reinterpret_cast<T*>(trw_smem);  // r x r, ld r
   int* perm = reinterpret_cast<int*>(S + (int64_t)r * r);
+  int* pv = perm + r;  // the pivots, staged
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int e = tid; e < r * r; e += nthr) S[e] = tk.LU[(e % r) + (int64_t)(e / r) * tk.ldlu];
-  if (tid == 0) {
-    for (int i = 0; i < r; ++i) perm[i] = i;
+  for (int j = tid; j < r; j += nthr) {
+    pv[j] = tk.piv[j];
+    perm[j] = j;
+  }
+  __syncthreads();
+  if (tid == 0)
     for (int j = 0; j < r; ++j) {
-      const int p = tk.piv[j];
+      const int p = pv[j];
       const int x = perm[j];
       perm[j] = perm[p];
       perm[p] = x;
     }
-  }
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63;
   const int nu = (r + 63) >> 6;
@@ -1162,7 +1172,7 @@ template <class T>
 void launch_trsm(const TrsmTask<T>* tasks, int ntasks, const int32_t* dyn, int maxr, int maxcols,
                  hipStream_t s) {
   if (ntasks <= 0 || maxr <= 0 || maxcols <= 0) return;
-  const size_t wlds = (size_t)maxr * maxr * sizeof(T) + (size_t)maxr * sizeof(int);
+  const size_t wlds = (size_t)maxr * maxr * sizeof(T) + 2 * (size_t)maxr * sizeof(int);
   if (maxcols <= 16 && maxr <= 256 && wlds <= (size_t)kLdsBytes) {
     static bool wattr = false;
     if (!wattr) {
@@ -1176,7 +1186,7 @@ void launch_trsm(const TrsmTask<T>* tasks, int ntasks, const int32_t* dyn, int m
   int tc = 32;
   while (tc > 1 && (int64_t)maxr * tc * (int64_t)sizeof(T) > 96 * 1024) tc >>= 1;
   tc = std::min(tc, maxcols);
-  const size_t lds = (size_t)maxr * tc * sizeof(T) + (size_t)maxr * sizeof(int);
+  const size_t lds = (size_t)maxr * tc * sizeof(T) + 2 * (size_t)maxr * sizeof(int);
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)k_trsm<T>, hipFuncAttributeMaxDynamicSharedMemorySize,

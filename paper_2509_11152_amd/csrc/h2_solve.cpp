@@ -5,6 +5,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
+#include <functional>
+#include <memory>
 
 #include "h2_driver.h"
 
@@ -17,14 +20,119 @@ namespace {
 // contributor K per chunk above which a skinny output is split over workgroups
 constexpr int64_t kSplitK = 192;
 
+// Where a solve's launches go: straight to the stream (descriptors staged
+// through the context's arena), or into a plan that later solves with the
+// same factor and number of right-hand sides replay: descriptors are appended
+// to a host image uploaded once, and every launch becomes a replay step that
+// receives the image's device address and the plan's partial-tile scratch.
+template <class T> struct Emit {
+  using Step = std::function<void(hipStream_t, const char*, T*)>;
+  h2_context_s* ctx = nullptr;
+  hipStream_t s = nullptr;
+  bool rec = false;
+  std::vector<char> img;
+  std::vector<Step> steps;
+  int64_t parts_need = 0;  // elements of partial-tile scratch the recorded steps use
+
+  template <class X> size_t stage(const std::vector<X>& v) {
+    const size_t off = (img.size() + 255) & ~(size_t)255;
+    img.resize(off + sizeof(X) * v.size());
+    std::memcpy(img.data() + off, v.data(), sizeof(X) * v.size());
+    return off;
+  }
+  void strip(const std::vector<STask<T>>& t, int64_t strips, int maxn) {
+    if (t.empty()) return;
+    const int n = (int)t.size();
+    if (!rec) {
+      launch_strip<T>(ctx->arena.put(t), n, nullptr, strips, maxn, s);
+      return;
+    }
+    const size_t o = stage(t);
+    steps.push_back([=](hipStream_t st, const char* b, T*) {
+      launch_strip<T>(reinterpret_cast<const STask<T>*>(b + o), n, nullptr, strips, maxn, st);
+    });
+  }
+  void trsm(const std::vector<TrsmTask<T>>& t, int maxr, int ncols) {
+    if (t.empty()) return;
+    const int n = (int)t.size();
+    if (!rec) {
+      launch_trsm<T>(ctx->arena.put(t), n, nullptr, maxr, ncols, s);
+      return;
+    }
+    const size_t o = stage(t);
+    steps.push_back([=](hipStream_t st, const char* b, T*) {
+      launch_trsm<T>(reinterpret_cast<const TrsmTask<T>*>(b + o), n, nullptr, maxr, ncols, st);
+    });
+  }
+  void copy(const std::vector<CTask<T, T>>& t, int64_t tiles) {
+    if (t.empty()) return;
+    const int n = (int)t.size();
+    if (!rec) {
+      launch_copy<T, T>(ctx->arena.put(t), n, tiles, s);
+      return;
+    }
+    const size_t o = stage(t);
+    steps.push_back([=](hipStream_t st, const char* b, T*) {
+      launch_copy<T, T>(reinterpret_cast<const CTask<T, T>*>(b + o), n, tiles, st);
+    });
+  }
+  void gemm(const std::vector<GOut<T>>& outs, const std::vector<GCon<T>>& cons, int64_t tiles,
+            int shape, int64_t ptiles, const std::vector<GOut<T>>& routs, int64_t rtiles) {
+    if (outs.empty()) return;
+    const int no = (int)outs.size(), nr = (int)routs.size();
+    const int64_t need = ptiles * 64 * 16;
+    if (!rec) {
+      T* parts = nullptr;
+      if (need > 0) {
+        DevArray<T>& P = parts_of<T>(ctx);
+        if (P.n < need) {
+          H2_HIP(hipStreamSynchronize(s));  // earlier launches may still read it
+          P.alloc(std::max(need, 2 * P.n), nullptr);
+        }
+        parts = P.p;
+      }
+      launch_gemm<T>(ctx->arena.put(outs), no, ctx->arena.put(cons), nullptr, tiles, shape, s,
+                     parts);
+      if (rtiles > 0) launch_gemm_reduce<T>(ctx->arena.put(routs), nr, parts, rtiles, s);
+      return;
+    }
+    const size_t oo = stage(outs), oc = stage(cons);
+    const size_t orr = rtiles > 0 ? stage(routs) : 0;
+    parts_need = std::max(parts_need, need);
+    steps.push_back([=](hipStream_t st, const char* b, T* parts) {
+      launch_gemm<T>(reinterpret_cast<const GOut<T>*>(b + oo), no,
+                     reinterpret_cast<const GCon<T>*>(b + oc), nullptr, tiles, shape, st, parts);
+      if (rtiles > 0)
+        launch_gemm_reduce<T>(reinterpret_cast<const GOut<T>*>(b + orr), nr, parts, rtiles, st);
+    });
+  }
+  void laswp(T* A, int64_t lda, int64_t ncols, int nb, const int32_t* piv) {
+    if (!rec) {
+      launch_laswp<T>(A, lda, ncols, 0, nb, piv, -1, -1, s);
+      return;
+    }
+    steps.push_back([=](hipStream_t st, const char*, T*) {
+      launch_laswp<T>(A, lda, ncols, 0, nb, piv, -1, -1, st);
+    });
+  }
+  void trsm_block(const T* A, int64_t lda, T* B, int64_t ldb, int nb, int64_t ncols, int lower) {
+    if (!rec) {
+      launch_trsm_block<T>(A, lda, B, ldb, nb, ncols, lower, s);
+      return;
+    }
+    steps.push_back([=](hipStream_t st, const char*, T*) {
+      launch_trsm_block<T>(A, lda, B, ldb, nb, ncols, lower, st);
+    });
+  }
+};
+
 template <class T> struct GemmBatch {
   std::vector<GOut<T>> outs;
   std::vector<GCon<T>> cons;
   int64_t tiles = 0, ptiles = 0, rtiles = 0;
   int shape, TM, TN;
-  h2_context_s* ctx;
   bool pending = false;
-  GemmBatch(int sh, h2_context_s* c) : shape(sh), TM(64), TN(sh == 0 ? 64 : 16), ctx(c) {}
+  explicit GemmBatch(int sh) : shape(sh), TM(64), TN(sh == 0 ? 64 : 16) {}
   // begin output C[m0:m, n0:n] = beta C + alpha sum ...
   void out(T* C, int64_t ldc, int m0, int m, int n0, int n, T alpha, T beta) {
     end();
@@ -90,26 +198,13 @@ template <class T> struct GemmBatch {
       rtiles += t;
     }
   }
-  void launch(DescArena& ar, hipStream_t s) {
+  void launch(Emit<T>& em) {
     end();
     if (outs.empty()) return;
-    T* parts = nullptr;
-    if (ptiles > 0) {
-      DevArray<T>& P = parts_of<T>(ctx);
-      const int64_t need = ptiles * TM * TN;
-      if (P.n < need) {
-        H2_HIP(hipStreamSynchronize(s));  // earlier launches may still read it
-        P.alloc(std::max(need, 2 * P.n), nullptr);
-      }
-      parts = P.p;
-    }
-    launch_gemm<T>(ar.put(outs), (int)outs.size(), ar.put(cons), nullptr, tiles, shape, s, parts);
-    if (rtiles > 0) {
-      std::vector<GOut<T>> routs;
-      for (auto& o : outs)
-        if (o.nsplit > 1) routs.push_back(o);
-      launch_gemm_reduce<T>(ar.put(routs), (int)routs.size(), parts, rtiles, s);
-    }
+    std::vector<GOut<T>> routs;
+    for (auto& o : outs)
+      if (o.nsplit > 1) routs.push_back(o);
+    em.gemm(outs, cons, tiles, shape, ptiles, routs, rtiles);
     outs.clear();
     cons.clear();
     tiles = ptiles = rtiles = 0;
@@ -137,9 +232,9 @@ template <class T> struct StripBatch {
     maxn = std::max(maxn, n);
     tasks.push_back(t);
   }
-  void launch(DescArena& ar, hipStream_t s) {
+  void launch(Emit<T>& em) {
     if (tasks.empty()) return;
-    launch_strip<T>(ar.put(tasks), (int)tasks.size(), nullptr, strips, maxn, s);
+    em.strip(tasks, strips, maxn);
     tasks.clear();
     strips = 0;
     maxn = 1;
@@ -163,9 +258,9 @@ template <class T> struct CopyB {
     tiles += ((int64_t)rows * cols + kCopyTile - 1) / kCopyTile;
     tasks.push_back(t);
   }
-  void launch(DescArena& ar, hipStream_t s) {
+  void launch(Emit<T>& em) {
     if (tasks.empty()) return;
-    launch_copy<T, T>(ar.put(tasks), (int)tasks.size(), tiles, s);
+    em.copy(tasks, tiles);
     tasks.clear();
     tiles = 0;
   }
@@ -186,44 +281,38 @@ template <class T> struct SolveInst {
   std::vector<int64_t> vlen;
 };
 
-template <class T>
-void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
-               const std::vector<const double*>& B, const std::vector<int64_t>& ldb, int nrhs,
-               const std::vector<double*>& X, const std::vector<int64_t>& ldx) {
-  hipStream_t s = ctx->stream;
-  DescArena& ar = ctx->arena;
-  ar.s = s;
-  const int shape = nrhs > 16 ? 0 : 1;
-  std::vector<SolveInst<T>> si(Fs.size());
-  size_t maxlev = 0;
-  for (size_t q = 0; q < Fs.size(); ++q) {
-    h2_factor_s* F = Fs[q];
-    SolveInst<T>& S = si[q];
-    S.F = F;
-    const size_t nlev = F->plans.size();
-    maxlev = std::max(maxlev, nlev);
-    S.vec = std::vector<DevArray<T>>(nlev + 1);
-    S.voff.resize(nlev + 1);
-    S.vlen.resize(nlev + 1);
-    for (size_t li = 0; li < nlev; ++li) {
-      const LevelPlan& P = F->plans[li];
-      S.voff[li].resize(P.nl);
-      int64_t o = 0;
-      for (int i = 0; i < P.nl; ++i) {
-        S.voff[li][i] = o;
-        o += P.n[i];
-      }
-      S.vlen[li] = o;
-      S.vec[li].alloc(std::max<int64_t>(o, 1) * nrhs, nullptr);
+// Work vectors of one instance: per level the cluster segments (leaf level
+// first), then the top vector.
+template <class T> void solve_setup(SolveInst<T>& S, h2_factor_s* F, int nrhs) {
+  S.F = F;
+  const size_t nlev = F->plans.size();
+  S.vec = std::vector<DevArray<T>>(nlev + 1);
+  S.voff.assign(nlev + 1, {});
+  S.vlen.assign(nlev + 1, 0);
+  for (size_t li = 0; li < nlev; ++li) {
+    const LevelPlan& P = F->plans[li];
+    S.voff[li].resize(P.nl);
+    int64_t o = 0;
+    for (int i = 0; i < P.nl; ++i) {
+      S.voff[li][i] = o;
+      o += P.n[i];
     }
-    S.voff[nlev] = F->top_off;
-    S.vlen[nlev] = F->n_top;
-    S.vec[nlev].alloc(std::max<int64_t>(F->n_top, 1) * nrhs, nullptr);
-    // b in tree order into the first vector
-    T* dst = S.vec[0].p;
-    const int64_t ld = S.vlen[0];
-    launch_gather_rows<T, double>(dst, ld, B[q], ldb[q], F->perm_d.p, F->N, nrhs, s);
+    S.vlen[li] = o;
+    S.vec[li].alloc(std::max<int64_t>(o, 1) * nrhs, nullptr);
   }
+  S.voff[nlev] = F->top_off;
+  S.vlen[nlev] = F->n_top;
+  S.vec[nlev].alloc(std::max<int64_t>(F->n_top, 1) * nrhs, nullptr);
+}
+
+// Algorithm 3 on the work vectors (the right-hand sides already gathered in
+// tree order into vec[0]): forward colour by colour and level by level, the
+// dense top solve, then backward.
+template <class T>
+void solve_body(Emit<T>& em, std::vector<SolveInst<T>>& si, int nrhs) {
+  const int shape = nrhs > 16 ? 0 : 1;
+  size_t maxlev = 0;
+  for (auto& S : si) maxlev = std::max(maxlev, S.F->plans.size());
   // ---- forward, level by level from the leaves ----
   for (size_t li = 0; li < maxlev; ++li) {
     int maxc = 0;
@@ -232,7 +321,7 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
     for (int c = 0; c < maxc; ++c) {
       StripBatch<T> sb;
       std::vector<TrsmTask<T>> trs;
-      GemmBatch<T> gb(shape, ctx);
+      GemmBatch<T> gb(shape);
       for (auto& S : si) {
         h2_factor_s* F = S.F;
         if (li >= F->plans.size()) continue;
@@ -277,13 +366,13 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
           a = b;
         }
       }
-      sb.launch(ar, s);
+      sb.launch(em);
       if (!trs.empty()) {
         int maxr = 1;
         for (auto& t : trs) maxr = std::max(maxr, t.rs);
-        launch_trsm<T>(ar.put(trs), (int)trs.size(), nullptr, maxr, nrhs, s);
+        em.trsm(trs, maxr, nrhs);
       }
-      gb.launch(ar, s);
+      gb.launch(em);
     }
     // upsweep: skeleton parts of the children form the parent segments
     CopyB<T> cb;
@@ -308,7 +397,7 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
         }
       }
     }
-    cb.launch(ar, s);
+    cb.launch(em);
   }
   // ---- dense top solve ----
   for (auto& S : si) {
@@ -323,26 +412,26 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
     T* b = S.vec[nx].p;
     const int64_t ldb2 = S.vlen[nx];
     T* M = topM<T>(F).p;
-    launch_laswp<T>(b, ldb2, nrhs, 0, (int)n, F->top_piv.p, -1, -1, s);
+    em.laswp(b, ldb2, nrhs, (int)n, F->top_piv.p);
     const int nb = 64;
     for (int64_t j0 = 0; j0 < n; j0 += nb) {
       const int w = (int)std::min<int64_t>(nb, n - j0);
-      launch_trsm_block<T>(M + j0 + j0 * n, n, b + j0, ldb2, w, nrhs, 1, s);
+      em.trsm_block(M + j0 + j0 * n, n, b + j0, ldb2, w, nrhs, 1);
       if (j0 + w < n) {
-        GemmBatch<T> gb(shape, ctx);
+        GemmBatch<T> gb(shape);
         gb.out(b + j0 + w, ldb2, 0, (int)(n - j0 - w), 0, nrhs, T(-1), T(1));
         gb.con(M + (j0 + w) + j0 * n, n, 0, b + j0, ldb2, 0, w);
-        gb.launch(ar, s);
+        gb.launch(em);
       }
     }
     for (int64_t j0 = ((n - 1) / nb) * nb; j0 >= 0; j0 -= nb) {
       const int w = (int)std::min<int64_t>(nb, n - j0);
-      launch_trsm_block<T>(M + j0 + j0 * n, n, b + j0, ldb2, w, nrhs, 0, s);
+      em.trsm_block(M + j0 + j0 * n, n, b + j0, ldb2, w, nrhs, 0);
       if (j0 > 0) {
-        GemmBatch<T> gb(shape, ctx);
+        GemmBatch<T> gb(shape);
         gb.out(b, ldb2, 0, (int)j0, 0, nrhs, T(-1), T(1));
         gb.con(M + j0 * n, n, 0, b + j0, ldb2, 0, w);
-        gb.launch(ar, s);
+        gb.launch(em);
       }
     }
   }
@@ -371,12 +460,12 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
         }
       }
     }
-    cb.launch(ar, s);
+    cb.launch(em);
     int maxc = 0;
     for (auto& S : si)
       if (lj < S.F->plans.size()) maxc = std::max(maxc, S.F->plans[lj].ncolors);
     for (int c = maxc - 1; c >= 0; --c) {
-      GemmBatch<T> gb(shape, ctx);
+      GemmBatch<T> gb(shape);
       StripBatch<T> sb;
       for (auto& S : si) {
         h2_factor_s* F = S.F;
@@ -400,11 +489,71 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
           sb.add(v + S.voff[lj][i], ld, st.Q.p + P.offQ[i], P.n[i], nrhs, 0, 0);
         }
       }
-      gb.launch(ar, s);
-      sb.launch(ar, s);
+      gb.launch(em);
+      sb.launch(em);
     }
   }
-  // ---- back to the original order ----
+}
+
+template <class T> struct SolvePlan : SolvePlanBase {
+  int nrhs = 0;
+  SolveInst<T> S;
+  DevArray<char> img;  // recorded descriptors
+  DevArray<T> parts;   // partial tiles of split products
+  std::vector<typename Emit<T>::Step> steps;
+};
+
+template <class T>
+void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
+               const std::vector<const double*>& B, const std::vector<int64_t>& ldb, int nrhs,
+               const std::vector<double*>& X, const std::vector<int64_t>& ldx) {
+  hipStream_t s = ctx->stream;
+  DescArena& ar = ctx->arena;
+  ar.s = s;
+  if (Fs.size() == 1) {
+    // one factor: the launch sequence depends only on the factor and nrhs, so
+    // it is recorded once and replayed by later solves
+    h2_factor_s* F = Fs[0];
+    auto* plan = dynamic_cast<SolvePlan<T>*>(F->splan.get());
+    if (!plan || plan->nrhs != nrhs) {
+      F->splan.reset();
+      auto np = std::make_unique<SolvePlan<T>>();
+      np->nrhs = nrhs;
+      solve_setup<T>(np->S, F, nrhs);
+      Emit<T> em;
+      em.ctx = ctx;
+      em.s = s;
+      em.rec = true;
+      std::vector<SolveInst<T>> one(1);
+      std::swap(one[0], np->S);
+      solve_body<T>(em, one, nrhs);
+      std::swap(one[0], np->S);
+      np->img.alloc(std::max<int64_t>((int64_t)em.img.size(), 1), nullptr);
+      if (!em.img.empty())
+        H2_HIP(hipMemcpy(np->img.p, em.img.data(), em.img.size(), hipMemcpyHostToDevice));
+      if (em.parts_need > 0) np->parts.alloc(em.parts_need, nullptr);
+      np->steps = std::move(em.steps);
+      plan = np.get();
+      F->splan = std::move(np);
+    }
+    SolveInst<T>& S = plan->S;
+    launch_gather_rows<T, double>(S.vec[0].p, S.vlen[0], B[0], ldb[0], F->perm_d.p, F->N, nrhs, s);
+    for (auto& st : plan->steps) st(s, plan->img.p, plan->parts.p);
+    launch_scatter_rows<double, T>(X[0], ldx[0], S.vec[0].p, S.vlen[0], F->perm_d.p, F->N, nrhs,
+                                   s);
+    H2_HIP(hipStreamSynchronize(s));
+    return;
+  }
+  std::vector<SolveInst<T>> si(Fs.size());
+  for (size_t q = 0; q < Fs.size(); ++q) {
+    solve_setup<T>(si[q], Fs[q], nrhs);
+    launch_gather_rows<T, double>(si[q].vec[0].p, si[q].vlen[0], B[q], ldb[q], Fs[q]->perm_d.p,
+                                  Fs[q]->N, nrhs, s);
+  }
+  Emit<T> em;
+  em.ctx = ctx;
+  em.s = s;
+  solve_body<T>(em, si, nrhs);
   for (size_t q = 0; q < Fs.size(); ++q) {
     SolveInst<T>& S = si[q];
     launch_scatter_rows<double, T>(X[q], ldx[q], S.vec[0].p, S.vlen[0], S.F->perm_d.p, S.F->N,
@@ -435,6 +584,9 @@ void matvec(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int
   DescArena& ar = ctx->arena;
   ar.s = s;
   const int shape = nrhs > 16 ? 0 : 1;
+  Emit<double> em;
+  em.ctx = ctx;
+  em.s = s;
   if (!H->mv_ready) {
     H->hat_off.assign(H->nn, 0);
     int64_t o = 0;
@@ -458,14 +610,14 @@ void matvec(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int
   const int L = H->L;
   if (H->top >= 0) {
     // leaves: xh = U^T x
-    GemmBatch<double> gb(shape, ctx);
+    GemmBatch<double> gb(shape);
     for (int q = H->lp[L]; q < H->nn; ++q) {
       if (!H->rank[q]) continue;
       gb.out(hx(q), H->rank[q], 0, H->rank[q], 0, nrhs, 1.0, 0.0);
       gb.con(d + H->offU[q], H->size(q), 1, xt.p + H->ib[q], N, 0, H->size(q));
       gb.end();
     }
-    gb.launch(ar, s);
+    gb.launch(em);
     for (int l = L - 1; l >= H->top; --l) {
       for (int q = H->lp[l]; q < H->lp[l + 1]; ++q) {
         if (!H->rank[q]) continue;
@@ -474,7 +626,7 @@ void matvec(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int
           if (H->rank[c]) gb.con(d + H->offE[c], H->rank[c], 1, hx(c), H->rank[c], 0, H->rank[c]);
         gb.end();
       }
-      gb.launch(ar, s);
+      gb.launch(em);
     }
     // couplings
     for (int q = 0; q < H->nn; ++q) {
@@ -486,7 +638,7 @@ void matvec(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int
       }
       gb.end();
     }
-    gb.launch(ar, s);
+    gb.launch(em);
     for (int l = H->top + 1; l <= L; ++l) {
       for (int q = H->lp[l]; q < H->lp[l + 1]; ++q) {
         const int p = H->parent[q];
@@ -495,11 +647,11 @@ void matvec(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int
         gb.con(d + H->offE[q], H->rank[q], 0, hy(p), H->rank[p], 0, H->rank[p]);
         gb.end();
       }
-      gb.launch(ar, s);
+      gb.launch(em);
     }
   }
   {
-    GemmBatch<double> gb(shape, ctx);
+    GemmBatch<double> gb(shape);
     for (int q = H->lp[L]; q < H->nn; ++q) {
       gb.out(yt.p + H->ib[q], N, 0, H->size(q), 0, nrhs, 1.0, 0.0);
       if (H->top >= 0 && H->rank[q])
@@ -510,7 +662,7 @@ void matvec(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int
       }
       gb.end();
     }
-    gb.launch(ar, s);
+    gb.launch(em);
   }
   launch_scatter_rows<double, double>(Y, ldy, yt.p, N, H->perm_d.p, N, nrhs, s);
   H2_HIP(hipStreamSynchronize(s));
