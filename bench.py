@@ -36,48 +36,77 @@ def parse():
     p.add_argument("--workload", default="exp3d_262144")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--construct-device", default="cuda")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run plain 256 MiB device copies (reference reading for HBM "
+                        "byte counters) and print their size")
     return p.parse_args()
 
 
-PHASES = ["augment", "project", "lu_multipliers", "schur", "close_out", "top_lu"]
-KERNEL_OF = {"augment": "k_augment", "project": "k_strip", "lu_multipliers": "k_lu + k_trsm",
-             "schur": "k_gemm (64x64 MFMA tiles)", "close_out": "k_copy",
-             "top_lu": "k_panel_lu + k_laswp + k_trsm_block + k_gemm"}
+def copy_calibration():
+    """Plain device-to-device copies of a known size: the FETCH_SIZE and
+    WRITE_SIZE counters of these dispatches give the scale factor between
+    counter readings and bytes moved."""
+    import torch
+    n = 1 << 26  # float32 elements = 256 MiB
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_dispatch": 4 * n, "dispatches": 5,
+                      "kernel": "torch elementwise copy"}), flush=True)
+
+
+# device phases of the factorization (h2_stats indices 0..7) and their kernels
+PHASES = ["fill_row_qr", "augment", "project", "lu", "multipliers", "schur", "close_out", "top_lu"]
+KERNEL_OF = {"fill_row_qr": "k_rfactor", "augment": "k_augment", "project": "k_strip",
+             "lu": "k_lu", "multipliers": "k_trsm", "schur": "k_gemm",
+             "close_out": "k_copy", "top_lu": "k_panel_lu + k_laswp + k_trsm_block + k_gemm"}
+# phases whose arithmetic runs on the vector ALU (Householder reductions,
+# Jacobi rotations, small LU and triangular solves); the others are priced
+# against MFMA or HBM by their algorithmic intensity
+ALU_PHASES = {"fill_row_qr", "augment", "lu", "multipliers"}
 
 
 def roofline(st, dt):
-    """Per-phase achieved rate from the library's algorithmic counts and the
-    device time of the phase (HIP events around its launches)."""
+    """Per-phase achieved rate: the library's algorithmic flop and byte counts
+    for the phase divided by its device time (HIP events around the phase's
+    launches on the library's stream, summed over the factorization).  Each
+    phase 0..7 is one kernel, so rate = (work per launch) / (mean launch time)."""
     peak_f = PEAK[dt]
     out = {}
     best = None
     for i, name in enumerate(PHASES):
         t = st["time_ms"][i] * 1e-3
-        fl, by = st["phase_flops"][i], st["phase_bytes"][i]
+        fl, by, nl = st["phase_flops"][i], st["phase_bytes"][i], st["launches"][i]
         if t <= 0 or (fl <= 0 and by <= 0):
             continue
         f_time = fl / (peak_f * 1e12)
         b_time = by / (HBM_PEAK * 1e9)
-        if name == "augment":
+        if name in ALU_PHASES:
             bound, ach, peak, unit = "alu", fl / t / 1e12, peak_f, "TFLOP/s"
         elif f_time >= b_time:
             bound, ach, peak, unit = "mfma", fl / t / 1e12, peak_f, "TFLOP/s"
         else:
             bound, ach, peak, unit = "hbm", by / t / 1e9, HBM_PEAK, "GB/s"
-        out[name] = {"kernel": KERNEL_OF[name], "ms": t * 1e3, "launches": st["launches"][i],
+        out[name] = {"kernel": KERNEL_OF[name], "ms": t * 1e3, "launches": nl,
+                     "ms_per_launch": t * 1e3 / max(nl, 1),
                      "flops": fl, "bytes": by, "bound": bound, "achieved": ach, "peak": peak,
                      "unit": unit, "frac": ach / peak}
         if best is None or t > out[best]["ms"] * 1e-3:
             best = name
     r = out[best]
     roof = {"bound": r["bound"], "achieved": r["achieved"], "peak": r["peak"], "unit": r["unit"],
-            "frac": r["frac"], "traffic": None, "kernel": r["kernel"], "phase": best}
+            "frac": r["frac"], "traffic": None, "kernel": r["kernel"], "phase": best,
+            "launches": r["launches"], "ms_per_launch": r["ms_per_launch"]}
     return roof, out
 
 
 def cpu_baseline(spec_name):
     """The oracle (single-threaded numpy FP64) on a bounded sample of the same
-    recipe, extrapolated linearly in N (the method is O(N) in time)."""
+    recipe (same kernel, tree, leaf size, tolerance and right-hand sides, fewer
+    points), extrapolated linearly in N (the method is O(N) in time)."""
     from threadpoolctl import threadpool_limits
 
     from h2gen import workloads
@@ -87,8 +116,7 @@ def cpu_baseline(spec_name):
 
     full = workloads.WORKLOADS[spec_name]
     sample = dict(full)
-    sample["N"] = 4096 if full["dim"] == 3 else 8192
-    sample["nrhs"] = min(full["nrhs"], 2)
+    sample["N"] = 8192 if full["dim"] == 3 else 16384
     w = workloads.make(sample)
     H = ob.parse(w["blob"])
     with threadpool_limits(1, user_api="blas"):
@@ -96,7 +124,6 @@ def cpu_baseline(spec_name):
         Fz = of.factor(H, sample["tol"])
         X, eb, its = oir.gmres_ir(H, Fz, w["B"], target=1e-12)
         dt = time.perf_counter() - t0
-    scale = (full["N"] / sample["N"]) * (full["nrhs"] / sample["nrhs"]) ** 0  # factor dominates
     return {
         "value": dt * full["N"] / sample["N"],
         "unit": "s",
@@ -105,12 +132,14 @@ def cpu_baseline(spec_name):
         "sample": f"oracle FP64 factor + GMRES-IR to 1e-12 at N={sample['N']} (same recipe, "
                   f"{sample['nrhs']} RHS) took {dt:.2f} s on 1 core; value = that x N/{sample['N']} "
                   f"(linear complexity)",
-        "_scale": scale,
     }
 
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
               "described but not built", file=sys.stderr)
@@ -206,9 +235,11 @@ def main():
         },
         "fp32_ir": {"factor_s": med(tf32), "total_s": value, "bkwd": eb32, "ir": rep32,
                     "factor_gflops": s32["factor_flops"] / med(tf32) / 1e9,
-                    "phase_ms": s32["time_ms"], "peak_bytes": s32["peak_bytes"]},
+                    "phase_ms": dict(zip(h2.PHASES, s32["time_ms"])),
+                    "peak_bytes": s32["peak_bytes"]},
         "fp64_ir": {"factor_s": med(tf64), "total_s": med(t64), "bkwd": eb64, "ir": rep64,
-                    "phase_ms": s64["time_ms"], "peak_bytes": s64["peak_bytes"]},
+                    "phase_ms": dict(zip(h2.PHASES, s64["time_ms"])),
+                    "peak_bytes": s64["peak_bytes"]},
         "fp64_plain": {"total_s": med(t64p), "bkwd": eb64p},
         "n_top": s32["n_top"],
         "roofline": roof,
@@ -218,7 +249,6 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         cb = cpu_baseline(args.workload)
-        cb.pop("_scale", None)
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 

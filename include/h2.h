@@ -175,6 +175,8 @@ typedef enum {
 h2_status h2_factor_export_matrix(h2_factor_t F, int level, h2_mat_kind kind, int i, int j,
                                   double* buf, int64_t cap, int64_t* rows, int64_t* cols);
 
+#define H2_PHASES 10
+
 typedef struct {
   int32_t levels;          /* skeletonized levels */
   int32_t max_colors;
@@ -183,12 +185,17 @@ typedef struct {
   int64_t peak_bytes;      /* high-water mark of device bytes during h2_factor */
   double factor_flops;     /* algorithmic flop count of the factorization */
   double solve_flops_per_rhs;
-  double time_ms[8];       /* device time per phase of the last h2_factor:
-                              0 augment, 1 project, 2 LU+multipliers, 3 Schur,
-                              4 close-out, 5 top LU, 6 host planning, 7 total */
-  double phase_flops[8];   /* algorithmic flops per phase (same indices) */
-  double phase_bytes[8];   /* algorithmic HBM bytes per phase (each operand once) */
-  int64_t launches[8];     /* kernel launches per phase */
+  double time_ms[H2_PHASES];     /* device time of the last h2_factor per phase, from
+                                    events around the phase's launches:
+                                    0 fill-row QR (k_rfactor), 1 augmentation and
+                                    complement (k_augment), 2 projection (k_strip),
+                                    3 LU of D_RR (k_lu), 4 multipliers (k_trsm),
+                                    5 Schur and fill-in (k_gemm), 6 close-out (k_copy),
+                                    7 dense top LU; 8 host planning the stream
+                                    waited for (wall); 9 total wall */
+  double phase_flops[H2_PHASES]; /* algorithmic flops per phase (same indices) */
+  double phase_bytes[H2_PHASES]; /* algorithmic HBM bytes per phase (each operand once) */
+  int64_t launches[H2_PHASES];   /* kernel launches per phase */
 } h2_stats;
 h2_status h2_factor_get_stats(h2_factor_t F, h2_stats* stats);
 

@@ -43,13 +43,21 @@ class _IRReport(ctypes.Structure):
                 ("max_bkwd", ctypes.c_double)]
 
 
+# factorization phases of h2_stats (indices 0..7 are device phases, one
+# kernel each; 8 = host planning the stream waited for, 9 = total wall)
+H2_PHASES = 10
+PHASES = ["fill_row_qr", "augment", "project", "lu", "multipliers", "schur", "close_out",
+          "top_lu", "host_planning", "total"]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("max_colors", ctypes.c_int32),
                 ("n_top", ctypes.c_int64), ("factor_bytes", ctypes.c_int64),
                 ("peak_bytes", ctypes.c_int64), ("factor_flops", ctypes.c_double),
-                ("solve_flops_per_rhs", ctypes.c_double), ("time_ms", ctypes.c_double * 8),
-                ("phase_flops", ctypes.c_double * 8), ("phase_bytes", ctypes.c_double * 8),
-                ("launches", ctypes.c_int64 * 8)]
+                ("solve_flops_per_rhs", ctypes.c_double), ("time_ms", ctypes.c_double * H2_PHASES),
+                ("phase_flops", ctypes.c_double * H2_PHASES),
+                ("phase_bytes", ctypes.c_double * H2_PHASES),
+                ("launches", ctypes.c_int64 * H2_PHASES)]
 
 
 class _Info(ctypes.Structure):

@@ -16,6 +16,7 @@
 #include <future>
 #include <memory>
 #include <numeric>
+#include <tuple>
 
 #include "h2_driver.h"
 
@@ -197,7 +198,7 @@ template <class T> struct Inst {
   DevArray<T> Fbuf;          // fill blocks of the current level
   DevArray<T> Vbuf;          // bases of the current level
   double flops = 0;
-  double pflops[8] = {0}, pbytes[8] = {0};
+  double pflops[H2_PHASES] = {0}, pbytes[H2_PHASES] = {0};
 };
 
 template <class T> int64_t copy_tiles(int rows, int cols) {
@@ -328,8 +329,8 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     evpool.push_back(e);
     return e;
   };
-  double phase_ms[8] = {0};
-  int64_t launches[8] = {0};
+  double phase_ms[H2_PHASES] = {0};
+  int64_t launches[H2_PHASES] = {0};
 
   // ---- leaf level plans ----
   {
@@ -406,9 +407,18 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     work.alloc(wmax, &act[0]->F->tr);
     plan_ms += ms_since(t0);
 
-    hipEvent_t ev_level0 = new_event();
-    H2_HIP(hipEventRecord(ev_level0, s));
-    std::vector<std::pair<int, hipEvent_t>> marks;  // (phase, event at phase end)
+    // (phase, start, end) events around each phase's launches
+    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> marks;
+    auto mark = [&](int ph) {
+      hipEvent_t e = new_event();
+      H2_HIP(hipEventRecord(e, s));
+      return std::make_pair(ph, e);
+    };
+    auto close_mark = [&](std::pair<int, hipEvent_t> st) {
+      hipEvent_t e = new_event();
+      H2_HIP(hipEventRecord(e, s));
+      marks.emplace_back(st.first, st.second, e);
+    };
     auto plan_colour = [&](int c) {
       ColourPlan<T> cp;
       auto& aug = cp.aug;
@@ -700,9 +710,12 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       for (auto& t : sl) maxn = std::max(maxn, t.n);
       for (auto& t : sr) maxn = std::max(maxn, t.n);
       const int32_t* dyn = rdev.p;
+      auto m0 = mark(0);
       for (size_t st = 0; st < rst.size(); ++st)
         launch_rfactor<T>(ar.put(rst[st]), (int)rst[st].size(), ar.put(rrefs[st]), rdev.p,
                           rmaxn[st], s);
+      close_mark(m0);
+      auto m1 = mark(1);
       if (same_norm) {
         launch_augment<T>(ar.put(aug), (int)aug.size(), rdev.p, eps_fill, ctx->d_err, maxn_aug,
                           s);
@@ -719,22 +732,29 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           pos += cnt;
         }
       }
-      launches[0] += (int64_t)rst.size() + (same_norm ? 1 : (int64_t)act.size());
-      launches[1] += 2;
+      close_mark(m1);
+      launches[0] += (int64_t)rst.size();
+      launches[1] += same_norm ? 1 : (int64_t)act.size();
       launches[2] += 2;
       launches[3] += 1;
-      hipEvent_t e1 = new_event();
-      H2_HIP(hipEventRecord(e1, s));
-      marks.push_back({0, e1});
-      launch_strip<T>(ar.put(sl), (int)sl.size(), dyn, nsl, maxn, s);
-      launch_strip<T>(ar.put(sr), (int)sr.size(), dyn, nsr, maxn, s);
-      hipEvent_t e2 = new_event();
-      H2_HIP(hipEventRecord(e2, s));
-      marks.push_back({1, e2});
+      launches[4] += 1;
+      launches[5] += 1;
+      {
+        // descriptors staged before the phase's first launch
+        const STask<T>* dl = ar.put(sl);
+        const STask<T>* dr = ar.put(sr);
+        auto m2 = mark(2);
+        launch_strip<T>(dl, (int)sl.size(), dyn, nsl, maxn, s);
+        launch_strip<T>(dr, (int)sr.size(), dyn, nsr, maxn, s);
+        close_mark(m2);
+      }
       {
         int maxr = 1;  // r <= n of the cluster (its D block's leading dimension)
         for (auto& t : lus) maxr = std::max(maxr, (int)t.lda);
-        launch_lu<T>(ar.put(lus), (int)lus.size(), dyn, ctx->d_err, maxr, s);
+        const LUTask<T>* dl = ar.put(lus);
+        auto m3 = mark(3);
+        launch_lu<T>(dl, (int)lus.size(), dyn, ctx->d_err, maxr, s);
+        close_mark(m3);
       }
       {
         int maxr = 1, maxcols = 1;
@@ -742,15 +762,18 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           maxr = std::max(maxr, (int)t.ldlu);
           maxcols = std::max(maxcols, t.ncols);
         }
-        launch_trsm<T>(ar.put(trs), (int)trs.size(), dyn, maxr, maxcols, s);
+        const TrsmTask<T>* dt = ar.put(trs);
+        auto m4 = mark(4);
+        launch_trsm<T>(dt, (int)trs.size(), dyn, maxr, maxcols, s);
+        close_mark(m4);
       }
-      hipEvent_t e3 = new_event();
-      H2_HIP(hipEventRecord(e3, s));
-      marks.push_back({2, e3});
-      launch_gemm<T>(ar.put(outs), (int)outs.size(), ar.put(cons), dyn, gtiles, 0, s);
-      hipEvent_t e4 = new_event();
-      H2_HIP(hipEventRecord(e4, s));
-      marks.push_back({3, e4});
+      {
+        const GOut<T>* dout = ar.put(outs);
+        const GCon<T>* dcon = ar.put(cons);
+        auto m5 = mark(5);
+        launch_gemm<T>(dout, (int)outs.size(), dcon, dyn, gtiles, 0, s);
+        close_mark(m5);
+      }
     }
     // ---- level end: read the ranks ----
     std::vector<int32_t> rh(total);
@@ -763,22 +786,21 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       if (herr & 2) throw H2Error(H2_ERROR_NUMERIC, "non-finite singular value in augmentation");
     }
     {
-      hipEvent_t prev = ev_level0;
       for (auto& m : marks) {
         float ms = 0;
-        H2_HIP(hipEventElapsedTime(&ms, prev, m.second));
-        phase_ms[m.first] += ms;
-        prev = m.second;
+        H2_HIP(hipEventElapsedTime(&ms, std::get<1>(m), std::get<2>(m)));
+        phase_ms[std::get<0>(m)] += ms;
       }
+      marks.clear();
     }
     ar.reset();
-    const auto tco = std::chrono::steady_clock::now();
     // ---- close-out into the next level (or the dense top block) ----
     // cb: skeleton blocks of near and fill entries (one source per destination
     // sub-block); cb2, launched after cb: couplings added to far-pair
     // sub-blocks and transfer blocks of the next bases.
     CopyBatch<T> cb, cb2;
     for (auto* I : act) {
+      const auto tpl = std::chrono::steady_clock::now();
       const h2_matrix_s& H = *I->H;
       h2_factor_s* F = I->F;
       LevelPlan& P = F->plans[I->li];
@@ -800,6 +822,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           // augmentation: projection of the fill row, Householder QR of its
           // transpose (f x n), SVD of the n x n factor (reported as 4 n^3)
           const double qr = f >= n ? 2 * f * n * n - 2 * n * n * n / 3 : 2 * n * f * f - 2 * f * f * f / 3;
+          const double f_qr = (4 * n * k * f + qr) * (f > 0);
           const double f_aug = (4 * n * k * f + qr + 4 * n * n * n) * (f > 0) +
                                2 * n * kt * kt - 2 * kt * kt * kt / 3 +
                                4 * (n * n * kt - n * kt * kt + kt * kt * kt / 3);
@@ -808,16 +831,22 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           const double f_schur = 2 * r * W * W;
           I->flops += f_aug + f_proj + f_lu + f_schur;
           const double b = (double)sizeof(T);
-          I->pflops[0] += f_aug;
-          I->pflops[1] += f_proj;
-          I->pflops[2] += f_lu;
-          I->pflops[3] += f_schur;
-          // compulsory bytes: fill row read; projected blocks read + written;
-          // panels read; Schur targets read + written once per contributor group
-          I->pbytes[0] += b * (n * f + n * k + n * n);
-          I->pbytes[1] += b * 2 * (n * n + n * Wn + n * f);
-          I->pbytes[2] += b * (r * r + 2 * r * W);
-          I->pbytes[3] += b * (2 * r * W + 2 * W * W);
+          I->pflops[0] += f_qr;
+          I->pflops[1] += f_aug - f_qr;
+          I->pflops[2] += f_proj;
+          I->pflops[3] += 2 * r * r * r / 3;
+          I->pflops[4] += 2 * r * r * W;
+          I->pflops[5] += f_schur;
+          // compulsory bytes: fill row read once (and the group factors
+          // written); R, V in and Q~ out; projected blocks read + written;
+          // D_RR read + written; panels read + written; Schur targets read +
+          // written once per contributor group
+          I->pbytes[0] += b * (n * f + n * n);
+          I->pbytes[1] += b * (n * n + n * k + n * n);
+          I->pbytes[2] += b * 2 * (n * n + n * Wn + n * f);
+          I->pbytes[3] += b * 2 * r * r;
+          I->pbytes[4] += b * (r * r + 2 * r * W);
+          I->pbytes[5] += b * (2 * r * W + 2 * W * W);
         }
       }
       const int lev = P.lev;
@@ -958,15 +987,21 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         I->li = F->plans.size() - 1;
         I->lev = plev;
         // Vnext/Fnext now hold the previous level's buffers: free after the copies
+        plan_ms += ms_since(tpl);
+        auto m6 = mark(6);
         cb.launch(ar, s);
         cb2.launch(ar, s);
+        close_mark(m6);
         cb = CopyBatch<T>();
         cb2 = CopyBatch<T>();
         H2_HIP(hipStreamSynchronize(s));
         ar.reset();
       } else {
+        plan_ms += ms_since(tpl);
+        auto m6 = mark(6);
         cb.launch(ar, s);
         cb2.launch(ar, s);
+        close_mark(m6);
         cb = CopyBatch<T>();
         cb2 = CopyBatch<T>();
         H2_HIP(hipStreamSynchronize(s));
@@ -978,15 +1013,12 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     }
     // the V fills must precede the E copies: the fills above were enqueued
     // before each instance's copy batch launch, so stream order holds.
-    plan_ms += ms_since(tco);
-    hipEvent_t eclose = new_event();
-    H2_HIP(hipEventRecord(eclose, s));
-    H2_HIP(hipEventSynchronize(eclose));
-    {
+    for (auto& m : marks) {
       float ms = 0;
-      H2_HIP(hipEventElapsedTime(&ms, marks.empty() ? ev_level0 : marks.back().second, eclose));
-      phase_ms[4] += ms;
+      H2_HIP(hipEventElapsedTime(&ms, std::get<1>(m), std::get<2>(m)));
+      phase_ms[std::get<0>(m)] += ms;
     }
+    marks.clear();
   }
 
   // ---- dense top factorization ----
@@ -1067,27 +1099,27 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         }
       }
       I.flops += 2.0 * (double)n * n * n / 3.0;
-      I.pflops[5] += 2.0 * (double)n * n * n / 3.0;
-      I.pbytes[5] += 2.0 * sizeof(T) * (double)n * n;
-      launches[5] += 4 * ((n + 63) / 64);
+      I.pflops[7] += 2.0 * (double)n * n * n / 3.0;
+      I.pbytes[7] += 2.0 * sizeof(T) * (double)n * n;
+      launches[7] += 4 * ((n + 63) / 64);
     }
     hipEvent_t et1 = new_event();
     H2_HIP(hipEventRecord(et1, s));
     H2_HIP(hipEventSynchronize(et1));
     float ms = 0;
     H2_HIP(hipEventElapsedTime(&ms, et0, et1));
-    phase_ms[5] += ms;
+    phase_ms[7] += ms;
     int herr = 0;
     H2_HIP(hipMemcpy(&herr, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost));
     if (herr & 1) throw H2Error(H2_ERROR_SINGULAR, "zero pivot in the dense top block");
     ar.reset();
   }
-  phase_ms[6] = plan_ms;
-  phase_ms[7] = ms_since(t_start);
+  phase_ms[8] = plan_ms;
+  phase_ms[9] = ms_since(t_start);
   for (auto e : evpool) (void)hipEventDestroy(e);
   for (auto& I : insts) {
     h2_factor_s* F = I.F;
-    for (int p = 0; p < 8; ++p) {
+    for (int p = 0; p < H2_PHASES; ++p) {
       F->stats.time_ms[p] = phase_ms[p];
       F->stats.phase_flops[p] = I.pflops[p];
       F->stats.phase_bytes[p] = I.pbytes[p];
