@@ -68,7 +68,9 @@ template <class T> __device__ inline T block_sum(T v, T* red) {
 // Workgroup = 4 waves arranged WM x WN; each wave owns FM x FN fragments of
 // 16 x 16.  Operands are read straight from global memory (L1/L2 cached) in
 // the MFMA lane layout: lane l supplies A[row l%16][k l/16] and
-// B[k l/16][col l%16]; accumulator element i is C[acc_row(l/16, i)][l%16].
+// B[k l/16][col l%16].  They enter the MFMA as (B^T, A^T), so it forms the
+// transposed block and accumulator element i is C[l%16][acc_row(l/16, i)]:
+// the epilogue's loads and stores of the column-major C are coalesced.
 // ---------------------------------------------------------------------------
 template <class T, int WM, int WN, int FM, int FN>
 __global__ __launch_bounds__(256) void k_gemm(const GOut<T>* __restrict__ outs, int nouts,
@@ -122,29 +124,32 @@ __global__ __launch_bounds__(256) void k_gemm(const GOut<T>* __restrict__ outs, 
         if (kok && col < n1) v = g.B[kx + (int64_t)col * g.ldb];
         bv[b] = v;
       }
+      // operands swapped: the accumulator holds the transposed 16 x 16 block,
+      // lane l16 owning row l16, so the column-major C is written by
+      // consecutive lanes along its contiguous dimension
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < FN; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
+        for (int b = 0; b < FN; ++b) acc[a][b] = mfma16(bv[b], av[a], acc[a][b]);
     }
   }
   const T alpha = o.alpha, beta = o.beta;
 #pragma unroll
-  for (int a = 0; a < FM; ++a)
+  for (int a = 0; a < FM; ++a) {
+    const int row = wr + a * 16 + l16;
+    if (row >= m1) continue;
 #pragma unroll
-    for (int b = 0; b < FN; ++b) {
-      const int col = wc + b * 16 + l16;
-      if (col >= n1) continue;
+    for (int b = 0; b < FN; ++b)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = wr + a * 16 + acc_row<T>(kq, i);
-        if (row < m1) {
+        const int col = wc + b * 16 + acc_row<T>(kq, i);
+        if (col < n1) {
           T* p = o.C + row + (int64_t)col * o.ldc;
           const T v = alpha * acc[a][b][i];
           *p = beta == T(0) ? v : beta * *p + v;
         }
       }
-    }
+  }
 }
 
 // Skinny variant for outputs of at most 16 columns (the solves' right-hand
