@@ -42,7 +42,12 @@ typedef enum {
   H2_ERROR_UNSUPPORTED = 8       /* a size beyond what the kernels handle */
 } h2_status;
 
-typedef enum { H2_PREC_FP64 = 0, H2_PREC_FP32 = 1 } h2_prec;
+/* Working precision of the factorization.  FP32: factor stored and computed
+ * in FP32 (MFMA with FP32 accumulation), the fill row reduced by a Householder
+ * QR (Section 3, second augmentation option).  FP32_GRAM: the same, except
+ * that the augmentation works from the FP64 Gram matrix Y Y^T of each FP32
+ * fill row and an FP64 eigendecomposition (Section 3, first option). */
+typedef enum { H2_PREC_FP64 = 0, H2_PREC_FP32 = 1, H2_PREC_FP32_GRAM = 2 } h2_prec;
 
 typedef struct h2_context_s* h2_context_t;
 typedef struct h2_matrix_s* h2_matrix_t;

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libh2rss.so")
 
 H2_PREC_FP64 = 0
 H2_PREC_FP32 = 1
+H2_PREC_FP32_GRAM = 2
 INT_SIZES, INT_RANKS, INT_COLORS, INT_FILL, INT_NTOP, INT_LEVELS = range(6)
 MAT_Q, MAT_BLOCK, MAT_TOP = range(3)
 

@@ -298,6 +298,9 @@ template <class T> struct ColourPlan {
   std::vector<std::vector<RTask<T>>> rst;  // per stage of the fill-row QR
   std::vector<std::vector<FillRef<T>>> rrefs;
   std::vector<int> rmaxn;
+  std::vector<GramTask<T>> gram;           // FP32: Gram matrices of the fill rows
+  std::vector<FillRef<T>> grefs;
+  int64_t gram_tiles = 0;
   std::vector<STask<T>> sl, sr;
   int64_t nsl = 0, nsr = 0;
   std::vector<LUTask<T>> lus;
@@ -310,9 +313,13 @@ template <class T> struct ColourPlan {
 // colours planned ahead of the launches
 constexpr int kPlanAhead = 8;
 
+
 template <class T>
 static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double tol) {
   hipStream_t s = ctx->stream;
+  // FP32 with the Gram augmentation (Section 3, first option): the fill row
+  // enters the augmentation as its FP64 Gram matrix; otherwise the QR route
+  const bool gram_mode = sizeof(T) == 4 && !insts.empty() && insts[0].F->prec == H2_PREC_FP32_GRAM;
   DescArena& ar = ctx->arena;
   ar.s = s;
   H2_HIP(hipMemsetAsync(ctx->d_err, 0, sizeof(int), s));
@@ -389,8 +396,9 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
                                               std::to_string(kMaxAugOrder));
     // augmentation workspace: max over colours of the sum of per-task scratch
     int64_t wmax = 0;
+    int64_t gwmax = 0;
     for (int c = 0; c < maxc; ++c) {
-      int64_t w = 0;
+      int64_t w = 0, gw = 0;
       for (auto* I : act) {
         LevelPlan& P = I->F->plans[I->li];
         if (c >= P.ncolors) continue;
@@ -398,13 +406,21 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           std::vector<int> rows;
           for (int64_t e = P.pptr[i]; e < P.pptr[i + 1]; ++e)
             if (P.isF[e] && P.firstc[e] < c) rows.push_back(P.n[P.pcol[e]]);
-          w += aug_work_elems(P.n[i]) + rf_scratch<T>(P.n[i], rows);
+          if (gram_mode) {
+            w += 2 * aug_work_elems(P.n[i]);  // FP64 arithmetic in FP32 units
+            gw += (int64_t)P.n[i] * P.n[i];
+          } else {
+            w += aug_work_elems(P.n[i]) + rf_scratch<T>(P.n[i], rows);
+          }
         }
       }
       wmax = std::max(wmax, w);
+      gwmax = std::max(gwmax, gw);
     }
     DevArray<T> work;
     work.alloc(wmax, &act[0]->F->tr);
+    DevArray<double> gwork;  // Gram matrices of a colour (FP32 path)
+    gwork.alloc(gwmax, &act[0]->F->tr);
     plan_ms += ms_since(t0);
 
     // (phase, start, end) events around each phase's launches
@@ -434,7 +450,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       auto& outs = cp.outs;
       auto& cons = cp.cons;
       int64_t& gtiles = cp.gtiles;
-      int64_t woff = 0;
+      int64_t woff = 0, goff = 0;
       std::vector<int32_t> slotbuf;  // pattern entry -> output of the colour
       for (auto* I : act) {
         LevelPlan& P = I->F->plans[I->li];
@@ -453,7 +469,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           at.V = I->Vbuf.p + P.offV[i];
           at.Q = S.Q.p + P.offQ[i];
           at.work = work.p + woff;
-          woff += aug_work_elems(ni);
+          woff += aug_work_elems(ni) * (gram_mode ? 2 : 1);
           at.n = ni;
           at.k = P.k[i];
           std::vector<FillRef<T>> cur;
@@ -467,10 +483,24 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
             fr.d0 = wdyn(j, false);
             cur.push_back(fr);
           }
+          if (gram_mode) {
+            GramTask<T> g{};
+            g.G = gwork.p + goff;
+            goff += (int64_t)ni * ni;
+            g.n = ni;
+            g.fbeg = (int)cp.grefs.size();
+            cp.grefs.insert(cp.grefs.end(), cur.begin(), cur.end());
+            g.fend = (int)cp.grefs.size();
+            g.tm = (ni + 63) / 64;
+            g.tile0 = cp.gram_tiles;
+            cp.gram_tiles += (int64_t)g.tm * g.tm;
+            cp.gram.push_back(g);
+            at.G = g.G;
+          }
           // stages of the tall-skinny QR: groups of fill blocks, then groups of
           // the previous stage's factors, until one factor remains
           const bool rf_glob = !rf_in_lds<T>(ni);
-          for (size_t st = 0;; ++st) {
+          for (size_t st = 0; !gram_mode; ++st) {
             std::vector<int> rows(cur.size());
             for (size_t q = 0; q < cur.size(); ++q) rows[q] = cur[q].ncols;
             const auto groups = rf_groups(rows, rf_group_rows(ni));
@@ -700,7 +730,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       auto& cons = cp.cons;
       const int64_t gtiles = cp.gtiles;
       if (aug.empty()) continue;
-      const T eps_fill = T(tol * act[0]->H->norm2);
+      const double eps_fill = tol * act[0]->H->norm2;
       // every instance shares tol but has its own norm: fold the norm in per task
       // by scaling? keep one threshold per launch group of equal norm.
       bool same_norm = true;
@@ -710,15 +740,24 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       for (auto& t : sl) maxn = std::max(maxn, t.n);
       for (auto& t : sr) maxn = std::max(maxn, t.n);
       const int32_t* dyn = rdev.p;
-      auto m0 = mark(0);
-      for (size_t st = 0; st < rst.size(); ++st)
-        launch_rfactor<T>(ar.put(rst[st]), (int)rst[st].size(), ar.put(rrefs[st]), rdev.p,
-                          rmaxn[st], s);
-      close_mark(m0);
+      const bool gram = gram_mode;
+      if (gram) {
+        const GramTask<T>* dg = ar.put(cp.gram);
+        const FillRef<T>* dr = ar.put(cp.grefs);
+        auto m0 = mark(0);
+        launch_gram<T>(dg, (int)cp.gram.size(), dr, rdev.p, cp.gram_tiles, s);
+        close_mark(m0);
+      } else {
+        auto m0 = mark(0);
+        for (size_t st = 0; st < rst.size(); ++st)
+          launch_rfactor<T>(ar.put(rst[st]), (int)rst[st].size(), ar.put(rrefs[st]), rdev.p,
+                            rmaxn[st], s);
+        close_mark(m0);
+      }
       auto m1 = mark(1);
       if (same_norm) {
         launch_augment<T>(ar.put(aug), (int)aug.size(), rdev.p, eps_fill, ctx->d_err, maxn_aug,
-                          s);
+                          gram, s);
       } else {
         // launch per instance with its own threshold
         size_t pos = 0;
@@ -727,13 +766,13 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           if (c >= P.ncolors) continue;
           const size_t cnt = P.members[c].size();
           std::vector<AugTask<T>> part(aug.begin() + pos, aug.begin() + pos + cnt);
-          launch_augment<T>(ar.put(part), (int)cnt, rdev.p, T(tol * I->H->norm2), ctx->d_err,
-                            maxn_aug, s);
+          launch_augment<T>(ar.put(part), (int)cnt, rdev.p, tol * I->H->norm2, ctx->d_err,
+                            maxn_aug, gram, s);
           pos += cnt;
         }
       }
       close_mark(m1);
-      launches[0] += (int64_t)rst.size();
+      launches[0] += gram ? 1 : (int64_t)rst.size();
       launches[1] += same_norm ? 1 : (int64_t)act.size();
       launches[2] += 2;
       launches[3] += 1;
@@ -774,6 +813,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         launch_gemm<T>(dout, (int)outs.size(), dcon, dyn, gtiles, 0, s);
         close_mark(m5);
       }
+      H2_HIP(hipGetLastError());  // a rejected launch configuration
     }
     // ---- level end: read the ranks ----
     std::vector<int32_t> rh(total);
@@ -822,8 +862,9 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           // augmentation: projection of the fill row, Householder QR of its
           // transpose (f x n), SVD of the n x n factor (reported as 4 n^3)
           const double qr = f >= n ? 2 * f * n * n - 2 * n * n * n / 3 : 2 * n * f * f - 2 * f * f * f / 3;
-          const double f_qr = (4 * n * k * f + qr) * (f > 0);
-          const double f_aug = (4 * n * k * f + qr + 4 * n * n * n) * (f > 0) +
+          // FP32 path: the Gram matrix Y Y^T (2 n^2 f) replaces the QR
+          const double f_qr = gram_mode ? 2 * n * n * f : (4 * n * k * f + qr) * (f > 0);
+          const double f_aug = (f_qr + 4 * n * n * n) * (f > 0) +
                                2 * n * kt * kt - 2 * kt * kt * kt / 3 +
                                4 * (n * n * kt - n * kt * kt + kt * kt * kt / 3);
           const double f_proj = 4 * n * n * n + 4 * n * n * Wn + 4 * n * kt * f;
@@ -841,7 +882,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           // written); R, V in and Q~ out; projected blocks read + written;
           // D_RR read + written; panels read + written; Schur targets read +
           // written once per contributor group
-          I->pbytes[0] += b * (n * f + n * n);
+          I->pbytes[0] += b * n * f + (gram_mode ? 8.0 : b) * n * n;
           I->pbytes[1] += b * (n * n + n * k + n * n);
           I->pbytes[2] += b * 2 * (n * n + n * Wn + n * f);
           I->pbytes[3] += b * 2 * r * r;
@@ -1013,6 +1054,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     }
     // the V fills must precede the E copies: the fills above were enqueued
     // before each instance's copy batch launch, so stream order holds.
+    H2_HIP(hipGetLastError());
     for (auto& m : marks) {
       float ms = 0;
       H2_HIP(hipEventElapsedTime(&ms, std::get<1>(m), std::get<2>(m)));

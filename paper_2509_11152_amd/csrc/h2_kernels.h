@@ -80,11 +80,22 @@ template <class T> struct RTask {
 template <class T> struct AugTask {
   const T* V;           // n x k input basis
   const T* Rt;          // n x n, Rt[b + a n] = R[a][b] (R upper triangular, R^T R = Y Y^T)
+  const double* G;      // or n x n FP64 Y Y^T (the FP32 factorization's Gram path)
   T* Q;                 // n x n output Q~ = [V~perp, V~]
   T* work;              // scratch
   int32_t n, k;
   int32_t ri;           // index into the r array (output)
   int32_t pad0;
+};
+
+// Gram matrix of one cluster's fill row (FP32 factorization): G = Y Y^T in
+// FP64 over the fill blocks FillRef[fbeg, fend), 64 x 64 tiles.
+template <class T> struct GramTask {
+  double* G;            // n x n, ld n
+  int32_t n;
+  int32_t fbeg, fend;
+  int32_t tm;           // tiles per dimension
+  int64_t tile0;        // first tile of this task in the launch
 };
 
 // LU with partial pivoting of the leading r x r block of A (r = dyn[ri]).
@@ -148,9 +159,10 @@ constexpr int kMaxAugOrder = 1024;
 // factors of a previous stage)
 inline int rf_group_rows(int n) { return n > 128 ? 2 * n : 256; }
 
-// scratch elements of one augmentation task of order n: V_perp (n^2),
-// reflectors or M' and W' (2 n^2), singular values, reflector scalars, ranks
-inline int64_t aug_work_elems(int n) { return 3 * (int64_t)n * n + 3 * (int64_t)n + 64; }
+// scratch elements of one augmentation task of order n: V_perp (n^2), the
+// reflectors of V (n^2), M' or M and W' (2 n^2), G V_perp (n^2), singular
+// values, reflector scalars, ranks
+inline int64_t aug_work_elems(int n) { return 5 * (int64_t)n * n + 3 * (int64_t)n + 64; }
 
 // ---- launchers (stream-ordered; descriptor arrays are device pointers) ----
 // shape 0: 64 x 64 tiles; shape 1: 64 x 16 tiles (at most 16 columns), where
@@ -171,8 +183,12 @@ template <class T>
 void launch_rfactor(const RTask<T>* tasks, int ntasks, const FillRef<T>* refs,
                     const int32_t* dyn, int maxn, hipStream_t s);
 template <class T>
-void launch_augment(const AugTask<T>* tasks, int ntasks, int32_t* r, T eps_fill, int* err,
-                    int maxn, hipStream_t s);
+void launch_gram(const GramTask<T>* tasks, int ntasks, const FillRef<T>* refs,
+                 const int32_t* dyn, int64_t ntiles, hipStream_t s);
+// gram: the tasks carry G (FP32 storage only), arithmetic in FP64
+template <class T>
+void launch_augment(const AugTask<T>* tasks, int ntasks, int32_t* r, double eps_fill, int* err,
+                    int maxn, bool gram, hipStream_t s);
 template <class T>
 void launch_lu(const LUTask<T>* tasks, int ntasks, const int32_t* dyn, int* err, int maxr,
                hipStream_t s);

@@ -626,113 +626,232 @@ void launch_rfactor(const RTask<T>* tasks, int ntasks, const FillRef<T>* refs,
                      refs, dyn);
 }
 
+// ---------------------------------------------------------------------------
+// Gram matrix of a cluster's fill row for the FP32 factorization (Section 3,
+// first augmentation option): G = Y Y^T over the active columns of the fill
+// blocks, in FP64 from the FP32 entries (their products are exact), on FP64
+// MFMA.  Workgroup = one 64 x 64 tile of G; each wave owns a 32 x 32 quarter
+// (2 x 2 fragments) and runs over every fill column, four k-steps at a time.
+// ---------------------------------------------------------------------------
 template <class T>
+__global__ __launch_bounds__(256) void k_gram(const GramTask<T>* __restrict__ tasks, int ntasks,
+                                              const FillRef<T>* __restrict__ refs,
+                                              const int32_t* __restrict__ dyn) {
+  const int64_t tile = blockIdx.x;
+  int lo = 0, hi = ntasks - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (tasks[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+  }
+  const GramTask<T>& tk = tasks[lo];
+  const int n = tk.n;
+  const int64_t t = tile - tk.tile0;
+  const int r0 = (int)(t % tk.tm) * 64, c0 = (int)(t / tk.tm) * 64;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int wr = r0 + (wave & 1) * 32, wc = c0 + (wave >> 1) * 32;
+  typename Acc<double>::type acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (typename Acc<double>::type){0, 0, 0, 0};
+  for (int f = tk.fbeg; f < tk.fend; ++f) {
+    const FillRef<T> fr = refs[f];
+    const int k0 = fr.d0 >= 0 ? dyn[fr.d0] : 0;
+    const int k1 = fr.ncols;
+    for (int kk = k0; kk < k1; kk += 16) {
+      double av[4][2], bv[4][2];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int kx = kk + 4 * s4 + kq;
+        const bool kok = kx < k1;
+        const T* col = fr.F + (int64_t)kx * fr.ld;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const int row = wr + a * 16 + l16;
+          av[s4][a] = (kok && row < n) ? double(col[row]) : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int cc = wc + b * 16 + l16;
+          bv[s4][b] = (kok && cc < n) ? double(col[cc]) : 0.0;
+        }
+      }
+      // G = Y Y^T: the "B" operand is Y^T, whose (k, col) entry is Y[col][k];
+      // operands enter swapped so the accumulator holds the transposed block
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(bv[s4][b], av[s4][a], acc[a][b]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int row = wr + a * 16 + l16;
+    if (row >= n) continue;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int cc = wc + b * 16 + acc_row<double>(kq, i);
+        if (cc < n) tk.G[row + (int64_t)cc * n] = acc[a][b][i];
+      }
+  }
+}
+
+template <class T>
+void launch_gram(const GramTask<T>* tasks, int ntasks, const FillRef<T>* refs,
+                 const int32_t* dyn, int64_t ntiles, hipStream_t s) {
+  if (ntasks <= 0 || ntiles <= 0) return;
+  hipLaunchKernelGGL(k_gram<T>, dim3((unsigned)ntiles), dim3(256), 0, s, tasks, ntasks, refs,
+                     dyn);
+}
+
+// T: storage type of V, R and Q~; A: arithmetic type.  GRAM: the fill row
+// comes as its FP64 Gram matrix G = Y Y^T instead of R (FP32 factorization),
+// and Jacobi runs on M = V_perp^T G V_perp (mp x mp), whose column norms after
+// convergence are the squared singular values.
+template <class T, class A, bool GRAM>
 __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__ tasks,
-                                                 int32_t* __restrict__ rout, T eps_fill,
+                                                 int32_t* __restrict__ rout, A eps_fill,
                                                  int* err, int lds_elems) {
   extern __shared__ char aug_smem[];
   const AugTask<T> tk = tasks[blockIdx.x];
   const int n = tk.n, k = tk.k;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
-  __shared__ T red[16];
+  __shared__ A red[16];
   __shared__ int sh_flag;
   if (n == 0) {
     if (tid == 0) rout[tk.ri] = 0;
     return;
   }
   const T* Rt = tk.Rt;                          // Rt[b + a n] = R[a][b]
-  T* G = tk.work;                               // n x n (V_perp)
-  T* Hm = G + (int64_t)n * n;                   // 2 n^2 (reflectors of V, or M' and W')
-  T* sig = Hm + 2 * (int64_t)n * n;             // n
-  T* tau = sig + n;                             // n
-  int* rank = reinterpret_cast<int*>(tau + n);  // n ints (fit in n T's)
+  const double* Gy = tk.G;                      // Gram matrix of the fill row (GRAM)
+  // global scratch, one region per phase (no phase writes where another
+  // phase's data were read): V_perp | reflectors of V | M' (or M) and W' | G V_perp
+  A* G = reinterpret_cast<A*>(tk.work);         // n x n (V_perp)
+  A* Hr = G + (int64_t)n * n;                   // n^2 (reflectors of V)
+  A* Hm = Hr + (int64_t)n * n;                  // 2 n^2 (M' or M, and W')
+  A* Hg = Hm + 2 * (int64_t)n * n;              // n^2 (G V_perp)
+  A* sig = Hg + (int64_t)n * n;                 // n
+  A* tau = sig + n;                             // n
+  int* rank = reinterpret_cast<int*>(tau + n);  // n ints (fit in n A's)
   T* Q = tk.Q;
+  // barrier; with glob, global-scratch stores of every wave are released
+  // before it and the other waves' acquired after it (agent-scope fences)
+  auto bsync = [&](bool glob) {
+    if (glob) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (glob) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  };
 
   // ---- 2. Householder QR of V (n x k): reflectors H_0 .. H_{k-1} ----
   const int mp = n - k;  // dimension of the complement of V
   const int64_t cap = lds_elems;
-  T* smem = reinterpret_cast<T*>(aug_smem);
+  A* smem = reinterpret_cast<A*>(aug_smem);
   const bool bc_lds = (int64_t)n * n + 8 <= cap;
-  T* Hv = bc_lds ? smem : Hm;                          // n x k reflectors, ld n
-  T* Xp = bc_lds ? smem + (int64_t)n * k : G;          // n x mp complement, ld n
-  for (int e = tid; e < n * k; e += nthr) Hv[e] = tk.V[e];
-  __syncthreads();
+  A* Hv = bc_lds ? smem : Hr;                          // n x k reflectors, ld n
+  A* Xp = bc_lds ? smem + (int64_t)n * k : G;          // n x mp complement, ld n
+  for (int e = tid; e < n * k; e += nthr) Hv[e] = A(tk.V[e]);
+  bsync(!bc_lds);
   for (int j = 0; j < k; ++j) {
-    T* hj = Hv + (int64_t)j * n;
-    T sq = 0;
+    A* hj = Hv + (int64_t)j * n;
+    A sq = 0;
     for (int t = j + 1 + tid; t < n; t += nthr) sq += hj[t] * hj[t];
     sq = block_sum(sq, red);
-    const T alpha = hj[j];
-    T tj = 0, beta = alpha;
-    if (sq != T(0)) {
-      const T nrm = sqrt(alpha * alpha + sq);
-      beta = alpha >= T(0) ? -nrm : nrm;
+    const A alpha = hj[j];
+    A tj = 0, beta = alpha;
+    if (sq != A(0)) {
+      const A nrm = sqrt(alpha * alpha + sq);
+      beta = alpha >= A(0) ? -nrm : nrm;
       tj = (beta - alpha) / beta;
     }
-    if (tj != T(0)) {
-      const T scale = T(1) / (alpha - beta);
+    if (tj != A(0)) {
+      const A scale = A(1) / (alpha - beta);
       for (int t = j + 1 + tid; t < n; t += nthr) hj[t] *= scale;
     }
-    __syncthreads();
+    bsync(!bc_lds);
     if (tid == 0) {
-      hj[j] = T(1);  // implicit unit of the reflector, stored explicitly
+      hj[j] = A(1);  // implicit unit of the reflector, stored explicitly
       tau[j] = tj;
     }
-    __syncthreads();
-    if (tj != T(0)) {
+    bsync(!bc_lds);
+    if (tj != A(0)) {
       for (int c = j + 1 + wave; c < k; c += nw) {
-        T* hc = Hv + (int64_t)c * n;
-        T d = 0;
+        A* hc = Hv + (int64_t)c * n;
+        A d = 0;
         for (int t = j + lane; t < n; t += 64) d += hj[t] * hc[t];
         d = wave_sum(d) * tj;
         for (int t = j + lane; t < n; t += 64) hc[t] -= d * hj[t];
       }
     }
-    __syncthreads();
+    bsync(!bc_lds);
   }
   // ---- 3. V_perp = H_0 ... H_{k-1} [0; I_mp], the complement of V ----
   for (int e = tid; e < n * mp; e += nthr) {
     const int row = e % n, c = e / n;
-    Xp[e] = (row == k + c) ? T(1) : T(0);
+    Xp[e] = (row == k + c) ? A(1) : A(0);
   }
-  __syncthreads();
+  bsync(!bc_lds);
   for (int j = k - 1; j >= 0; --j) {
-    const T tj = tau[j];
-    if (tj == T(0)) continue;
-    const T* hj = Hv + (int64_t)j * n;
+    const A tj = tau[j];
+    if (tj == A(0)) continue;
+    const A* hj = Hv + (int64_t)j * n;
     for (int c = wave; c < mp; c += nw) {
-      T* xc = Xp + (int64_t)c * n;
-      T d = 0;
+      A* xc = Xp + (int64_t)c * n;
+      A d = 0;
       for (int t = j + lane; t < n; t += 64) d += hj[t] * xc[t];
       d = wave_sum(d) * tj;
       for (int t = j + lane; t < n; t += 64) xc[t] -= d * hj[t];
     }
-    __syncthreads();
+    bsync(!bc_lds);
   }
-  T* Vp = G;  // keep V_perp in global scratch (n x mp, ld n)
+  A* Vp = G;  // keep V_perp in global scratch (n x mp, ld n)
   if (bc_lds)
     for (int e = tid; e < n * mp; e += nthr) Vp[e] = Xp[e];
-  __syncthreads();
+  bsync(true);
 
-  // ---- 4. M' = R V_perp (n x mp) and W' = I (mp x mp) ----
-  // The projected fill row is (I - V V^T) Y = V_perp V_perp^T R^T Q_Y^T, so its
-  // nonzero singular values and left singular vectors are those of M'^T
-  // mapped by V_perp: one-sided Jacobi on the columns of M' with the rotations
-  // accumulated in W' gives them (W' orthonormal to working precision).
-  const bool de_lds = (int64_t)n * mp + (int64_t)mp * mp + 8 <= cap;
-  T* Ms = de_lds ? smem : Hm;                          // n x mp, ld n
-  T* Ws = de_lds ? smem + (int64_t)n * mp : Hm + (int64_t)n * mp;  // mp x mp
-  for (int e = tid; e < n * mp; e += nthr) {
-    const int a = e % n, c = e / n;
-    T acc = 0;
-    for (int b = a; b < n; ++b) acc += Rt[b + (int64_t)a * n] * Vp[b + (int64_t)c * n];
-    Ms[e] = acc;
+  // ---- 4. the matrix whose columns Jacobi orthogonalizes, and W' = I ----
+  // R path: M' = R V_perp (n x mp).  The projected fill row is
+  // (I - V V^T) Y = V_perp V_perp^T R^T Q_Y^T, so its nonzero singular values
+  // and left singular vectors are those of M'^T mapped by V_perp.
+  // GRAM path: M = V_perp^T G V_perp (mp x mp), symmetric positive
+  // semidefinite; its right singular vectors are its eigenvectors and its
+  // singular values the squares of those of the projected fill row.
+  const int mrow = GRAM ? mp : n;  // length of the columns Jacobi rotates
+  const bool de_lds = (int64_t)mrow * mp + (int64_t)mp * mp + 8 <= cap;
+  A* Ms = de_lds ? smem : Hm;                                       // mrow x mp, ld mrow
+  A* Ws = de_lds ? smem + (int64_t)mrow * mp : Hm + (int64_t)mrow * mp;  // mp x mp
+  if constexpr (GRAM) {
+    A* GV = Hg;  // G V_perp, n x mp
+    for (int e = tid; e < n * mp; e += nthr) {
+      const int a = e % n, c = e / n;
+      A acc = 0;
+      for (int b = 0; b < n; ++b) acc += A(Gy[a + (int64_t)b * n]) * Vp[b + (int64_t)c * n];
+      GV[e] = acc;
+    }
+    bsync(true);
+    for (int e = tid; e < mp * mp; e += nthr) {
+      const int a = e % mp, c = e / mp;
+      A acc = 0;
+      for (int b = 0; b < n; ++b) acc += Vp[b + (int64_t)a * n] * GV[b + (int64_t)c * n];
+      Ms[e] = acc;
+    }
+  } else {
+    for (int e = tid; e < n * mp; e += nthr) {
+      const int a = e % n, c = e / n;
+      A acc = 0;
+      for (int b = a; b < n; ++b) acc += A(Rt[b + (int64_t)a * n]) * Vp[b + (int64_t)c * n];
+      Ms[e] = acc;
+    }
   }
-  for (int e = tid; e < mp * mp; e += nthr) Ws[e] = (e % mp == e / mp) ? T(1) : T(0);
-  __syncthreads();
+  for (int e = tid; e < mp * mp; e += nthr) Ws[e] = (e % mp == e / mp) ? A(1) : A(0);
+  bsync(!de_lds);
 
-  // ---- 5. one-sided Jacobi on the columns of M' ----
+  // ---- 5. one-sided Jacobi on the columns of M' (or M) ----
   // Round-robin ordering: every round rotates ne/2 disjoint column pairs.  A
   // group of LG lanes takes a pair (rows t = gl + LG u staged in registers);
   // LG is chosen per cluster so the pairs of a round spread over the groups.
@@ -743,9 +862,9 @@ __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__
   {
     int best = 1 << 30;
     for (int g = 8; g <= 64; g <<= 1) {
-      if ((n + g - 1) / g > RJ) continue;
+      if ((mrow + g - 1) / g > RJ) continue;
       const int passes = (npair + nthr / g - 1) / (nthr / g);
-      const int cost = passes * ((n + g - 1) / g + 2 * __builtin_ctz(g));
+      const int cost = passes * ((mrow + g - 1) / g + 2 * __builtin_ctz(g));
       if (cost < best) {
         best = cost;
         LG = g;
@@ -753,7 +872,7 @@ __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__
     }
   }
   const int grp = tid / LG, gl = tid % LG, ngrp = nthr / LG;
-  const T tolj = eps_of<T>() * T(n);
+  const A tolj = eps_of<A>() * A(mrow);
   for (int sweep = 0; sweep < 40 && mp > 1; ++sweep) {
     if (tid == 0) sh_flag = 0;
     __syncthreads();
@@ -768,15 +887,15 @@ __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__
           b = (rnd - p + ne - 1) % (ne - 1);
         }
         if (a >= mp || b >= mp) continue;
-        T* ga = Ms + (int64_t)a * n;
-        T* gb = Ms + (int64_t)b * n;
-        T x[RJ], y[RJ];
-        T al = 0, be = 0, gab = 0;
+        A* ga = Ms + (int64_t)a * mrow;
+        A* gb = Ms + (int64_t)b * mrow;
+        A x[RJ], y[RJ];
+        A al = 0, be = 0, gab = 0;
 #pragma unroll
         for (int u = 0; u < RJ; ++u) {
           const int t = gl + LG * u;
-          x[u] = t < n ? ga[t] : T(0);
-          y[u] = t < n ? gb[t] : T(0);
+          x[u] = t < mrow ? ga[t] : A(0);
+          y[u] = t < mrow ? gb[t] : A(0);
           al += x[u] * x[u];
           be += y[u] * y[u];
           gab += x[u] * y[u];
@@ -786,25 +905,25 @@ __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__
           be += __shfl_xor(be, o, 64);
           gab += __shfl_xor(gab, o, 64);
         }
-        if (gab != T(0) && fabs(gab) > tolj * sqrt(al * be)) {
-          const T zeta = (be - al) / (T(2) * gab);
-          const T tt = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
-          const T cs = T(1) / sqrt(T(1) + tt * tt);
-          const T sn = cs * tt;
+        if (gab != A(0) && fabs(gab) > tolj * sqrt(al * be)) {
+          const A zeta = (be - al) / (A(2) * gab);
+          const A tt = (zeta >= A(0) ? A(1) : A(-1)) / (fabs(zeta) + sqrt(A(1) + zeta * zeta));
+          const A cs = A(1) / sqrt(A(1) + tt * tt);
+          const A sn = cs * tt;
 #pragma unroll
           for (int u = 0; u < RJ; ++u) {
             const int t = gl + LG * u;
-            if (t < n) {
+            if (t < mrow) {
               ga[t] = cs * x[u] - sn * y[u];
               gb[t] = sn * x[u] + cs * y[u];
             }
           }
-          T* wa = Ws + (int64_t)a * mp;
-          T* wb = Ws + (int64_t)b * mp;
+          A* wa = Ws + (int64_t)a * mp;
+          A* wb = Ws + (int64_t)b * mp;
 #pragma unroll
           for (int u = 0; u < RJ; ++u) {
             const int t = gl + LG * u;
-            const T wu = t < mp ? wa[t] : T(0), wv = t < mp ? wb[t] : T(0);
+            const A wu = t < mp ? wa[t] : A(0), wv = t < mp ? wb[t] : A(0);
             if (t < mp) {
               wa[t] = cs * wu - sn * wv;
               wb[t] = sn * wu + cs * wv;
@@ -813,26 +932,27 @@ __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__
           if (gl == 0) sh_flag = 1;
         }
       }
-      __syncthreads();
+      bsync(!de_lds);
     }
     const int fl = sh_flag;
     __syncthreads();
     if (!fl) break;
   }
   for (int c = wave; c < mp; c += nw) {
-    T sq = 0;
-    for (int t = lane; t < n; t += 64) sq += Ms[t + (int64_t)c * n] * Ms[t + (int64_t)c * n];
+    A sq = 0;
+    for (int t = lane; t < mrow; t += 64) sq += Ms[t + (int64_t)c * mrow] * Ms[t + (int64_t)c * mrow];
     sq = wave_sum(sq);
-    if (lane == 0) sig[c] = sqrt(sq);
+    // R path: the column norm is sigma; GRAM path: it is sigma^2
+    if (lane == 0) sig[c] = GRAM ? sqrt(sqrt(sq)) : sqrt(sq);
   }
-  __syncthreads();
+  bsync(true);
 
   // ---- 6. selection and Q~ = [V_perp W'_rest, V, V_perp W'_sel] ----
   for (int c = tid; c < mp; c += nthr) {
     int pos = 0;
-    const T sc = sig[c];
+    const A sc = sig[c];
     for (int i = 0; i < mp; ++i) {
-      const T si = sig[i];
+      const A si = sig[i];
       pos += (si > sc) || (si == sc && i < c);
     }
     rank[c] = pos;
@@ -852,9 +972,9 @@ __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__
     const int t = e % n, c = e / n;
     const int pos = rank[c];
     const int qcol = pos < rbar ? kt - rbar + pos + r : pos - rbar;
-    T acc = 0;
+    A acc = 0;
     for (int b = 0; b < mp; ++b) acc += Vp[t + (int64_t)b * n] * Ws[b + (int64_t)c * mp];
-    Q[t + (int64_t)qcol * n] = acc;
+    Q[t + (int64_t)qcol * n] = T(acc);
   }
   for (int e = tid; e < n * k; e += nthr) Q[(int64_t)r * n + e] = tk.V[e];
   if (tid == 0) {
@@ -864,21 +984,33 @@ __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__
   }
 }
 
-template <class T>
-void launch_augment(const AugTask<T>* tasks, int ntasks, int32_t* r, T eps_fill, int* err,
-                    int maxn, hipStream_t s) {
-  if (ntasks <= 0) return;
+template <class T, class A, bool GRAM>
+static void launch_augment_t(const AugTask<T>* tasks, int ntasks, int32_t* r, A eps_fill,
+                             int* err, int maxn, hipStream_t s) {
   // LDS: the reflectors of V and V_perp (n^2), then M' and W' (at most 2 n^2)
-  const int64_t cap = kLdsBytes / (int64_t)sizeof(T);
+  const int64_t cap = kLdsBytes / (int64_t)sizeof(A);
   const int64_t need = std::min<int64_t>(cap, 2 * (int64_t)maxn * maxn + 8);
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_augment<T>,
+    (void)hipFuncSetAttribute((const void*)k_augment<T, A, GRAM>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_augment<T>, dim3(ntasks), dim3(1024), (size_t)(need * sizeof(T)), s, tasks,
-                     r, eps_fill, err, (int)need);
+  hipLaunchKernelGGL((k_augment<T, A, GRAM>), dim3(ntasks), dim3(1024),
+                     (size_t)(need * sizeof(A)), s, tasks, r, eps_fill, err, (int)need);
+}
+
+template <class T>
+void launch_augment(const AugTask<T>* tasks, int ntasks, int32_t* r, double eps_fill, int* err,
+                    int maxn, bool gram, hipStream_t s) {
+  if (ntasks <= 0) return;
+  if constexpr (sizeof(T) == 4) {
+    if (gram) {
+      launch_augment_t<T, double, true>(tasks, ntasks, r, eps_fill, err, maxn, s);
+      return;
+    }
+  }
+  launch_augment_t<T, T, false>(tasks, ntasks, r, T(eps_fill), err, maxn, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1562,7 +1694,10 @@ void launch_check_finite(const double* X, int64_t n, int* flag, hipStream_t s) {
                                 hipStream_t);                                                 \
   template void launch_rfactor<T>(const RTask<T>*, int, const FillRef<T>*, const int32_t*, int, \
                                   hipStream_t);                                               \
-  template void launch_augment<T>(const AugTask<T>*, int, int32_t*, T, int*, int, hipStream_t); \
+  template void launch_gram<T>(const GramTask<T>*, int, const FillRef<T>*, const int32_t*,    \
+                               int64_t, hipStream_t);                                         \
+  template void launch_augment<T>(const AugTask<T>*, int, int32_t*, double, int*, int, bool,  \
+                                  hipStream_t);                                               \
   template void launch_lu<T>(const LUTask<T>*, int, const int32_t*, int*, int, hipStream_t);  \
   template void launch_trsm<T>(const TrsmTask<T>*, int, const int32_t*, int, int, hipStream_t); \
   template void launch_copy<T, double>(const CTask<T, double>*, int, int64_t, hipStream_t);   \

@@ -102,14 +102,16 @@ def test_solve_fp64(lib, ctx, name, spec):
 
 
 @pytest.mark.parametrize("name,spec", [("exp2d_4096", None), ("exp3d_4096", EXP3D_4096)])
-def test_fp32_factor_with_fp64_refinement(lib, ctx, name, spec):
+@pytest.mark.parametrize("mode", ["qr", "gram"])
+def test_fp32_factor_with_fp64_refinement(lib, ctx, name, spec, mode):
     from oracle import h2ops
 
-    print(f"[gpu] fp32 + GMRES-IR {name}", flush=True)
+    print(f"[gpu] fp32 ({mode} augmentation) + GMRES-IR {name}", flush=True)
     w = workload(name, spec)
     H = gpu_matrix(lib, ctx, name, spec)
     Ho = oracle_matrix(name, spec)
-    F32 = lib.Factor(ctx, H, w["spec"]["tol"], lib.H2_PREC_FP32)
+    prec = lib.H2_PREC_FP32 if mode == "qr" else lib.H2_PREC_FP32_GRAM
+    F32 = lib.Factor(ctx, H, w["spec"]["tol"], prec)
     X, rep = lib.solve_ir(ctx, H, F32, _cuda(w["B"]), target=1e-12)
     X = X.cpu().numpy()
     eb = h2ops.backward_error(Ho, X, w["B"])
