@@ -275,18 +275,15 @@ static std::vector<std::pair<int, int>> rf_groups(const std::vector<int>& rows, 
 }
 
 // Scratch elements of the tall-skinny QR of a fill row of order n whose
-// blocks have the given widths: one n x n factor per group of every stage
-// (plus the global-memory reduction space when R does not fit in LDS).
-template <class T> static int64_t rf_scratch(int n, std::vector<int> rows) {
-  const int cap = rf_group_rows(n);
+// blocks have the given widths: one n x n factor per task of every stage
+// (groups of blocks, then pairs of factors), plus the global-memory
+// reduction space when R does not fit in LDS.
+template <class T> static int64_t rf_scratch(int n, const std::vector<int>& rows) {
   const int64_t per = (int64_t)n * n + (rf_in_lds<T>(n) ? 0 : (int64_t)(n + kAugChunk) * n);
-  int64_t tot = 0;
-  for (;;) {
-    const size_t g = rf_groups(rows, cap).size();
-    tot += (int64_t)g * per;
-    if (g == 1) return tot;
-    rows.assign(g, n);
-  }
+  int64_t g = (int64_t)rf_groups(rows, rf_group_rows(n)).size();
+  int64_t tot = g * per;
+  for (; g > 1; g = (g + 1) / 2) tot += (g / 2) * per;
+  return tot;
 }
 
 // Launch descriptors of one colour of one level (all instances).  They are
@@ -501,9 +498,17 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           // the previous stage's factors, until one factor remains
           const bool rf_glob = !rf_in_lds<T>(ni);
           for (size_t st = 0; !gram_mode; ++st) {
-            std::vector<int> rows(cur.size());
-            for (size_t q = 0; q < cur.size(); ++q) rows[q] = cur[q].ncols;
-            const auto groups = rf_groups(rows, rf_group_rows(ni));
+            // stage 0: groups of fill blocks; later stages: pairs of factors
+            // (an odd one passes to the next stage as it is)
+            std::vector<std::pair<int, int>> groups;
+            if (st == 0) {
+              std::vector<int> rows(cur.size());
+              for (size_t q = 0; q < cur.size(); ++q) rows[q] = cur[q].ncols;
+              groups = rf_groups(rows, rf_group_rows(ni));
+            } else {
+              for (int q = 0; q < (int)cur.size(); q += 2)
+                groups.push_back({q, std::min(q + 2, (int)cur.size())});
+            }
             if (rst.size() <= st) {
               rst.emplace_back();
               rrefs.emplace_back();
@@ -511,7 +516,12 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
             }
             std::vector<FillRef<T>> next;
             for (const auto& g : groups) {
+              if (st > 0 && g.second - g.first == 1) {
+                next.push_back(cur[g.first]);
+                continue;
+              }
               RTask<T> t{};
+              t.tri = st > 0 ? 1 : 0;
               t.out = work.p + woff;
               woff += (int64_t)ni * ni;
               if (rf_glob) {

@@ -72,7 +72,8 @@ template <class T> struct RTask {
   T* work;              // (n + kAugChunk) x n, used only when R does not fit in LDS
   int32_t n;
   int32_t fbeg, fend;   // FillRef range
-  int32_t pad0;
+  int32_t tri;          // 1: every block is an n x n factor of a previous stage
+                        // (upper triangular in the layout of `out`)
 };
 
 // Basis augmentation + complement of one cluster (Algorithm 2, first loop),
@@ -135,29 +136,31 @@ constexpr int kAugChunk = 64;
 
 constexpr int kLdsBytes = 150 * 1024;  // dynamic LDS a workgroup may request
 
-// Fill-row reduction in LDS: tpc threads per column (4, 2 or 1 by order),
-// kRfRows chunk rows per thread in registers; LDS holds R packed upper
-// triangular (n (n + 1) / 2), the current reflector (double-buffered chunk
-// column) and the reflector parameters.
-constexpr int kRfRows = 32;
-__host__ __device__ inline int rf_tpc(int n) { return n <= 64 ? 4 : n <= 128 ? 2 : 1; }
-__host__ __device__ inline int64_t rf_lds_elems(int n) {
-  return (int64_t)n * (n + 1) / 2 + 2 * (int64_t)rf_tpc(n) * kRfRows + 8;
+// Fill-row reduction in LDS, one lane per column: wave w of the workgroup
+// owns columns 64 w .. 64 w + 63 and every lane holds rf_chunk<T>() rows of
+// its column in registers.  LDS holds R packed upper triangular by rows (row
+// j at rf_rowoff(j, n), entries j..n-1) after two reflector buffers.
+template <class T> __host__ __device__ constexpr int rf_chunk() { return sizeof(T) == 4 ? 64 : 32; }
+__host__ __device__ inline int64_t rf_rowoff(int j, int n) {
+  return (int64_t)j * n - (int64_t)j * (j - 1) / 2;
+}
+// one reflector buffer: the chunk column, its squared norm, R[j][j] (padded
+// to 16 bytes)
+template <class T> __host__ __device__ constexpr int rf_xstride() {
+  return rf_chunk<T>() + (int)(16 / sizeof(T));
+}
+template <class T> __host__ __device__ inline int64_t rf_lds_elems(int n) {
+  return (int64_t)n * (n + 1) / 2 + 2 * (int64_t)rf_xstride<T>();
 }
 // whether the fill-row reduction of order n runs in LDS (else in `work`)
 template <class T> __host__ __device__ inline bool rf_in_lds(int n) {
-  return n <= 256 && rf_lds_elems(n) <= kLdsBytes / (int64_t)sizeof(T);
-}
-// LDS elements enough for every in-LDS order <= maxn
-__host__ __device__ inline int64_t rf_lds_bound(int maxn) {
-  return (int64_t)maxn * (maxn + 1) / 2 + 8 * (int64_t)kRfRows + 8;
+  return n <= 256 && rf_lds_elems<T>(n) <= kLdsBytes / (int64_t)sizeof(T);
 }
 // largest cluster order the augmentation supports (lanes x registers of a
 // Jacobi pair)
 constexpr int kMaxAugOrder = 1024;
-// rows of Y^T one reduction group takes (whole fill blocks, at least two
-// factors of a previous stage)
-inline int rf_group_rows(int n) { return n > 128 ? 2 * n : 256; }
+// rows of Y^T one first-stage group takes (whole fill blocks, at least one)
+inline int rf_group_rows(int) { return 256; }
 
 // scratch elements of one augmentation task of order n: V_perp (n^2), the
 // reflectors of V (n^2), M' or M and W' (2 n^2), G V_perp (n^2), singular

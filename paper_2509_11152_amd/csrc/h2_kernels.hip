@@ -36,6 +36,17 @@ template <class T> __device__ inline int acc_row(int kq, int i);
 template <> __device__ inline int acc_row<double>(int kq, int i) { return kq + 4 * i; }
 template <> __device__ inline int acc_row<float>(int kq, int i) { return 4 * kq + i; }
 
+// Global-memory view of a pointer taken from a task descriptor (device
+// allocations only): accesses through it are global, not flat, so they do
+// not count against the LDS wait counter.
+template <class T> using gptr = __attribute__((address_space(1))) T*;
+template <class T> __device__ inline gptr<T> gmem(T* p) { return (gptr<T>)p; }
+
+// 16-byte vector of T (one LDS b128 access)
+template <class T> struct Vec16;
+template <> struct Vec16<float> { typedef float __attribute__((ext_vector_type(4))) type; };
+template <> struct Vec16<double> { typedef double __attribute__((ext_vector_type(2))) type; };
+
 template <class T> __device__ inline T eps_of();
 template <> __device__ inline double eps_of<double>() { return DBL_EPSILON; }
 template <> __device__ inline float eps_of<float>() { return FLT_EPSILON; }
@@ -428,7 +439,7 @@ __device__ void structured_qr(T* R, T* C, int ldw, int n, int m, T* red) {
       for (int t = threadIdx.x; t < m; t += blockDim.x) C[t + (int64_t)j * ldw] *= scale;
       if (threadIdx.x == 0) R[j + (int64_t)j * ldw] = sh_beta;
       __syncthreads();
-      for (int c = j + 1 + wave; c < n; c += 4) {
+      for (int c = j + 1 + wave; c < n; c += (int)(blockDim.x >> 6)) {
         T* Cc = C + (int64_t)c * ldw;
         const T* vj = C + (int64_t)j * ldw;
         T part = 0;
@@ -444,76 +455,45 @@ __device__ void structured_qr(T* R, T* C, int ldw, int n, int m, T* red) {
   (void)red;
 }
 
-// Same reduction for one chunk of at most tpc * RPT rows held in registers:
-// thread (c, sl) = (tid / tpc, tid % tpc) holds rows t = sl + tpc u of
-// column c.  R is packed upper triangular in LDS (column c at c (c + 1) / 2);
-// the reflector vector (the chunk column j) is published in LDS by its owners
-// (double-buffered) and partial sums meet by lane shuffles.  Column j+1's
-// owners form its reflector right after their update in step j, so every
-// column costs one barrier.
-__host__ __device__ inline int pk(int c) { return c * (c + 1) / 2; }
-
+// Load the next chunk of at most RPT rows of Y^T (fill columns) into the
+// registers of the lanes that own columns: cr[u] = Y[col][row u].  (f, c0) is
+// the position in the FillRef list (block, first unread column of it); rows
+// beyond the end of the fill row are zero.  Returns the rows loaded.
 template <class T, int RPT>
-__device__ void structured_qr_regs(T (&cr)[RPT], T* Rp, T* vbuf, T* par, int n, int tpc) {
-  const int c = threadIdx.x / tpc, sl = threadIdx.x % tpc;
-  const int ch = tpc * RPT;
-  auto gsum = [&](T v) {
-    for (int o = 1; o < tpc; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
-  };
-  // par[3*(j&1) + {0,1,2}] = tau, beta, scale of reflector j
-  auto reflector = [&](int j) {
-    T* v = vbuf + (j & 1) * ch;
-    T s2 = 0;
+__device__ inline int rf_load_chunk(T (&cr)[RPT], const FillRef<T>* __restrict__ refs,
+                                    const int32_t* __restrict__ dyn, int fend, int& f, int& c0,
+                                    int col, int n) {
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      v[sl + tpc * u] = cr[u];
-      s2 += cr[u] * cr[u];
-    }
-    s2 = gsum(s2);
-    if (sl == 0) {
-      const T alpha = Rp[pk(j) + j];
-      T* q = par + 3 * (j & 1);
-      if (s2 == T(0)) {
-        q[0] = 0;
-        q[1] = alpha;
-        q[2] = 0;
-      } else {
-        const T nrm = sqrt(alpha * alpha + s2);
-        const T beta = alpha >= T(0) ? -nrm : nrm;
-        q[0] = (beta - alpha) / beta;
-        q[1] = beta;
-        q[2] = T(1) / (alpha - beta);
-      }
-    }
-  };
-  if (c == 0) reflector(0);
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    const T* q = par + 3 * (j & 1);
-    const T tau = q[0], beta = q[1], scale = q[2];
-    if (c > j && c < n && tau != T(0)) {
-      const T* v = vbuf + (j & 1) * ch;
-      T vv[RPT];
-      T d = 0;
+  for (int u = 0; u < RPT; ++u) cr[u] = T(0);
+  int fill = 0;
+  while (fill < RPT && f < fend) {
+    const FillRef<T> fr = refs[f];
+    const int take = min(RPT - fill, fr.ncols - c0);
+    if (take > 0 && col < n) {
+      const gptr<const T> src = gmem(fr.F) + col + (int64_t)(c0 - fill) * fr.ld;
 #pragma unroll
-      for (int u = 0; u < RPT; ++u) {
-        vv[u] = v[sl + tpc * u];
-        d += vv[u] * cr[u];
-      }
-      d = gsum(d);
-      T* rjc = Rp + pk(c) + j;
-      const T r0 = *rjc;
-      const T tw = tau * (r0 + scale * d);
-      const T f = tw * scale;
-#pragma unroll
-      for (int u = 0; u < RPT; ++u) cr[u] -= f * vv[u];
-      if (sl == 0) *rjc = r0 - tw;
+      for (int u = 0; u < RPT; ++u)
+        if (u >= fill && u < fill + take) cr[u] = src[(int64_t)u * fr.ld];
     }
-    if (c == j + 1 && c < n) reflector(c);
-    if (c == j && sl == 0) Rp[pk(j) + j] = beta;
-    __syncthreads();
+    fill += max(take, 0);
+    c0 += max(take, 0);
+    if (c0 >= fr.ncols) {
+      ++f;
+      c0 = (f < fend && refs[f].d0 >= 0) ? dyn[refs[f].d0] : 0;
+    }
   }
+  return fill;
+}
+
+template <class T> __device__ inline T lane_value(T v, int l);
+template <> __device__ inline float lane_value<float>(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+template <> __device__ inline double lane_value<double>(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 // ---------------------------------------------------------------------------
@@ -521,6 +501,16 @@ __device__ void structured_qr_regs(T (&cr)[RPT], T* Rp, T* vbuf, T* par, int n, 
 // blocks of one cluster, output its R factor as out[col + t n] = R[t][col].
 // The fill block of a neighbour already skeletonized at this level is read
 // from its active window (first column dyn[d0]).
+//
+// In LDS (orders up to 256): thread `col` owns column col of the stacked
+// [R; chunk] and holds the chunk's rows of that column in registers.  Step j
+// of a chunk: the owner of column j publishes it (x), its squared norm and
+// alpha = R[j][j]; the reflector with vector [1; x / (alpha - beta)] zeroes
+// the chunk's column j, and every column c > j takes w = R[j][c] + v . chunk_c,
+// R[j][c] -= tau w, chunk_c -= tau w v.  R[j][c] is touched by its own lane
+// only, so a step costs one barrier (a single-wave workgroup's barrier is
+// free, and it reads the norm off the owner's lane).
+// Otherwise R and the chunk live in `work` (structured_qr above).
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ __launch_bounds__(256) void k_rfactor(const RTask<T>* __restrict__ tasks,
@@ -533,48 +523,116 @@ __global__ __launch_bounds__(256) void k_rfactor(const RTask<T>* __restrict__ ta
   __shared__ T red[8];
   if (n == 0) return;
   // same test as the host's (which gives `work` to the others); the launch
-  // provides rf_lds_bound(max order) elements of LDS
+  // provides LDS for every in-LDS order of the launch and 64 threads per 64
+  // columns
   if (rf_in_lds<T>(n)) {
-    constexpr int RPT = kRfRows;
-    const int tpc = rf_tpc(n);
-    const int ch = tpc * RPT;
-    const int c = tid / tpc, sl = tid % tpc;
-    T* Rp = reinterpret_cast<T*>(rf_smem);
-    T* vbuf = Rp + pk(n);
-    T* par = vbuf + 2 * ch;
-    for (int e = tid; e < pk(n); e += nthr) Rp[e] = 0;
+    constexpr int RPT = rf_chunk<T>();
+    const int col = tid, lane = tid & 63;
+    const bool one_wave = nthr == 64;
+    // reflector buffers first (16-byte aligned vectors), then R
+    T* xb = reinterpret_cast<T*>(rf_smem);
+    T* Rr = xb + 2 * rf_xstride<T>();
+    for (int64_t e = tid; e < (int64_t)n * (n + 1) / 2; e += nthr) Rr[e] = T(0);
     __syncthreads();
+    int par = 0;
     T cr[RPT];
+    // reflector steps j0..n-1 on the chunk in cr (its columns j < j0 are zero)
+    auto run_steps = [&](int j0) {
+      for (int j = j0; j < n; ++j, par ^= 1) {
+        // the chunk's column j (x), its squared norm and alpha = R[j][j] as
+        // wave-uniform values: read off the owner's lane (one wave) or
+        // published in LDS, read once per wave (lane u takes x[u]) and
+        // spread by lane reads
+        T xs[RPT];
+        T s2, alpha;
+        T d0 = 0, d1 = 0;
+        if (one_wave) {
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) cr[u] = 0;
-    int fill = 0;
-    for (int f = tk.fbeg; f < tk.fend; ++f) {
-      const FillRef<T> fr = refs[f];
-      int col0 = fr.d0 >= 0 ? dyn[fr.d0] : 0;
-      while (col0 < fr.ncols) {
-        const int take = min(ch - fill, fr.ncols - col0);
-        if (c < n) {
+          for (int u = 0; u < RPT; ++u) xs[u] = lane_value<T>(cr[u], j);
+          alpha = Rr[rf_rowoff(j, n)];
+        } else {
+          T* x = xb + par * rf_xstride<T>();
+          if (col == j) {
+            T q0 = 0, q1 = 0;
 #pragma unroll
-          for (int u = 0; u < RPT; ++u) {
-            const int t = sl + tpc * u;
-            if (t >= fill && t < fill + take) cr[u] = fr.F[c + (int64_t)(col0 + t - fill) * fr.ld];
+            for (int u = 0; u < RPT; u += 2) {
+              x[u] = cr[u];
+              x[u + 1] = cr[u + 1];
+              q0 += cr[u] * cr[u];
+              q1 += cr[u + 1] * cr[u + 1];
+            }
+            x[RPT] = q0 + q1;
+            x[RPT + 1] = Rr[rf_rowoff(j, n)];
           }
-        }
-        fill += take;
-        col0 += take;
-        if (fill == ch) {
-          structured_qr_regs<T, RPT>(cr, Rp, vbuf, par, n, tpc);
+          __syncthreads();
+          const T mine = x[lane < RPT ? lane : 0];
 #pragma unroll
-          for (int u = 0; u < RPT; ++u) cr[u] = 0;
-          fill = 0;
+          for (int u = 0; u < RPT; ++u) xs[u] = lane_value<T>(mine, u);
+          s2 = x[RPT];
+          alpha = x[RPT + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < RPT; u += 2) {
+          d0 += xs[u] * cr[u];
+          d1 += xs[u + 1] * cr[u + 1];
+        }
+        const T d = d0 + d1;
+        // one wave: the squared norm is the owner's own d (same summation
+        // order as the published sum)
+        if (one_wave) s2 = lane_value<T>(d, j);
+        if (s2 != T(0)) {
+          const T nrm = sqrt(alpha * alpha + s2);
+          const T beta = alpha >= T(0) ? -nrm : nrm;
+          const T tau = (beta - alpha) / beta;
+          const T scale = T(1) / (alpha - beta);
+          if (col > j && col < n) {
+            T* rjc = Rr + rf_rowoff(j, n) + (col - j);
+            const T r0 = *rjc;
+            const T tw = tau * (r0 + scale * d);
+            const T fct = tw * scale;
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) cr[u] -= fct * xs[u];
+            *rjc = r0 - tw;
+          }
+          if (col == j) Rr[rf_rowoff(j, n)] = beta;
         }
       }
+    };
+    if (tk.tri) {
+      // stacked factors of a previous stage: the first is R itself, the
+      // others enter in chunks of RPT rows; rows t0.. of an upper triangular
+      // factor are zero in the columns before t0
+      if (tk.fend > tk.fbeg) {
+        const gptr<const T> F0 = gmem(refs[tk.fbeg].F);
+        for (int64_t e = tid; e < (int64_t)n * n; e += nthr) {
+          const int t = (int)(e / n), c = (int)(e % n);
+          if (t <= c) Rr[rf_rowoff(t, n) + (c - t)] = F0[c + (int64_t)t * n];
+        }
+      }
+      __syncthreads();
+      for (int f = tk.fbeg + 1; f < tk.fend; ++f) {
+        const gptr<const T> Fb = gmem(refs[f].F);
+        for (int t0 = 0; t0 < n; t0 += RPT) {
+#pragma unroll
+          for (int u = 0; u < RPT; ++u)
+            cr[u] = (col < n && t0 + u < n) ? Fb[col + (int64_t)(t0 + u) * n] : T(0);
+          run_steps(t0);
+        }
+      }
+    } else {
+      int f = tk.fbeg;
+      int c0 = (f < tk.fend && refs[f].d0 >= 0) ? dyn[refs[f].d0] : 0;
+      for (;;) {
+        const int rows = rf_load_chunk<T, RPT>(cr, refs, dyn, tk.fend, f, c0, col, n);
+        if (rows == 0) break;
+        run_steps(0);
+      }
     }
-    if (fill > 0) structured_qr_regs<T, RPT>(cr, Rp, vbuf, par, n, tpc);
     __syncthreads();
-    for (int e = tid; e < n * n; e += nthr) {
-      const int col = e % n, t = e / n;
-      tk.out[e] = t <= col ? Rp[pk(col) + t] : T(0);
+    if (col < n) {
+      const gptr<T> out = gmem(tk.out);
+      for (int t = 0; t < n; ++t)
+        out[col + (int64_t)t * n] = t <= col ? Rr[rf_rowoff(t, n) + (col - t)] : T(0);
     }
   } else {
     const int ldw = n + kAugChunk;
@@ -614,16 +672,20 @@ template <class T>
 void launch_rfactor(const RTask<T>* tasks, int ntasks, const FillRef<T>* refs,
                     const int32_t* dyn, int maxn, hipStream_t s) {
   if (ntasks <= 0) return;
-  const int64_t cap = kLdsBytes / (int64_t)sizeof(T);
-  const int64_t need = std::min(cap, rf_lds_bound(maxn));
+  // every order of the launch fits in LDS: 64 threads per 64 columns of the
+  // largest and its LDS; otherwise 256 threads (enough for every in-LDS
+  // order) and the full LDS allowance
+  const bool lds = rf_in_lds<T>(maxn);
+  const int threads = lds ? 64 * ((maxn + 63) / 64) : 256;
+  const int64_t need = lds ? rf_lds_elems<T>(maxn) : kLdsBytes / (int64_t)sizeof(T);
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)k_rfactor<T>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_rfactor<T>, dim3(ntasks), dim3(256), (size_t)(need * sizeof(T)), s, tasks,
-                     refs, dyn);
+  hipLaunchKernelGGL(k_rfactor<T>, dim3(ntasks), dim3(threads), (size_t)(need * sizeof(T)), s,
+                     tasks, refs, dyn);
 }
 
 // ---------------------------------------------------------------------------
