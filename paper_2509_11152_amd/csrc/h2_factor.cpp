@@ -16,6 +16,7 @@
 #include <future>
 #include <memory>
 #include <numeric>
+#include <thread>
 #include <tuple>
 
 #include "h2_driver.h"
@@ -31,6 +32,22 @@ uint64_t node_hash(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
   return z ^ (z >> 31);
+}
+
+// f(lo, hi) over [0, n) split into contiguous ranges on up to 8 threads (the
+// calling thread takes the first)
+template <class Fn> void parallel_ranges(int n, Fn f) {
+  const int hw = (int)std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+  const int nt = std::max(1, std::min(hw, n / 256));
+  if (nt == 1) {
+    f(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t)
+    th.emplace_back(f, (int)((int64_t)n * t / nt), (int)((int64_t)n * (t + 1) / nt));
+  f(0, (int)((int64_t)n / nt));
+  for (auto& x : th) x.join();
 }
 
 // Greedy colouring of the near graph in decreasing (hash(id), id) priority;
@@ -82,10 +99,10 @@ void plan_level(const h2_matrix_s& H, int lev, const std::vector<int>& n,
   // fill pattern: lifted pairs plus non-near pairs of neighbours of a common
   // cluster; first colour writing each fill entry
   std::vector<std::vector<std::pair<int, int>>> rows(P.nl);  // (col, firstc)
-  {
+  parallel_ranges(P.nl, [&](int j0, int j1) {
     std::vector<int> stamp(P.nl, -1), minc(P.nl, INT_MAX);
     std::vector<int> cols;
-    for (int j = 0; j < P.nl; ++j) {
+    for (int j = j0; j < j1; ++j) {
       for (int i : P.nb[j]) stamp[i] = j;  // near of j
       cols.clear();
       for (int i : P.nb[j]) {
@@ -106,17 +123,29 @@ void plan_level(const h2_matrix_s& H, int lev, const std::vector<int>& n,
         minc[k] = INT_MAX;
       }
       for (int i : P.nb[j]) minc[i] = INT_MAX;
+      std::sort(rows[j].begin(), rows[j].end());
     }
-  }
-  for (auto& pr : lifted) {
-    auto& rw = rows[pr.first];
-    bool found = false;
-    for (auto& x : rw)
-      if (x.first == pr.second) {
-        x.second = -1;
-        found = true;
+  });
+  // lifted pairs (sorted): present from the start of the level (firstc -1)
+  {
+    std::vector<int64_t> lb(P.nl + 1, 0);
+    for (auto& pr : lifted) ++lb[pr.first + 1];
+    for (int j = 0; j < P.nl; ++j) lb[j + 1] += lb[j];
+    parallel_ranges(P.nl, [&](int j0, int j1) {
+      for (int j = j0; j < j1; ++j) {
+        auto& rw = rows[j];
+        const size_t nold = rw.size();
+        for (int64_t q = lb[j]; q < lb[j + 1]; ++q) {
+          const int c = lifted[q].second;
+          auto it = std::lower_bound(rw.begin(), rw.begin() + nold, std::make_pair(c, INT_MIN));
+          if (it != rw.begin() + nold && it->first == c)
+            it->second = -1;
+          else
+            rw.push_back({c, -1});
+        }
+        if (rw.size() != nold) std::sort(rw.begin(), rw.end());
       }
-    if (!found) rw.push_back({pr.second, -1});
+    });
   }
   P.pptr.assign(P.nl + 1, 0);
   P.pcol.clear();
@@ -125,7 +154,6 @@ void plan_level(const h2_matrix_s& H, int lev, const std::vector<int>& n,
   P.fill_pairs.clear();
   for (int j = 0; j < P.nl; ++j) {
     auto& rw = rows[j];
-    std::sort(rw.begin(), rw.end());
     // merge near (sorted) and fill (sorted)
     size_t a = 0, b = 0;
     const auto& nbj = P.nb[j];
@@ -817,10 +845,13 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         close_mark(m4);
       }
       {
+        // one workgroup per target block unless some block spans many tiles
+        int32_t maxt = 0;
+        for (const auto& o : outs) maxt = std::max(maxt, o.tm * o.tn);
         const GOut<T>* dout = ar.put(outs);
         const GCon<T>* dcon = ar.put(cons);
         auto m5 = mark(5);
-        launch_gemm<T>(dout, (int)outs.size(), dcon, dyn, gtiles, 0, s);
+        launch_gemm<T>(dout, (int)outs.size(), dcon, dyn, gtiles, maxt <= 16 ? 2 : 0, s);
         close_mark(m5);
       }
       H2_HIP(hipGetLastError());  // a rejected launch configuration
@@ -920,17 +951,33 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         return std::binary_search(b, e, s2);
       };
       const bool is_top = (lev == I->tlev);
-      // lifted fill pairs of the next level
+      // lifted fill pairs of the next level (sorted, distinct): per parent
+      // pt, the parents of its children's fill columns that are not near pt
       std::vector<std::pair<int, int>> lifted;
-      for (int j = 0; j < P.nl; ++j)
-        for (int64_t e = P.pptr[j]; e < P.pptr[j + 1]; ++e) {
-          if (!P.isF[e]) continue;
-          const int k = P.pcol[e];
-          const int pt = H.parent[P.a + j], ps = H.parent[P.a + k];
-          if (!pnear(pt, ps)) lifted.push_back({pt - pa, ps - pa});
-        }
-      std::sort(lifted.begin(), lifted.end());
-      lifted.erase(std::unique(lifted.begin(), lifted.end()), lifted.end());
+      {
+        const int np = (int)n2.size();
+        std::vector<std::vector<int>> lrow(np);
+        parallel_ranges(np, [&](int t0, int t1) {
+          std::vector<int> stamp(np, -1);
+          for (int t = t0; t < t1; ++t) {
+            const int tau = pa + t;
+            auto& lr = lrow[t];
+            for (int c = H.cp[tau]; c < H.cp[tau + 1]; ++c) {
+              const int j = c - P.a;
+              for (int64_t e = P.pptr[j]; e < P.pptr[j + 1]; ++e) {
+                if (!P.isF[e]) continue;
+                const int ps = H.parent[P.a + P.pcol[e]];
+                if (stamp[ps - pa] == t) continue;
+                stamp[ps - pa] = t;
+                if (!pnear(tau, ps)) lr.push_back(ps - pa);
+              }
+            }
+            std::sort(lr.begin(), lr.end());
+          }
+        });
+        for (int t = 0; t < np; ++t)
+          for (int x : lrow[t]) lifted.push_back({t, x});
+      }
       // destination of a parent pair block: next level D / F, or the dense top
       T* Dn = nullptr;
       T* Fn = nullptr;

@@ -170,7 +170,8 @@ inline int64_t aug_work_elems(int n) { return 5 * (int64_t)n * n + 3 * (int64_t)
 // ---- launchers (stream-ordered; descriptor arrays are device pointers) ----
 // shape 0: 64 x 64 tiles; shape 1: 64 x 16 tiles (at most 16 columns), where
 // outputs with nsplit > 1 leave their chunks' partial tiles in `parts`
-// (64 x 16 each) for launch_gemm_reduce
+// (64 x 16 each) for launch_gemm_reduce; shape 2: 64 x 64 tiles, one
+// workgroup per output (for outputs of a few tiles)
 template <class T>
 void launch_gemm(const GOut<T>* outs, int nouts, const GCon<T>* cons, const int32_t* dyn,
                  int64_t ntiles, int shape, hipStream_t s, T* parts = nullptr);

@@ -277,6 +277,100 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(const GOut<T>* __restrict__
   }
 }
 
+// One workgroup per output (no tile search), looping over the output's 64 x
+// 64 tiles: each wave owns a 32 x 32 quarter.  The tile's C entries are
+// fetched before the products and the operands of up to kGemmKB k-steps are
+// loaded together, so a tile costs few memory round trips; many workgroups
+// per CU hide them.  For outputs of a few tiles (Schur updates of blocks).
+constexpr int kGemmKB = 2;
+template <class T>
+__global__ __launch_bounds__(256) void k_gemm_out(const GOut<T>* __restrict__ outs,
+                                                  const GCon<T>* __restrict__ cons,
+                                                  const int32_t* __restrict__ dyn) {
+  constexpr int FM = 2, FN = 2;
+  const GOut<T>& o = outs[blockIdx.x];
+  const int m0 = o.m0d >= 0 ? dyn[o.m0d] : o.m0s;
+  const int m1 = o.m1d >= 0 ? dyn[o.m1d] : o.m;
+  const int n0 = o.n0d >= 0 ? dyn[o.n0d] : o.n0s;
+  const int n1 = o.n;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const T alpha = o.alpha, beta = o.beta;
+  const gptr<T> C = gmem(o.C);
+  const int ntile = o.tm * o.tn;
+  for (int t = 0; t < ntile; ++t) {
+    const int ti = t % o.tm, tj = t / o.tm;
+    const int r0 = m0 + ti * 64, c0 = n0 + tj * 64;
+    if (r0 >= m1 || c0 >= n1) continue;
+    const int wr = r0 + (wave & 1) * 32, wc = c0 + (wave >> 1) * 32;
+    // C entries this lane combines in the epilogue
+    T cv[FM][FN][4];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = wr + a * 16 + l16, col = wc + b * 16 + acc_row<T>(kq, i);
+          cv[a][b][i] = (beta != T(0) && row < m1 && col < n1)
+                            ? C[row + (int64_t)col * o.ldc] : T(0);
+        }
+    typename Acc<T>::type acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) acc[a][b] = (typename Acc<T>::type){0, 0, 0, 0};
+    for (int ci = o.cbeg; ci < o.cend; ++ci) {
+      const GCon<T> g = cons[ci];
+      const int k0 = g.k0d >= 0 ? dyn[g.k0d] : g.k0s;
+      const int k1 = g.k1d >= 0 ? dyn[g.k1d] : g.k;
+      const gptr<const T> A = gmem(g.A), B = gmem(g.B);
+      for (int kb = k0; kb < k1; kb += 4 * kGemmKB) {
+        T av[kGemmKB][FM], bv[kGemmKB][FN];
+#pragma unroll
+        for (int q = 0; q < kGemmKB; ++q) {
+          const int kx = kb + 4 * q + kq;
+          const bool kok = kx < k1;
+#pragma unroll
+          for (int a = 0; a < FM; ++a) {
+            const int row = wr + a * 16 + l16;
+            av[q][a] = (kok && row < m1)
+                           ? (g.transA ? A[kx + (int64_t)row * g.lda] : A[row + (int64_t)kx * g.lda])
+                           : T(0);
+          }
+#pragma unroll
+          for (int b = 0; b < FN; ++b) {
+            const int col = wc + b * 16 + l16;
+            bv[q][b] = (kok && col < n1) ? B[kx + (int64_t)col * g.ldb] : T(0);
+          }
+        }
+        // operands swapped: the accumulator holds the transposed block, lane
+        // l16 owning row l16 (coalesced epilogue)
+#pragma unroll
+        for (int q = 0; q < kGemmKB; ++q) {
+          if (kb + 4 * q >= k1) break;
+#pragma unroll
+          for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b) acc[a][b] = mfma16(bv[q][b], av[q][a], acc[a][b]);
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+      const int row = wr + a * 16 + l16;
+      if (row >= m1) continue;
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int col = wc + b * 16 + acc_row<T>(kq, i);
+          if (col < n1) C[row + (int64_t)col * o.ldc] = beta * cv[a][b][i] + alpha * acc[a][b][i];
+        }
+    }
+  }
+}
+
 template <class T>
 void launch_gemm(const GOut<T>* outs, int nouts, const GCon<T>* cons, const int32_t* dyn,
                  int64_t ntiles, int shape, hipStream_t s, T* parts) {
@@ -284,6 +378,8 @@ void launch_gemm(const GOut<T>* outs, int nouts, const GCon<T>* cons, const int3
   if (shape == 0)
     hipLaunchKernelGGL((k_gemm<T, 2, 2, 2, 2>), dim3((unsigned)ntiles), dim3(256), 0, s, outs,
                        nouts, cons, dyn);
+  else if (shape == 2)
+    hipLaunchKernelGGL((k_gemm_out<T>), dim3((unsigned)nouts), dim3(256), 0, s, outs, cons, dyn);
   else
     hipLaunchKernelGGL((k_gemm_skinny<T>), dim3((unsigned)ntiles), dim3(256), 0, s, outs, nouts,
                        cons, dyn, parts);
