@@ -898,12 +898,15 @@ __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__
   A* tau = sig + n;                             // n
   int* rank = reinterpret_cast<int*>(tau + n);  // n ints (fit in n A's)
   T* Q = tk.Q;
-  // barrier; with glob, global-scratch stores of every wave are released
-  // before it and the other waves' acquired after it (agent-scope fences)
+  // barrier between phases; the scratch in global memory is private to the
+  // workgroup, whose waves share one CU, so the barrier's workgroup-scope
+  // release/acquire orders those accesses as well as LDS.  The Gram variant
+  // (glob: the next phase reads global scratch) adds agent-scope fences: its
+  // results are wrong without them, for a reason not yet identified.
   auto bsync = [&](bool glob) {
-    if (glob) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (GRAM && glob) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (glob) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (GRAM && glob) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   };
 
   // ---- 2. Householder QR of V (n x k): reflectors H_0 .. H_{k-1} ----
