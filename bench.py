@@ -36,6 +36,11 @@ def parse():
     p.add_argument("--workload", default="exp3d_262144")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--construct-device", default="cuda")
+    p.add_argument("--save-blob", default=None,
+                   help="after construction, write the serialized matrix and right-hand sides to "
+                        "PATH.blob.npy and PATH.rhs.npy")
+    p.add_argument("--load-blob", default=None,
+                   help="skip construction: read the files --save-blob wrote for this workload")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run plain 256 MiB device copies (reference reading for HBM "
                         "byte counters) and print their size")
@@ -103,6 +108,34 @@ def roofline(st, dt):
     return roof, out
 
 
+# FP32 kernels of the phases whose HBM traffic the PMC summary records
+PMC_KERNEL = {"fill_row_qr": "h2k::k_rfactor<float>",
+              "augment": "h2k::k_augment<float, float, false>",
+              "schur": "h2k::k_gemm_out<float>"}
+
+
+def measured_traffic(workload, phase):
+    """HBM bytes per launch of the phase's kernel from the committed PMC summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or None when
+    there is none for this workload and kernel or the kernel source changed since
+    the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.md")
+    if phase not in PMC_KERNEL or not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    src = os.path.join(ROOT, "paper_2509_11152_amd", "csrc", "h2_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    k = rec.get("kernels", {}).get(PMC_KERNEL[phase])
+    if rec.get("workload") != workload or rec.get("kernel_source_sha256") != sha or k is None:
+        return None
+    return k["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(spec_name):
     """The oracle (single-threaded numpy FP64) on a bounded sample of the same
     recipe (same kernel, tree, leaf size, tolerance and right-hand sides, fewer
@@ -151,14 +184,26 @@ def main():
     from h2gen import workloads
 
     spec = workloads.WORKLOADS[args.workload]
-    log(f"[bench] constructing {args.workload} (N={spec['N']}) on {args.construct_device}")
     t0 = time.perf_counter()
-    w = workloads.make(spec, device=args.construct_device, verbose=True)
-    log(f"[bench] construction {time.perf_counter() - t0:.1f} s, blob {w['blob'].nbytes / 1e9:.2f} GB")
+    if args.load_blob:
+        log(f"[bench] reading {args.load_blob}.blob.npy / .rhs.npy ({args.workload})")
+        w = {"blob": np.load(args.load_blob + ".blob.npy", mmap_mode="r"),
+             "B": np.load(args.load_blob + ".rhs.npy")}
+        if w["B"].shape[0] != spec["N"]:
+            raise SystemExit(f"{args.load_blob}: right-hand sides of N={w['B'].shape[0]}, "
+                             f"workload {args.workload} has N={spec['N']}")
+    else:
+        log(f"[bench] constructing {args.workload} (N={spec['N']}) on {args.construct_device}")
+        w = workloads.make(spec, device=args.construct_device, verbose=True)
+        w.pop("h", None)
+        log(f"[bench] construction {time.perf_counter() - t0:.1f} s, blob {w['blob'].nbytes / 1e9:.2f} GB")
+        if args.save_blob:
+            np.save(args.save_blob + ".blob.npy", w["blob"])
+            np.save(args.save_blob + ".rhs.npy", w["B"])
+            log(f"[bench] wrote {args.save_blob}.blob.npy / .rhs.npy")
     dev = torch.device("cuda:0")
     ctx = h2.Context(0)
     H = h2.Matrix(ctx, w["blob"])
-    del w["h"]
     B = torch.tensor(w["B"], dtype=torch.float64, device=dev)
     tol = spec["tol"]
 
@@ -214,6 +259,7 @@ def main():
     med = lambda v: float(np.median(v))
     value = med(t32)
     roof, phases = roofline(s32, "f32")
+    roof["traffic"] = measured_traffic(args.workload, roof["phase"])
     _, phases64 = roofline(s64, "f64")
     out = {
         "metric": METRIC,
