@@ -35,6 +35,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="exp3d_262144")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-batched", action="store_true",
+                   help="skip the 64-instance batched measurement")
     p.add_argument("--construct-device", default="cuda")
     p.add_argument("--save-blob", default=None,
                    help="after construction, write the serialized matrix and right-hand sides to "
@@ -66,7 +68,7 @@ def copy_calibration():
 # device phases of the factorization (h2_stats indices 0..7) and their kernels
 PHASES = ["fill_row_qr", "augment", "project", "lu", "multipliers", "schur", "close_out", "top_lu"]
 KERNEL_OF = {"fill_row_qr": "k_rfactor", "augment": "k_augment", "project": "k_strip",
-             "lu": "k_lu", "multipliers": "k_trsm", "schur": "k_gemm",
+             "lu": "k_lu", "multipliers": "k_trsm", "schur": "k_gemm_out",
              "close_out": "k_copy", "top_lu": "k_panel_lu + k_laswp + k_trsm_block + k_gemm"}
 # phases whose arithmetic runs on the vector ALU (Householder reductions,
 # Jacobi rotations, small LU and triangular solves); the others are priced
@@ -134,6 +136,60 @@ def measured_traffic(workload, phase):
     if rec.get("workload") != workload or rec.get("kernel_source_sha256") != sha or k is None:
         return None
     return k["traffic_bytes_per_launch"]
+
+
+def batched_bench(args, h2, ctx):
+    """The batched configuration: 64 independent systems, N_i log-uniform in
+    [2048, 32768] (2D Gaussian kernel, KD tree, tol 1e-8, 16 RHS each), factored
+    by one h2_factor_batched call and solved by one h2_solve_batched call in
+    FP64.  Rate = sum over instances of the work model's (factor + solve) flops
+    / wall time of factor + solve (median of the timed repetitions)."""
+    import numpy as np
+    import torch
+
+    from h2gen import workloads
+    sizes = workloads.batch_sizes()
+    t0 = time.perf_counter()
+    Hs, Bs, tol = [], [], None
+    for i, n in enumerate(sizes):
+        spec = workloads.batch_workload(i, int(n))
+        w = workloads.make(spec, device=args.construct_device)
+        Hs.append(h2.Matrix(ctx, w["blob"]))
+        Bs.append(torch.tensor(w["B"], dtype=torch.float64, device="cuda"))
+        tol = spec["tol"]
+        del w
+        if i % 8 == 7:
+            log(f"[bench] batched: constructed {i + 1} instances ({time.perf_counter() - t0:.1f} s)")
+    log(f"[bench] batched: {len(Hs)} instances, sum N = {int(sizes.sum())}, constructed in "
+        f"{time.perf_counter() - t0:.1f} s")
+    tf, ts = [], []
+    Fs = Xs = None
+    for rep in range(args.warmup + args.steps):
+        Fs = Xs = None
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        Fs = h2.factor_batched(ctx, Hs, tol, h2.H2_PREC_FP64)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        Xs = h2.solve_batched(ctx, Fs, Bs)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        if rep >= args.warmup:
+            tf.append(b - a)
+            ts.append(c - b)
+        log(f"[bench] batched rep {rep}: factor {b - a:.3f}s solve {c - b:.3f}s")
+    nrhs = Bs[0].shape[1]
+    fl_f = sum(F.stats()["factor_flops"] for F in Fs)
+    fl_s = sum(F.stats()["solve_flops_per_rhs"] * nrhs for F in Fs)
+    eb = 0.0
+    for H, B, X in zip(Hs, Bs, Xs):
+        R = B - H.matvec(X)
+        eb = max(eb, float((torch.linalg.norm(R, dim=0) / torch.linalg.norm(B, dim=0)).max()))
+    f, so = float(np.median(tf)), float(np.median(ts))
+    return {"instances": len(Hs), "sum_N": int(sizes.sum()), "nrhs": int(nrhs), "tol": tol,
+            "dtype": "f64", "factor_s": f, "solve_s": so,
+            "gflops": (fl_f + fl_s) / (f + so) / 1e9, "factor_gflops": fl_f / f / 1e9,
+            "max_bkwd": eb, "workload": "gauss2d batch, 64 x N_i log-uniform in [2048, 32768]"}
 
 
 def cpu_baseline(spec_name):
@@ -292,6 +348,10 @@ def main():
         "phases_fp32": phases,
         "phases_fp64": phases64,
     }
+    if not args.no_batched:
+        del X32, X64, X64p, F32, F64, H
+        torch.cuda.empty_cache()
+        out["batched"] = batched_bench(args, h2, ctx)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         cb = cpu_baseline(args.workload)

@@ -241,7 +241,8 @@ class Factor:
         _check(lib.h2_factor_get_stats(self.ptr, ctypes.byref(s)))
         return {"levels": s.levels, "max_colors": s.max_colors, "n_top": s.n_top,
                 "factor_bytes": s.factor_bytes, "peak_bytes": s.peak_bytes,
-                "factor_flops": s.factor_flops, "time_ms": list(s.time_ms),
+                "factor_flops": s.factor_flops, "solve_flops_per_rhs": s.solve_flops_per_rhs,
+                "time_ms": list(s.time_ms),
                 "phase_flops": list(s.phase_flops), "phase_bytes": list(s.phase_bytes),
                 "launches": list(s.launches)}
 

@@ -501,6 +501,35 @@ template <class T> struct SolvePlan : SolvePlanBase {
   DevArray<char> img;  // recorded descriptors
   DevArray<T> parts;   // partial tiles of split products
   std::vector<typename Emit<T>::Step> steps;
+  // the steps captured as one HIP graph (kernel nodes only), instantiated on
+  // the plan's second use; `replays` counts uses
+  hipGraphExec_t gexec = nullptr;
+  bool graph_failed = false;
+  int64_t replays = 0;
+  ~SolvePlan() override {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+  }
+  // capture the replay of the steps on stream s; false if the runtime refuses
+  bool capture(hipStream_t s) {
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    for (auto& st : steps) st(s, img.p, parts.p);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(s, &g) != hipSuccess || g == nullptr) {
+      (void)hipGetLastError();
+      return false;
+    }
+    const hipError_t e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      gexec = nullptr;
+      return false;
+    }
+    return true;
+  }
 };
 
 template <class T>
@@ -538,7 +567,14 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
     }
     SolveInst<T>& S = plan->S;
     launch_gather_rows<T, double>(S.vec[0].p, S.vlen[0], B[0], ldb[0], F->perm_d.p, F->N, nrhs, s);
-    for (auto& st : plan->steps) st(s, plan->img.p, plan->parts.p);
+    // first use: replay launch by launch; from the second on, one graph launch
+    if (plan->replays > 0 && !plan->gexec && !plan->graph_failed)
+      plan->graph_failed = !plan->capture(s);
+    if (plan->gexec)
+      H2_HIP(hipGraphLaunch(plan->gexec, s));
+    else
+      for (auto& st : plan->steps) st(s, plan->img.p, plan->parts.p);
+    ++plan->replays;
     launch_scatter_rows<double, T>(X[0], ldx[0], S.vec[0].p, S.vlen[0], F->perm_d.p, F->N, nrhs,
                                    s);
     H2_HIP(hipStreamSynchronize(s));

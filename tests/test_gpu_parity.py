@@ -132,3 +132,30 @@ def test_batched_equals_single(lib, ctx):
         for lev in Fs.levels():
             assert (F.ints(lev, lib.INT_RANKS) == Fs.ints(lev, lib.INT_RANKS)).all()
         assert np.array_equal(X.cpu().numpy(), Xs.cpu().numpy()), n
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solve_graph_replays_match_eager(lib, ctx, prec):
+    """Solves after the first with one factor launch the recorded plan as one
+    HIP graph.  Every replay, with eager work and synchronisations in between,
+    equals the first (launch-by-launch) solve bit for bit; the graph reads the
+    new input (2B gives exactly 2X, the solve being linear and the scaling
+    exact); the unrecorded multi-factor path gives the same bits."""
+    name, spec = "exp3d_4096", EXP3D_4096
+    print(f"[gpu] solve graph replays {prec} {name}", flush=True)
+    w = workload(name, spec)
+    H = gpu_matrix(lib, ctx, name, spec)
+    p = lib.H2_PREC_FP64 if prec == "fp64" else lib.H2_PREC_FP32
+    F = lib.Factor(ctx, H, w["spec"]["tol"], p)
+    B = _cuda(w["B"][:, :2])
+    X0 = F.solve(B).cpu().numpy()
+    for rep in range(3):
+        X = F.solve(B).cpu().numpy()
+        assert np.array_equal(X, X0), rep
+        H.matvec(B)
+        ctx.sync()
+    X2 = F.solve(2 * B).cpu().numpy()
+    assert np.array_equal(X2, 2 * X0)
+    Xd = lib.solve_batched(ctx, [F, F], [B, B])
+    assert np.array_equal(Xd[0].cpu().numpy(), X0)
+    assert np.array_equal(Xd[1].cpu().numpy(), X0)
