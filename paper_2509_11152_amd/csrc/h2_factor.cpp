@@ -497,6 +497,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           woff += aug_work_elems(ni) * (gram_mode ? 2 : 1);
           at.n = ni;
           at.k = P.k[i];
+          at.eps = tol * I->H->norm2;  // eps_fill of the task's own matrix
           std::vector<FillRef<T>> cur;
           for (int64_t e = P.pptr[i]; e < P.pptr[i + 1]; ++e) {
             if (!P.isF[e] || P.firstc[e] >= c) continue;  // zero until a later colour
@@ -768,11 +769,6 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       auto& cons = cp.cons;
       const int64_t gtiles = cp.gtiles;
       if (aug.empty()) continue;
-      const double eps_fill = tol * act[0]->H->norm2;
-      // every instance shares tol but has its own norm: fold the norm in per task
-      // by scaling? keep one threshold per launch group of equal norm.
-      bool same_norm = true;
-      for (auto* I : act) same_norm &= (I->H->norm2 == act[0]->H->norm2);
       int maxn = 1, maxn_aug = 1;
       for (auto& t : aug) maxn_aug = std::max(maxn_aug, t.n);
       for (auto& t : sl) maxn = std::max(maxn, t.n);
@@ -793,25 +789,10 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         close_mark(m0);
       }
       auto m1 = mark(1);
-      if (same_norm) {
-        launch_augment<T>(ar.put(aug), (int)aug.size(), rdev.p, eps_fill, ctx->d_err, maxn_aug,
-                          gram, s);
-      } else {
-        // launch per instance with its own threshold
-        size_t pos = 0;
-        for (auto* I : act) {
-          LevelPlan& P = I->F->plans[I->li];
-          if (c >= P.ncolors) continue;
-          const size_t cnt = P.members[c].size();
-          std::vector<AugTask<T>> part(aug.begin() + pos, aug.begin() + pos + cnt);
-          launch_augment<T>(ar.put(part), (int)cnt, rdev.p, tol * I->H->norm2, ctx->d_err,
-                            maxn_aug, gram, s);
-          pos += cnt;
-        }
-      }
+      launch_augment<T>(ar.put(aug), (int)aug.size(), rdev.p, ctx->d_err, maxn_aug, gram, s);
       close_mark(m1);
       launches[0] += gram ? 1 : (int64_t)rst.size();
-      launches[1] += same_norm ? 1 : (int64_t)act.size();
+      launches[1] += 1;
       launches[2] += 2;
       launches[3] += 1;
       launches[4] += 1;

@@ -87,6 +87,7 @@ template <class T> struct AugTask {
   int32_t n, k;
   int32_t ri;           // index into the r array (output)
   int32_t pad0;
+  double eps;           // truncation threshold eps_fill = tol ||A||_2 of the task's matrix
 };
 
 // Gram matrix of one cluster's fill row (FP32 factorization): G = Y Y^T in
@@ -191,8 +192,8 @@ void launch_gram(const GramTask<T>* tasks, int ntasks, const FillRef<T>* refs,
                  const int32_t* dyn, int64_t ntiles, hipStream_t s);
 // gram: the tasks carry G (FP32 storage only), arithmetic in FP64
 template <class T>
-void launch_augment(const AugTask<T>* tasks, int ntasks, int32_t* r, double eps_fill, int* err,
-                    int maxn, bool gram, hipStream_t s);
+void launch_augment(const AugTask<T>* tasks, int ntasks, int32_t* r, int* err, int maxn, bool gram,
+                    hipStream_t s);
 template <class T>
 void launch_lu(const LUTask<T>* tasks, int ntasks, const int32_t* dyn, int* err, int maxr,
                hipStream_t s);

@@ -873,10 +873,11 @@ void launch_gram(const GramTask<T>* tasks, int ntasks, const FillRef<T>* refs,
 // convergence are the squared singular values.
 template <class T, class A, bool GRAM>
 __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__ tasks,
-                                                 int32_t* __restrict__ rout, A eps_fill,
-                                                 int* err, int lds_elems) {
+                                                 int32_t* __restrict__ rout, int* err,
+                                                 int lds_elems) {
   extern __shared__ char aug_smem[];
   const AugTask<T> tk = tasks[blockIdx.x];
+  const A eps_fill = A(tk.eps);
   const int n = tk.n, k = tk.k;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
@@ -1146,8 +1147,8 @@ __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__
 }
 
 template <class T, class A, bool GRAM>
-static void launch_augment_t(const AugTask<T>* tasks, int ntasks, int32_t* r, A eps_fill,
-                             int* err, int maxn, hipStream_t s) {
+static void launch_augment_t(const AugTask<T>* tasks, int ntasks, int32_t* r, int* err, int maxn,
+                             hipStream_t s) {
   // LDS: the reflectors of V and V_perp (n^2), then M' and W' (at most 2 n^2)
   const int64_t cap = kLdsBytes / (int64_t)sizeof(A);
   const int64_t need = std::min<int64_t>(cap, 2 * (int64_t)maxn * maxn + 8);
@@ -1158,20 +1159,20 @@ static void launch_augment_t(const AugTask<T>* tasks, int ntasks, int32_t* r, A 
     attr_set = true;
   }
   hipLaunchKernelGGL((k_augment<T, A, GRAM>), dim3(ntasks), dim3(1024),
-                     (size_t)(need * sizeof(A)), s, tasks, r, eps_fill, err, (int)need);
+                     (size_t)(need * sizeof(A)), s, tasks, r, err, (int)need);
 }
 
 template <class T>
-void launch_augment(const AugTask<T>* tasks, int ntasks, int32_t* r, double eps_fill, int* err,
-                    int maxn, bool gram, hipStream_t s) {
+void launch_augment(const AugTask<T>* tasks, int ntasks, int32_t* r, int* err, int maxn, bool gram,
+                    hipStream_t s) {
   if (ntasks <= 0) return;
   if constexpr (sizeof(T) == 4) {
     if (gram) {
-      launch_augment_t<T, double, true>(tasks, ntasks, r, eps_fill, err, maxn, s);
+      launch_augment_t<T, double, true>(tasks, ntasks, r, err, maxn, s);
       return;
     }
   }
-  launch_augment_t<T, T, false>(tasks, ntasks, r, T(eps_fill), err, maxn, s);
+  launch_augment_t<T, T, false>(tasks, ntasks, r, err, maxn, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1857,7 +1858,7 @@ void launch_check_finite(const double* X, int64_t n, int* flag, hipStream_t s) {
                                   hipStream_t);                                               \
   template void launch_gram<T>(const GramTask<T>*, int, const FillRef<T>*, const int32_t*,    \
                                int64_t, hipStream_t);                                         \
-  template void launch_augment<T>(const AugTask<T>*, int, int32_t*, double, int*, int, bool,  \
+  template void launch_augment<T>(const AugTask<T>*, int, int32_t*, int*, int, bool,          \
                                   hipStream_t);                                               \
   template void launch_lu<T>(const LUTask<T>*, int, const int32_t*, int*, int, hipStream_t);  \
   template void launch_trsm<T>(const TrsmTask<T>*, int, const int32_t*, int, int, hipStream_t); \
