@@ -1067,7 +1067,11 @@ __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__
           be += __shfl_xor(be, o, 64);
           gab += __shfl_xor(gab, o, 64);
         }
-        if (gab != A(0) && fabs(gab) > tolj * sqrt(al * be)) {
+        // relative test against sqrt(al) sqrt(be): the product al be can
+        // underflow for tiny columns, and a zero there would make every
+        // nonzero gab look unconverged
+        const A nab = sqrt(al) * sqrt(be);
+        if (gab != A(0) && nab > A(0) && fabs(gab) > tolj * nab) {
           const A zeta = (be - al) / (A(2) * gab);
           const A tt = (zeta >= A(0) ? A(1) : A(-1)) / (fabs(zeta) + sqrt(A(1) + zeta * zeta));
           const A cs = A(1) / sqrt(A(1) + tt * tt);
