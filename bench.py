@@ -140,7 +140,8 @@ def measured_traffic(workload, phase):
 
 def batched_bench(args, h2, ctx):
     """The batched configuration: 64 independent systems, N_i log-uniform in
-    [2048, 32768] (2D Gaussian kernel, KD tree, tol 1e-8, 16 RHS each), factored
+    [2048, 32768] (2D Gaussian kernel, KD tree, tol 1e-8, 16 RHS each, leaf size
+    chosen by paper_2509_11152_amd.tune on the largest instance), factored
     by one h2_factor_batched call and solved by one h2_solve_batched call in
     FP64.  Rate = sum over instances of the work model's (factor + solve) flops
     / wall time of factor + solve (median of the timed repetitions)."""
@@ -148,11 +149,26 @@ def batched_bench(args, h2, ctx):
     import torch
 
     from h2gen import workloads
+    from paper_2509_11152_amd import tune
     sizes = workloads.batch_sizes()
+    # leaf size: the fastest of 32, 64, 128 on the largest instance (it
+    # dominates the batch's time)
+    big = int(np.argmax(sizes))
+    big_spec = workloads.batch_workload(big, int(sizes[big]))
+
+    def build(leaf):
+        w = workloads.make(workloads.batch_workload(big, int(sizes[big]), leaf=leaf),
+                           device=args.construct_device)
+        return w["blob"], w["B"]
+
+    t0 = time.perf_counter()
+    leaf, tune_s = tune.choose_leaf(ctx, build, big_spec["tol"])
+    log(f"[bench] batched: leaf {leaf} chosen in {time.perf_counter() - t0:.1f} s "
+        f"({', '.join(f'{k}: {v:.3f} s' for k, v in tune_s.items())})")
     t0 = time.perf_counter()
     Hs, Bs, tol = [], [], None
     for i, n in enumerate(sizes):
-        spec = workloads.batch_workload(i, int(n))
+        spec = workloads.batch_workload(i, int(n), leaf=leaf)
         w = workloads.make(spec, device=args.construct_device)
         Hs.append(h2.Matrix(ctx, w["blob"]))
         Bs.append(torch.tensor(w["B"], dtype=torch.float64, device="cuda"))
@@ -189,7 +205,8 @@ def batched_bench(args, h2, ctx):
     return {"instances": len(Hs), "sum_N": int(sizes.sum()), "nrhs": int(nrhs), "tol": tol,
             "dtype": "f64", "factor_s": f, "solve_s": so,
             "gflops": (fl_f + fl_s) / (f + so) / 1e9, "factor_gflops": fl_f / f / 1e9,
-            "max_bkwd": eb, "workload": "gauss2d batch, 64 x N_i log-uniform in [2048, 32768]"}
+            "max_bkwd": eb, "leaf": leaf, "leaf_tuning_s": {str(k): v for k, v in tune_s.items()},
+            "workload": "gauss2d batch, 64 x N_i log-uniform in [2048, 32768]"}
 
 
 def cpu_baseline(spec_name):

@@ -59,3 +59,10 @@ EXP3D_4096 = dict(N=4096, dim=3, seed=116, kernel=("exp", 0.1, 1e-2), tree="kd",
 # one leaf-level block row per cluster with no admissible pair: pure dense LU
 NOFAR_256 = dict(N=256, dim=2, seed=121, kernel=("exp", 0.1, 1e-2), tree="2d", leaf=64,
                  eta=0.7, tol=1e-8, nrhs=2, rhs_seed=221, p0=10)
+
+# the batched recipe (2D Gaussian kernel, KD tree, tol 1e-8) at the other leaf sizes the
+# batched configuration's leaf choice may pick
+GAUSS_L32 = dict(N=3000, dim=2, seed=3001, kernel=("gauss", 0.05, 1e-3), tree="kd", leaf=32,
+                 eta=0.7, tol=1e-8, nrhs=4, rhs_seed=4001, p0=10)
+GAUSS_L128 = dict(N=4096, dim=2, seed=3002, kernel=("gauss", 0.05, 1e-3), tree="kd", leaf=128,
+                  eta=0.7, tol=1e-8, nrhs=4, rhs_seed=4002, p0=10)

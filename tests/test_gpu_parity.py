@@ -8,7 +8,8 @@ reach a backward error of 1e-12 measured with the oracle's FP64 product.
 import numpy as np
 import pytest
 
-from conftest import EXP3D_4096, NOFAR_256, oracle_factor, oracle_matrix, workload
+from conftest import (EXP3D_4096, GAUSS_L32, GAUSS_L128, NOFAR_256, oracle_factor, oracle_matrix,
+                      workload)
 
 pytestmark = pytest.mark.gpu
 
@@ -18,6 +19,8 @@ CASES = [
     ("exp3d_4096", EXP3D_4096),
     ("nofar_256", NOFAR_256),
     ("gauss2d_3000", None),
+    ("gauss2d_leaf32", GAUSS_L32),
+    ("gauss2d_leaf128", GAUSS_L128),
 ]
 
 
