@@ -83,12 +83,13 @@ void color_level(LevelPlan& P) {
 }  // namespace
 
 // Build the plan of level `lev` given the sizes n and the lifted fill pairs.
-void plan_level(const h2_matrix_s& H, int lev, const std::vector<int>& n,
-                const std::vector<std::pair<int, int>>& lifted, LevelPlan& P) {
+// Structure of level `lev` (colours, fill pattern, first colours, fill pairs)
+// given its lifted fill pairs; it does not depend on the cluster sizes.
+void plan_level_structure(const h2_matrix_s& H, int lev,
+                          const std::vector<std::pair<int, int>>& lifted, LevelPlan& P) {
   P.lev = lev;
   P.a = H.lp[lev];
   P.nl = H.lp[lev + 1] - P.a;
-  P.n = n;
   P.k.resize(P.nl);
   for (int i = 0; i < P.nl; ++i) P.k[i] = H.rank[P.a + i];
   P.nb.assign(P.nl, {});
@@ -172,7 +173,12 @@ void plan_level(const h2_matrix_s& H, int lev, const std::vector<int>& n,
     }
     P.pptr[j + 1] = (int64_t)P.pcol.size();
   }
-  // layout: D entries and F entries in two buffers, CSR order, n_i x n_j column-major
+}
+
+// Block layout of a level from its cluster sizes n: D entries and F entries in
+// two buffers, CSR order, n_i x n_j column-major.
+void plan_level_layout(LevelPlan& P, const std::vector<int>& n) {
+  P.n = n;
   P.poff.assign(P.pcol.size(), 0);
   P.nD = P.nF = 0;
   for (int j = 0; j < P.nl; ++j)
@@ -199,6 +205,48 @@ void plan_level(const h2_matrix_s& H, int lev, const std::vector<int>& n,
     P.nPiv += P.n[i];
   }
   P.r.assign(P.nl, 0);
+}
+
+// Build the plan of level `lev` given the sizes n and the lifted fill pairs.
+void plan_level(const h2_matrix_s& H, int lev, const std::vector<int>& n,
+                const std::vector<std::pair<int, int>>& lifted, LevelPlan& P) {
+  plan_level_structure(H, lev, lifted, P);
+  plan_level_layout(P, n);
+}
+
+// Lifted fill pairs of level plev (sorted, distinct) from the fill pattern of
+// the level below it: per parent pt, the parents of its children's fill
+// columns that are not near pt.
+std::vector<std::pair<int, int>> lifted_pairs(const h2_matrix_s& H, const LevelPlan& P, int plev) {
+  const int pa = H.lp[plev];
+  const int np = H.lp[plev + 1] - pa;
+  auto pnear = [&](int t, int s2) {  // is (t, s2) (global) a near pair of level plev
+    const auto b = H.near_col.begin() + H.near_ptr[t], e = H.near_col.begin() + H.near_ptr[t + 1];
+    return std::binary_search(b, e, s2);
+  };
+  std::vector<std::vector<int>> lrow(np);
+  parallel_ranges(np, [&](int t0, int t1) {
+    std::vector<int> stamp(np, -1);
+    for (int t = t0; t < t1; ++t) {
+      const int tau = pa + t;
+      auto& lr = lrow[t];
+      for (int c = H.cp[tau]; c < H.cp[tau + 1]; ++c) {
+        const int j = c - P.a;
+        for (int64_t e = P.pptr[j]; e < P.pptr[j + 1]; ++e) {
+          if (!P.isF[e]) continue;
+          const int ps = H.parent[P.a + P.pcol[e]];
+          if (stamp[ps - pa] == t) continue;
+          stamp[ps - pa] = t;
+          if (!pnear(tau, ps)) lr.push_back(ps - pa);
+        }
+      }
+      std::sort(lr.begin(), lr.end());
+    }
+  });
+  std::vector<std::pair<int, int>> lifted;
+  for (int t = 0; t < np; ++t)
+    for (int x : lrow[t]) lifted.push_back({t, x});
+  return lifted;
 }
 
 namespace {
@@ -399,6 +447,22 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       if (!I.done) act.push_back(&I);
     if (act.empty()) break;
     const auto t0 = std::chrono::steady_clock::now();
+    // structure of each instance's next level (lifted pairs, colours, fill
+    // pattern), which needs no rank of this level: planned on worker threads
+    // while this level's colours run, taken at the level end
+    std::vector<std::future<std::unique_ptr<LevelPlan>>> next_struct(act.size());
+    for (size_t q = 0; q < act.size(); ++q) {
+      Inst<T>* I = act[q];
+      if (I->lev == I->tlev) continue;  // the next level is the dense top block
+      const h2_matrix_s* Hp = I->H;
+      const LevelPlan* Pp = &I->F->plans[I->li];
+      const int plev = I->lev - 1;
+      next_struct[q] = std::async(std::launch::async, [Hp, Pp, plev]() {
+        auto PN = std::make_unique<LevelPlan>();
+        plan_level_structure(*Hp, plev, lifted_pairs(*Hp, *Pp, plev), *PN);
+        return PN;
+      });
+    }
     int total = 0, maxc = 0;
     for (auto* I : act) {
       LevelPlan& P = I->F->plans[I->li];
@@ -861,7 +925,8 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     // sub-block); cb2, launched after cb: couplings added to far-pair
     // sub-blocks and transfer blocks of the next bases.
     CopyBatch<T> cb, cb2;
-    for (auto* I : act) {
+    for (size_t q = 0; q < act.size(); ++q) {
+      Inst<T>* I = act[q];
       const auto tpl = std::chrono::steady_clock::now();
       const h2_matrix_s& H = *I->H;
       h2_factor_s* F = I->F;
@@ -927,38 +992,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         n2[t] = o;
       }
       const int pa = H.lp[plev];
-      auto pnear = [&](int t, int s2) {  // is (t, s2) (global) a near pair of level plev
-        const auto b = H.near_col.begin() + H.near_ptr[t], e = H.near_col.begin() + H.near_ptr[t + 1];
-        return std::binary_search(b, e, s2);
-      };
       const bool is_top = (lev == I->tlev);
-      // lifted fill pairs of the next level (sorted, distinct): per parent
-      // pt, the parents of its children's fill columns that are not near pt
-      std::vector<std::pair<int, int>> lifted;
-      {
-        const int np = (int)n2.size();
-        std::vector<std::vector<int>> lrow(np);
-        parallel_ranges(np, [&](int t0, int t1) {
-          std::vector<int> stamp(np, -1);
-          for (int t = t0; t < t1; ++t) {
-            const int tau = pa + t;
-            auto& lr = lrow[t];
-            for (int c = H.cp[tau]; c < H.cp[tau + 1]; ++c) {
-              const int j = c - P.a;
-              for (int64_t e = P.pptr[j]; e < P.pptr[j + 1]; ++e) {
-                if (!P.isF[e]) continue;
-                const int ps = H.parent[P.a + P.pcol[e]];
-                if (stamp[ps - pa] == t) continue;
-                stamp[ps - pa] = t;
-                if (!pnear(tau, ps)) lr.push_back(ps - pa);
-              }
-            }
-            std::sort(lr.begin(), lr.end());
-          }
-        });
-        for (int t = 0; t < np; ++t)
-          for (int x : lrow[t]) lifted.push_back({t, x});
-      }
       // destination of a parent pair block: next level D / F, or the dense top
       T* Dn = nullptr;
       T* Fn = nullptr;
@@ -983,9 +1017,12 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         launch_fill<T>(M.p, o * o, T(0), s);
         Dn = M.p;
       } else {
-        F->plans.emplace_back();
+        // structure planned during the level's colours; only the layout
+        // needed the ranks
+        std::unique_ptr<LevelPlan> nxt = next_struct[q].get();
+        F->plans.push_back(std::move(*nxt));
         PN = &F->plans.back();
-        plan_level(H, plev, n2, lifted, *PN);
+        plan_level_layout(*PN, n2);
       }
       LevelPlan& Pc = F->plans[I->li];
       LevelStore<T>* Sc = &store_of<T>(F, I->li);
