@@ -117,7 +117,10 @@ typedef struct {
   double target_bkwd; /* stop when ||b - A x|| / ||b|| <= target for every column */
   int restart;        /* GMRES restart length */
   int max_outer;      /* refinement steps */
-  double inner_rtol;  /* GMRES relative tolerance on the preconditioned residual */
+  double inner_rtol;  /* GMRES relative tolerance on the preconditioned residual; every
+                         refinement step recomputes the FP64 residual, so a loose value
+                         (1e-3) trades inner steps (one solve + one product each) for
+                         cheap outer steps */
 } h2_ir_opts;
 
 typedef struct {
@@ -131,7 +134,7 @@ typedef struct {
  * r = b - A x with the FP64 H^2 product, stop at the target, solve A d = r by
  * GMRES left-preconditioned with the factor, x += d.  Residuals, updates and
  * the Krylov basis are FP64; the factor may be FP32.  Columns are refined
- * together.  B, X: device N x nrhs FP64.  opts NULL = {1e-12, 30, 20, 1e-8}.
+ * together.  B, X: device N x nrhs FP64.  opts NULL = {1e-12, 30, 20, 1e-3}.
  * Returns NOT_CONVERGED (with the report filled) when the target is missed.
  */
 h2_status h2_solve_ir(h2_context_t ctx, h2_matrix_t H, h2_factor_t F, const double* B,

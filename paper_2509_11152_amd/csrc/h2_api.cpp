@@ -349,7 +349,7 @@ h2_status h2_solve_ir(h2_context_t ctx, h2_matrix_t H, h2_factor_t F, const doub
   if (!ctx || !H || !F || !B || !X || nrhs < 0 || ldb < H->N || ldx < H->N || F->N != H->N)
     return H2_ERROR_INVALID_ARGUMENT;
   if ((const void*)B == (const void*)X) return H2_ERROR_INVALID_ARGUMENT;
-  h2_ir_opts o{1e-12, 30, 20, 1e-8};
+  h2_ir_opts o{1e-12, 30, 20, 1e-3};
   if (opts) o = *opts;
   if (o.restart < 1 || o.max_outer < 0 || !(o.target_bkwd > 0)) return H2_ERROR_INVALID_ARGUMENT;
   h2_ir_report rep{};
