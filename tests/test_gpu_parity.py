@@ -162,3 +162,20 @@ def test_solve_graph_replays_match_eager(lib, ctx, prec):
     Xd = lib.solve_batched(ctx, [F, F], [B, B])
     assert np.array_equal(Xd[0].cpu().numpy(), X0)
     assert np.array_equal(Xd[1].cpu().numpy(), X0)
+
+
+def test_choose_leaf_returns_the_fastest_candidate(lib, ctx):
+    """The leaf-size choice times every candidate and returns the fastest."""
+    from h2gen import workloads
+
+    from paper_2509_11152_amd import tune
+    print("[gpu] leaf choice", flush=True)
+
+    def build(leaf):
+        w = workloads.make(workloads.batch_workload(0, 2500, leaf=leaf))
+        return w["blob"], w["B"][:, :2]
+
+    best, times = tune.choose_leaf(ctx, build, 1e-8, candidates=(32, 64), reps=1)
+    assert set(times) == {32, 64}
+    assert all(t > 0 for t in times.values())
+    assert best == min(times, key=lambda k: (times[k], k))
