@@ -101,7 +101,7 @@ _SIG = {
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"HIP library {LIB_PATH} is not built (run __graft_entry__.build())")
+        raise ImportError(f"HIP library {LIB_PATH} is not built (run python paper_2509_11152_amd/build.py)")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in _SIG.items():
         f = getattr(lib, name)

@@ -22,7 +22,7 @@ def test_header_declares_the_boundary():
 
 def test_library_exports_every_declared_symbol():
     path = os.path.join(ROOT, "paper_2509_11152_amd", "libh2rss.so")
-    assert os.path.exists(path), "build the library first (__graft_entry__.build())"
+    assert os.path.exists(path), "build the library first (python paper_2509_11152_amd/build.py)"
     lib = ctypes.CDLL(path)
     for n in _declared():
         assert hasattr(lib, n), n
