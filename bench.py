@@ -7,6 +7,12 @@ factor + the same refinement, and the plain FP64 factor + solve) is timed in
 the same run for comparison.  Inputs are resident in HBM before timing
 starts; construction of the synthetic H^2 matrix is not timed.
 
+After the timed steps, the batched configuration (64 independent 2D systems,
+N_i log-uniform in [2048, 32768], FP64, leaf size chosen by timing) is
+factored and solved with one batched call each and reported under "batched"
+(work-model GFLOP/s).  "roofline" gives the dominant factor kernel's
+achieved rate and, from the committed PMC summary, its HBM traffic per launch.
+
 Prints one JSON line (see the keys below).  Only one GPU is used: --gpus > 1
 exits with a message.
 """

@@ -66,7 +66,8 @@ template <class T> struct FillRef {
 // One stage of the tall-skinny QR of a fill row Y (Section 3, QR-based
 // augmentation): the R factor of the rows of Y^T held by a group of fill
 // blocks.  It is written as an n x n fill block, out[col + t n] = R[t][col],
-// so a later stage reduces the groups' factors like any other fill blocks.
+// so a later stage can read the factors like fill blocks; later stages merge
+// them in pairs (tri).
 template <class T> struct RTask {
   T* out;               // n x n, ld n
   T* work;              // (n + kAugChunk) x n, used only when R does not fit in LDS
