@@ -44,9 +44,9 @@ typedef enum {
 
 /* Working precision of the factorization.  FP32: factor stored and computed
  * in FP32 (MFMA with FP32 accumulation), the fill row reduced by a Householder
- * QR (Section 3, second augmentation option).  FP32_GRAM: the same, except
+ * QR (Section 2.1, second augmentation option).  FP32_GRAM: the same, except
  * that the augmentation works from the FP64 Gram matrix Y Y^T of each FP32
- * fill row and an FP64 eigendecomposition (Section 3, first option). */
+ * fill row and an FP64 eigendecomposition (Section 2.1, first option). */
 typedef enum { H2_PREC_FP64 = 0, H2_PREC_FP32 = 1, H2_PREC_FP32_GRAM = 2 } h2_prec;
 
 typedef struct h2_context_s* h2_context_t;
@@ -56,9 +56,36 @@ typedef struct h2_factor_s* h2_factor_t;
 /* Message of a status code (static storage). */
 const char* h2_status_string(h2_status s);
 
-/* Create a context on HIP device `device` that enqueues work on `stream`
- * (a hipStream_t; NULL = the default stream).  The stream is borrowed. */
-h2_status h2_context_create(int device, void* stream, h2_context_t* ctx);
+/* Device memory callbacks.  `alloc` returns a device pointer to at least
+ * `bytes` bytes that work enqueued on `stream` may use from then on, or NULL
+ * when it cannot; `free` hands a block back in stream order (work already
+ * enqueued on `stream` may still read it; the allocator may give it to later
+ * work of the same stream).  Called from the thread that makes the library
+ * call, never from inside a kernel or a captured graph. */
+typedef void* (*h2_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*h2_free_fn)(void* ptr, size_t bytes, void* stream, void* user);
+
+typedef struct {
+  int device;        /* HIP device id */
+  void* stream;      /* hipStream_t the context enqueues its work on (borrowed).
+                        NULL: the context creates its own stream, which orders
+                        itself with the legacy default stream like any
+                        hipStreamCreate stream, and destroys it with the context. */
+  h2_alloc_fn alloc; /* both NULL: hipMallocAsync / hipFreeAsync on the stream,
+                        from the device's default memory pool, whose release
+                        threshold is raised so that freed blocks stay cached */
+  h2_free_fn free;
+  void* user;        /* passed to alloc and free */
+} h2_context_opts;
+
+/* Create a context (opts NULL = device 0, its own stream, the pool
+ * allocator).  Every device byte the library holds for the context, its
+ * matrices and its factors comes from the context's allocator: the factor's
+ * per-level block buffers (Section 2.2: one buffer per level, offsets from
+ * prefix sums of the block dimension products) as well as every temporary
+ * workspace (Section 2.2: a memory pool for temporaries).  Matrices and
+ * factors must be destroyed before their context. */
+h2_status h2_context_create(const h2_context_opts* opts, h2_context_t* ctx);
 h2_status h2_context_destroy(h2_context_t ctx);
 /* Last error message of the context (valid until the next call on it). */
 const char* h2_last_error(h2_context_t ctx);
@@ -69,11 +96,26 @@ h2_status h2_sync(h2_context_t ctx);
  * Load a serialized symmetric H^2 matrix (format H2B1 v1: cluster tree,
  * same-level near/far lists, leaf bases U, transfers E, dense near blocks D,
  * couplings S; Section 1.1).  `blob` is a HOST buffer of `bytes` bytes, owned
- * by the caller and not referenced after return.  The structure is validated
- * (magic/version, balanced tree, CSR bounds, symmetric pattern, finite data)
- * and the data are copied to the device.  Errors: H2_ERROR_FORMAT.
+ * by the caller and not referenced after return.  It is validated as by
+ * h2_blob_check, then the data are copied to the device.
+ * Errors: H2_ERROR_FORMAT (the message names the failed check).
  */
 h2_status h2_matrix_load(h2_context_t ctx, const void* blob, size_t bytes, h2_matrix_t* H);
+
+/*
+ * Validate a serialized matrix on the host without a device: magic and
+ * version, header sizes, balanced tree (all leaves on one level, children
+ * tiling their parent), permutation, sorted same-level near/far CSR lists
+ * with a symmetric pattern, the diagonal in every near list, data length,
+ * finite entries, orthonormal leaf bases (max |U^T U - I| <= 1e-10),
+ * orthonormal stacked transfers of every inner node (max |sum_c E_c^T E_c - I|
+ * <= 1e-10), symmetric values (max |D_ji - D_ij^T| and max |S_ji - S_ij^T| at
+ * most 1e-12 ||A||_2 with the blob's norm).  Section 1.1 defines the
+ * representation; the symmetry is the standing assumption of Section 2.
+ * Returns H2_SUCCESS or H2_ERROR_FORMAT; on failure the reason is copied
+ * into `msg` (capacity `msgcap` bytes, NUL-terminated; msg may be NULL).
+ */
+h2_status h2_blob_check(const void* blob, size_t bytes, char* msg, size_t msgcap);
 h2_status h2_matrix_destroy(h2_matrix_t H);
 
 typedef struct {
@@ -95,15 +137,30 @@ h2_status h2_matrix_get_info(h2_matrix_t H, h2_matrix_info* info);
 h2_status h2_matvec(h2_context_t ctx, h2_matrix_t H, const double* X, int64_t ldx, int nrhs,
                     double* Y, int64_t ldy);
 
+/* Options of a factorization call (NULL = all defaults). */
+typedef struct {
+  double norm2;       /* > 0: ||A||_2 used in eps_fill = tol ||A||_2 in place of
+                         the blob's estimate (Section 2.1 leaves the norm to the user) */
+  int64_t pool_bytes; /* > 0: cap on the device bytes the call holds at once
+                         (factor storage plus workspaces, over all instances);
+                         reaching it fails the call with OUT_OF_MEMORY */
+  int32_t keep_owner_lists; /* nonzero: keep every colour's Schur target lists for
+                               h2_factor_export_ints(H2_INT_OWNERS) (host memory grows
+                               with the number of targets) */
+  int32_t pad0;
+} h2_factor_opts;
+
 /*
  * Factorize (Algorithm 1 with Algorithm 2 per colour): eps_lu = tol, fill
- * truncation threshold eps_fill = tol * ||A||_2 (blob norm).  prec selects the
- * arithmetic of the factorization and of its storage (FP64, or FP32 with FP32
- * accumulation).  Synchronizes with the device once per tree level.
- * Errors: INVALID_ARGUMENT (tol < 0 or not finite), OUT_OF_MEMORY, SINGULAR,
- * NUMERIC, UNSUPPORTED.
+ * truncation threshold eps_fill = tol * ||A||_2 (blob norm unless opts
+ * overrides it).  prec selects the arithmetic of the factorization and of
+ * its storage (FP64, or FP32 with FP32 accumulation).  Synchronizes with the
+ * device once per tree level.  Errors: INVALID_ARGUMENT (tol < 0 or not
+ * finite, bad opts), OUT_OF_MEMORY (allocator failure or opts->pool_bytes),
+ * SINGULAR (zero pivot), NUMERIC, UNSUPPORTED.
  */
-h2_status h2_factor(h2_context_t ctx, h2_matrix_t H, double tol, h2_prec prec, h2_factor_t* F);
+h2_status h2_factor(h2_context_t ctx, h2_matrix_t H, double tol, h2_prec prec,
+                    const h2_factor_opts* opts, h2_factor_t* F);
 h2_status h2_factor_destroy(h2_factor_t F);
 
 /*
@@ -145,10 +202,11 @@ h2_status h2_solve_ir(h2_context_t ctx, h2_matrix_t H, h2_factor_t F, const doub
  * Batched factorization of `count` independent matrices: levels are aligned
  * by height above the leaves and every (height, colour step) runs as one set
  * of launches over all instances.  Fs[i] receives the factor of Hs[i] and can
- * be used with h2_solve like any other factor.
+ * be used with h2_solve like any other factor.  opts->norm2, when set,
+ * replaces every instance's norm; a failure fails the whole call.
  */
 h2_status h2_factor_batched(h2_context_t ctx, int count, const h2_matrix_t* Hs, double tol,
-                            h2_prec prec, h2_factor_t* Fs);
+                            h2_prec prec, const h2_factor_opts* opts, h2_factor_t* Fs);
 
 /* Batched solve: one set of launches per (height, colour step) over all instances.
  * B[i], X[i]: device N_i x nrhs FP64 with leading dimensions ldb[i], ldx[i]. */
@@ -162,7 +220,19 @@ typedef enum {
   H2_INT_COLORS = 2,   /* colour of every cluster */
   H2_INT_FILL = 3,     /* fill pattern: pairs (j, k) of global node ids, flattened */
   H2_INT_NTOP = 4,     /* order of the dense top block (level argument ignored) */
-  H2_INT_LEVELS = 5    /* skeletonized levels, leaf level first */
+  H2_INT_LEVELS = 5,   /* skeletonized levels, leaf level first */
+  H2_INT_OFFSETS = 6,  /* block layout of the level (Section 2.2: offsets are prefix sums of
+                          the products of block dimensions): for every entry of the level's
+                          block pattern (near pairs and fill pairs, rows ascending, columns
+                          ascending) the record (j, k, is_fill, offset) with global node ids;
+                          near blocks and fill blocks have a buffer each, n_j x n_k blocks in
+                          that order */
+  H2_INT_CLUSTER_OFFSETS = 7, /* per cluster of the level: offset of Q~_i (prefix sum of n_i^2) */
+  H2_INT_OWNERS = 8    /* Schur/fill-in owner lists (needs opts->keep_owner_lists): for every
+                          colour c ascending and every target block (j, k) that clusters of
+                          colour c update, targets ascending, the record
+                          (c, j, k, m, i_1 .. i_m) with the m contributing clusters ascending
+                          (global ids) */
 } h2_int_kind;
 
 /* Copy an integer output of the factorization into the host buffer `buf`
@@ -204,6 +274,8 @@ typedef struct {
   double phase_flops[H2_PHASES]; /* algorithmic flops per phase (same indices) */
   double phase_bytes[H2_PHASES]; /* algorithmic HBM bytes per phase (each operand once) */
   int64_t launches[H2_PHASES];   /* kernel launches per phase */
+  int64_t solves;                /* h2_solve calls served by the factor's recorded plan */
+  int64_t solve_graph_launches;  /* of those, replays as one captured HIP graph launch */
 } h2_stats;
 h2_status h2_factor_get_stats(h2_factor_t F, h2_stats* stats);
 

@@ -131,8 +131,16 @@ def factor(H, tol, keep_trace=False):
         Lf.Q, Lf.lu, Lf.r, Lf.kt, Lf.X, Lf.Y = {}, {}, {}, {}, {}, {}
         ncolors = max(color.values()) + 1
         Lf.ncolors = ncolors
+        Lf.owners = {}
         for c in range(ncolors):
             members = [q for q in nodes if color[q] == c]
+            # Section 2.2: several clusters of one colour may update the same
+            # block; the contributors of each target, in the order their
+            # updates are applied (ascending cluster id)
+            for i in members:
+                for j in nb[i]:
+                    for k in nb[i]:
+                        Lf.owners.setdefault((c, j, k), []).append(i)
             # Algorithm 2: the parallel loop computes every basis of the colour
             # from the fill present before the colour's projections ...
             for i in members:
@@ -377,6 +385,47 @@ def solve(Fz, B):
     X = np.empty_like(y)
     X[Fz.perm] = y
     return X[:, 0] if one else X
+
+
+def block_layout(Lf):
+    """Section 2.2's memory layout of one level: the blocks of the level's
+    pattern (near pairs and fill pairs; rows ascending, columns ascending)
+    placed in one buffer for the near blocks and one for the fill blocks, each
+    block n_j x n_k, at offsets that are exclusive prefix sums of the products
+    of the block dimensions.  Returns records (j, k, is_fill, offset)."""
+    nearset = {(q, j) for q in Lf.nodes for j in Lf.near[q]}
+    frow = {q: [] for q in Lf.nodes}
+    for (a, k) in Lf.fpat:
+        frow[a].append(k)
+    out = []
+    nxt = {False: 0, True: 0}
+    for j in Lf.nodes:
+        cols = sorted(set(Lf.near[j]) | set(frow[j]))
+        for k in cols:
+            isf = (j, k) not in nearset
+            out.append((j, k, int(isf), nxt[isf]))
+            nxt[isf] += Lf.n[j] * Lf.n[k]
+    return out
+
+
+def cluster_offsets(Lf):
+    """Offsets of the level's n_i x n_i transforms Q~_i in one buffer
+    (exclusive prefix sum of n_i^2, Section 2.2)."""
+    out, o = [], 0
+    for q in Lf.nodes:
+        out.append(o)
+        o += Lf.n[q] * Lf.n[q]
+    return out
+
+
+def owner_records(Lf):
+    """Flattened (c, j, k, m, i_1..i_m) for every colour c ascending and every
+    target (j, k) ascending that clusters of colour c update."""
+    rec = []
+    for (c, j, k) in sorted(Lf.owners):
+        con = Lf.owners[(c, j, k)]
+        rec += [c, j, k, len(con)] + list(con)
+    return rec
 
 
 def integer_outputs(Fz):

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libh2rss.so")
 H2_PREC_FP64 = 0
 H2_PREC_FP32 = 1
 H2_PREC_FP32_GRAM = 2
-INT_SIZES, INT_RANKS, INT_COLORS, INT_FILL, INT_NTOP, INT_LEVELS = range(6)
+(INT_SIZES, INT_RANKS, INT_COLORS, INT_FILL, INT_NTOP, INT_LEVELS, INT_OFFSETS,
+ INT_CLUSTER_OFFSETS, INT_OWNERS) = range(9)
 MAT_Q, MAT_BLOCK, MAT_TOP = range(3)
 
 STATUS = {
@@ -58,7 +59,23 @@ class _Stats(ctypes.Structure):
                 ("solve_flops_per_rhs", ctypes.c_double), ("time_ms", ctypes.c_double * H2_PHASES),
                 ("phase_flops", ctypes.c_double * H2_PHASES),
                 ("phase_bytes", ctypes.c_double * H2_PHASES),
-                ("launches", ctypes.c_int64 * H2_PHASES)]
+                ("launches", ctypes.c_int64 * H2_PHASES),
+                ("solves", ctypes.c_int64), ("solve_graph_launches", ctypes.c_int64)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                            ctypes.c_void_p)
+
+
+class _CtxOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("alloc", _ALLOC_FN),
+                ("free", _FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class _FactorOpts(ctypes.Structure):
+    _fields_ = [("norm2", ctypes.c_double), ("pool_bytes", ctypes.c_int64),
+                ("keep_owner_lists", ctypes.c_int32), ("pad0", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -72,7 +89,8 @@ _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _SIG = {
     "h2_status_string": (ctypes.c_char_p, [ctypes.c_int]),
-    "h2_context_create": (ctypes.c_int, [ctypes.c_int, _P, ctypes.POINTER(_P)]),
+    "h2_context_create": (ctypes.c_int, [ctypes.POINTER(_CtxOpts), ctypes.POINTER(_P)]),
+    "h2_blob_check": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.c_char_p, ctypes.c_size_t]),
     "h2_context_destroy": (ctypes.c_int, [_P]),
     "h2_last_error": (ctypes.c_char_p, [_P]),
     "h2_sync": (ctypes.c_int, [_P]),
@@ -80,13 +98,15 @@ _SIG = {
     "h2_matrix_destroy": (ctypes.c_int, [_P]),
     "h2_matrix_get_info": (ctypes.c_int, [_P, ctypes.POINTER(_Info)]),
     "h2_matvec": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, _P, _I64]),
-    "h2_factor": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_P)]),
+    "h2_factor": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int,
+                                 ctypes.POINTER(_FactorOpts), ctypes.POINTER(_P)]),
     "h2_factor_destroy": (ctypes.c_int, [_P]),
     "h2_solve": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, _P, _I64]),
     "h2_solve_ir": (ctypes.c_int, [_P, _P, _P, _P, _I64, ctypes.c_int, _P, _I64,
                                    ctypes.POINTER(_IROpts), ctypes.POINTER(_IRReport)]),
     "h2_factor_batched": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.c_double,
-                                         ctypes.c_int, ctypes.POINTER(_P)]),
+                                         ctypes.c_int, ctypes.POINTER(_FactorOpts),
+                                         ctypes.POINTER(_P)]),
     "h2_solve_batched": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P),
                                         ctypes.POINTER(_I64), ctypes.c_int, ctypes.POINTER(_P),
                                         ctypes.POINTER(_I64)]),
@@ -129,12 +149,42 @@ def _colmajor(X):
 
 
 class Context:
-    def __init__(self, device=0, stream=None):
+    """A library context on one device.
+
+    stream: None lets the library create its own stream (ordered with the
+    legacy default stream, which is torch's default); or a torch.cuda.Stream
+    to enqueue on.  allocator: "torch" backs every device byte the library
+    holds with torch's caching allocator; "pool" uses the device's
+    stream-ordered memory pool."""
+
+    def __init__(self, device=0, stream=None, allocator="torch"):
         import torch
 
-        self.torch_stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.device = device
+        self.torch_stream = stream
+        self._cbs = None
+        opts = _CtxOpts()
+        opts.device = device
+        opts.stream = stream.cuda_stream if stream is not None else None
+        if allocator == "torch":
+            def _alloc(nbytes, strm, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), device, int(strm or 0))
+                except Exception:
+                    return None
+
+            def _free(ptr, nbytes, strm, user):
+                try:
+                    torch.cuda.caching_allocator_delete(int(ptr))
+                except Exception:
+                    pass
+
+            self._cbs = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+            opts.alloc, opts.free = self._cbs
+        elif allocator != "pool":
+            raise ValueError(f"unknown allocator {allocator!r}")
         self.ptr = _P()
-        _check(lib.h2_context_create(device, _P(self.torch_stream.cuda_stream), ctypes.byref(self.ptr)))
+        _check(lib.h2_context_create(ctypes.byref(opts), ctypes.byref(self.ptr)))
 
     def sync(self):
         _check(lib.h2_sync(self.ptr), self)
@@ -188,8 +238,12 @@ class Matrix:
             pass
 
 
+def _factor_opts(norm2=None, pool_bytes=None, keep_owner_lists=False):
+    return _FactorOpts(float(norm2 or 0.0), int(pool_bytes or 0), int(bool(keep_owner_lists)), 0)
+
+
 class Factor:
-    def __init__(self, ctx, H, tol, prec=H2_PREC_FP64, _ptr=None):
+    def __init__(self, ctx, H, tol, prec=H2_PREC_FP64, _ptr=None, **opts):
         self.ctx = ctx
         self.n = H.n
         self.prec = prec
@@ -197,7 +251,9 @@ class Factor:
             self.ptr = _ptr
         else:
             self.ptr = _P()
-            _check(lib.h2_factor(ctx.ptr, H.ptr, float(tol), prec, ctypes.byref(self.ptr)), ctx)
+            o = _factor_opts(**opts)
+            _check(lib.h2_factor(ctx.ptr, H.ptr, float(tol), prec, ctypes.byref(o),
+                                 ctypes.byref(self.ptr)), ctx)
 
     def solve(self, B, out=None):
         import torch
@@ -244,7 +300,8 @@ class Factor:
                 "factor_flops": s.factor_flops, "solve_flops_per_rhs": s.solve_flops_per_rhs,
                 "time_ms": list(s.time_ms),
                 "phase_flops": list(s.phase_flops), "phase_bytes": list(s.phase_bytes),
-                "launches": list(s.launches)}
+                "launches": list(s.launches), "solves": s.solves,
+                "solve_graph_launches": s.solve_graph_launches}
 
     def __del__(self):
         try:
@@ -253,6 +310,14 @@ class Factor:
                 self.ptr = _P()
         except Exception:
             pass
+
+
+def blob_check(blob):
+    """Host-side validation of a serialized matrix: (status code, message)."""
+    buf = np.ascontiguousarray(np.asarray(blob, dtype=np.uint8))
+    msg = ctypes.create_string_buffer(512)
+    code = lib.h2_blob_check(buf.ctypes.data_as(_P), buf.nbytes, msg, 512)
+    return code, msg.value.decode()
 
 
 def solve_ir(ctx, H, F, B, target=1e-12, restart=30, max_outer=20, inner_rtol=1e-3):
@@ -272,10 +337,12 @@ def solve_ir(ctx, H, F, B, target=1e-12, restart=30, max_outer=20, inner_rtol=1e
                    "max_bkwd": rep.max_bkwd, "converged": code == 0}
 
 
-def factor_batched(ctx, Hs, tol, prec=H2_PREC_FP64):
+def factor_batched(ctx, Hs, tol, prec=H2_PREC_FP64, **opts):
     arr = (_P * len(Hs))(*[H.ptr for H in Hs])
     out = (_P * len(Hs))()
-    _check(lib.h2_factor_batched(ctx.ptr, len(Hs), arr, float(tol), prec, out), ctx)
+    o = _factor_opts(**opts)
+    _check(lib.h2_factor_batched(ctx.ptr, len(Hs), arr, float(tol), prec, ctypes.byref(o), out),
+           ctx)
     return [Factor(ctx, H, tol, prec, _ptr=_P(out[i])) for i, H in enumerate(Hs)]
 
 

@@ -4,6 +4,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
+#include <thread>
 
 #include "h2_driver.h"
 #include "h2_internal.h"
@@ -164,6 +166,99 @@ void parse(const uint8_t* p, size_t bytes, h2_matrix_s& H) {
     if (H.far_ptr[H.lp[l + 1]] > H.far_ptr[H.lp[l]]) H.top = l;
 }
 
+
+// f(lo, hi) over [0, n) in contiguous ranges on up to 8 threads
+template <class Fn> void par_ranges(int64_t n, Fn f) {
+  const int hw = (int)std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(hw, n / 64));
+  if (nt == 1) {
+    f((int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(f, n * t / nt, n * (t + 1) / nt);
+  f((int64_t)0, n / nt);
+  for (auto& x : th) x.join();
+}
+
+// Numerical checks of the data section: finite entries, orthonormal leaf
+// bases and stacked transfers, symmetric near blocks and couplings.
+void check_data(const double* d, const h2_matrix_s& H) {
+  std::atomic<int> bad{0};
+  par_ranges(H.ndata, [&](int64_t a, int64_t b) {
+    for (int64_t i = a; i < b; ++i)
+      if (!std::isfinite(d[i])) {
+        bad = 1;
+        return;
+      }
+  });
+  if (bad) fail_format("non-finite matrix entry");
+  constexpr double kOrth = 1e-10;
+  // max |G - I| of G = sum over blocks of B^T B (blocks of `rows` x k, column-major)
+  auto gram_dev = [](const std::vector<std::pair<const double*, int>>& blocks, int k) {
+    double dev = 0;
+    for (int a = 0; a < k; ++a)
+      for (int b = 0; b <= a; ++b) {
+        double g = 0;
+        for (const auto& bl : blocks) {
+          const double* x = bl.first + (int64_t)a * bl.second;
+          const double* y = bl.first + (int64_t)b * bl.second;
+          for (int r = 0; r < bl.second; ++r) g += x[r] * y[r];
+        }
+        dev = std::max(dev, std::fabs(g - (a == b ? 1.0 : 0.0)));
+      }
+    return dev;
+  };
+  const int leaf0 = H.lp[H.L];
+  std::atomic<int> which{0};
+  par_ranges(H.nn, [&](int64_t a, int64_t b) {
+    for (int64_t q = a; q < b && !which; ++q) {
+      const int k = H.rank[q];
+      if (k == 0) continue;
+      std::vector<std::pair<const double*, int>> blocks;
+      if (q >= leaf0) {
+        blocks.push_back({d + H.offU[q], H.size((int)q)});
+      } else {
+        for (int c = H.cp[q]; c < H.cp[q + 1]; ++c)
+          if (H.rank[c] > 0) blocks.push_back({d + H.offE[c], H.rank[c]});
+      }
+      if (gram_dev(blocks, k) > kOrth) which = q >= leaf0 ? 1 : 2;
+    }
+  });
+  if (which == 1) fail_format("leaf basis U is not orthonormal (max |U^T U - I| > 1e-10)");
+  if (which == 2)
+    fail_format("stacked transfers are not orthonormal (max |sum E_c^T E_c - I| > 1e-10)");
+  // symmetric values: block (j, i) equals the transpose of block (i, j)
+  const double tol = 1e-12 * H.norm2;
+  auto sym = [&](const std::vector<int64_t>& ptr, const std::vector<int32_t>& col,
+                 const std::vector<int64_t>& off, bool dense, int q0) {
+    std::atomic<int> asym{0};
+    par_ranges(H.nn - q0, [&](int64_t a, int64_t b) {
+      for (int64_t qq = a; qq < b && !asym; ++qq) {
+        const int q = q0 + (int)qq;
+        for (int64_t e = ptr[q]; e < ptr[q + 1]; ++e) {
+          const int j = col[e];
+          if (j < q) continue;
+          const auto bj = col.begin() + ptr[j], ej = col.begin() + ptr[j + 1];
+          const int64_t et = ptr[j] + (std::lower_bound(bj, ej, q) - bj);
+          const int m = dense ? H.size(q) : H.rank[q];
+          const int n = dense ? H.size(j) : H.rank[j];
+          const double* x = d + off[e];   // m x n
+          const double* y = d + off[et];  // n x m
+          for (int c = 0; c < n; ++c)
+            for (int r = 0; r < m; ++r)
+              if (std::fabs(x[r + (int64_t)c * m] - y[c + (int64_t)r * n]) > tol) asym = 1;
+        }
+      }
+    });
+    return asym != 0;
+  };
+  if (sym(H.near_ptr, H.near_col, H.offD, true, leaf0))
+    fail_format("near blocks are not symmetric (D_ji != D_ij^T)");
+  if (sym(H.far_ptr, H.far_col, H.offS, false, 0))
+    fail_format("couplings are not symmetric (S_ji != S_ij^T)");
+}
+
 }  // namespace
 
 extern "C" {
@@ -183,23 +278,47 @@ const char* h2_status_string(h2_status s) {
   return "unknown status";
 }
 
-h2_status h2_context_create(int device, void* stream, h2_context_t* out) {
+h2_status h2_context_create(const h2_context_opts* opts, h2_context_t* out) {
   if (!out) return H2_ERROR_INVALID_ARGUMENT;
   *out = nullptr;
+  h2_context_opts o{0, nullptr, nullptr, nullptr, nullptr};
+  if (opts) o = *opts;
+  if ((o.alloc == nullptr) != (o.free == nullptr)) return H2_ERROR_INVALID_ARGUMENT;
   auto* ctx = new (std::nothrow) h2_context_s();
   if (!ctx) return H2_ERROR_OUT_OF_MEMORY;
   h2_status st = guard(nullptr, [&] {
     int count = 0;
     H2_HIP(hipGetDeviceCount(&count));
-    if (device < 0 || device >= count) throw H2Error(H2_ERROR_INVALID_ARGUMENT, "bad device");
-    H2_HIP(hipSetDevice(device));
-    ctx->device = device;
-    ctx->stream = (hipStream_t)stream;
+    if (o.device < 0 || o.device >= count) throw H2Error(H2_ERROR_INVALID_ARGUMENT, "bad device");
+    H2_HIP(hipSetDevice(o.device));
+    ctx->device = o.device;
+    if (o.stream) {
+      ctx->stream = (hipStream_t)o.stream;
+    } else {
+      H2_HIP(hipStreamCreate(&ctx->stream));
+      ctx->own_stream = true;
+    }
+    if (!o.alloc) {
+      // keep freed blocks of the default pool cached instead of returning
+      // them to the device at every synchronisation
+      hipMemPool_t pool = nullptr;
+      H2_HIP(hipDeviceGetDefaultMemPool(&pool, o.device));
+      uint64_t thr = UINT64_MAX;
+      H2_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+    }
+    ctx->mem.fa = o.alloc;
+    ctx->mem.ff = o.free;
+    ctx->mem.user = o.user;
+    ctx->mem.s = ctx->stream;
+    ctx->tr.mem = &ctx->mem;
     ctx->arena.s = ctx->stream;
-    H2_HIP(hipMalloc((void**)&ctx->d_err, sizeof(int)));
-    H2_HIP(hipMemset(ctx->d_err, 0, sizeof(int)));
+    ctx->arena.mem = &ctx->mem;
+    ctx->d_err.alloc(1, &ctx->tr);
+    h2k::launch_fill<int32_t>(ctx->d_err.p, 1, 0, ctx->stream);
+    H2_HIP(hipStreamSynchronize(ctx->stream));
   });
   if (st != H2_SUCCESS) {
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return st;
   }
@@ -212,8 +331,14 @@ h2_status h2_context_destroy(h2_context_t ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   ctx->arena.free_all();
-  if (ctx->d_err) (void)hipFree(ctx->d_err);
+  ctx->parts32.release();
+  ctx->parts64.release();
+  ctx->d_err.release();
+  (void)hipStreamSynchronize(ctx->stream);
+  const hipStream_t s = ctx->stream;
+  const bool own = ctx->own_stream;
   delete ctx;
+  if (own) (void)hipStreamDestroy(s);
   return H2_SUCCESS;
 }
 
@@ -224,25 +349,53 @@ h2_status h2_sync(h2_context_t ctx) {
   return guard(ctx, [&] { H2_HIP(hipStreamSynchronize(ctx->stream)); });
 }
 
+h2_status h2_blob_check(const void* blob, size_t bytes, char* msg, size_t msgcap) {
+  if (msg && msgcap) msg[0] = 0;
+  if (!blob) return H2_ERROR_INVALID_ARGUMENT;
+  h2_matrix_s H;
+  std::string err;
+  h2_status st = H2_SUCCESS;
+  try {
+    const uint8_t* p = (const uint8_t*)blob;
+    parse(p, bytes, H);
+    check_data((const double*)(p + bytes - (size_t)H.ndata * 8), H);
+  } catch (const H2Error& e) {
+    st = e.code;
+    err = e.what();
+  } catch (const std::bad_alloc&) {
+    st = H2_ERROR_OUT_OF_MEMORY;
+    err = "host allocation failed";
+  } catch (const std::exception& e) {
+    st = H2_ERROR_FORMAT;
+    err = e.what();
+  }
+  if (msg && msgcap) {
+    std::strncpy(msg, err.c_str(), msgcap - 1);
+    msg[msgcap - 1] = 0;
+  }
+  return st;
+}
+
 h2_status h2_matrix_load(h2_context_t ctx, const void* blob, size_t bytes, h2_matrix_t* out) {
   if (!ctx || !blob || !out) return H2_ERROR_INVALID_ARGUMENT;
   *out = nullptr;
   auto* H = new (std::nothrow) h2_matrix_s();
   if (!H) return H2_ERROR_OUT_OF_MEMORY;
   H->ctx = ctx;
+  H->tr.mem = &ctx->mem;
   h2_status st = guard(ctx, [&] {
     H2_HIP(hipSetDevice(ctx->device));
     const uint8_t* p = (const uint8_t*)blob;
     parse(p, bytes, *H);
-    const size_t data_off = bytes - (size_t)H->ndata * 8;
-    // finite data
-    const double* d = (const double*)(p + data_off);
-    for (int64_t i = 0; i < H->ndata; ++i)
-      if (!std::isfinite(d[i])) throw H2Error(H2_ERROR_FORMAT, "non-finite matrix entry");
+    const double* d = (const double*)(p + bytes - (size_t)H->ndata * 8);
+    check_data(d, *H);
     H->data.alloc(H->ndata, &H->tr);
-    if (H->ndata) H2_HIP(hipMemcpy(H->data.p, d, (size_t)H->ndata * 8, hipMemcpyHostToDevice));
+    if (H->ndata)
+      H2_HIP(hipMemcpyAsync(H->data.p, d, (size_t)H->ndata * 8, hipMemcpyHostToDevice, ctx->stream));
     H->perm_d.alloc(H->N, &H->tr);
-    H2_HIP(hipMemcpy(H->perm_d.p, H->perm.data(), (size_t)H->N * 8, hipMemcpyHostToDevice));
+    H2_HIP(hipMemcpyAsync(H->perm_d.p, H->perm.data(), (size_t)H->N * 8, hipMemcpyHostToDevice,
+                          ctx->stream));
+    H2_HIP(hipStreamSynchronize(ctx->stream));
   });
   if (st != H2_SUCCESS) {
     delete H;
@@ -284,15 +437,20 @@ h2_status h2_matvec(h2_context_t ctx, h2_matrix_t H, const double* X, int64_t ld
   });
 }
 
-h2_status h2_factor(h2_context_t ctx, h2_matrix_t H, double tol, h2_prec prec, h2_factor_t* F) {
-  return h2_factor_batched(ctx, 1, &H, tol, prec, F);
+h2_status h2_factor(h2_context_t ctx, h2_matrix_t H, double tol, h2_prec prec,
+                    const h2_factor_opts* opts, h2_factor_t* F) {
+  return h2_factor_batched(ctx, 1, &H, tol, prec, opts, F);
 }
 
 h2_status h2_factor_batched(h2_context_t ctx, int count, const h2_matrix_t* Hs, double tol,
-                            h2_prec prec, h2_factor_t* Fs) {
+                            h2_prec prec, const h2_factor_opts* opts, h2_factor_t* Fs) {
   if (!ctx || count <= 0 || !Hs || !Fs) return H2_ERROR_INVALID_ARGUMENT;
   if (!(tol >= 0) || !std::isfinite(tol)) return H2_ERROR_INVALID_ARGUMENT;
   if (prec != H2_PREC_FP64 && prec != H2_PREC_FP32 && prec != H2_PREC_FP32_GRAM)
+    return H2_ERROR_INVALID_ARGUMENT;
+  h2_factor_opts o{};
+  if (opts) o = *opts;
+  if (std::isnan(o.norm2) || !std::isfinite(o.norm2) || o.norm2 < 0 || o.pool_bytes < 0)
     return H2_ERROR_INVALID_ARGUMENT;
   for (int i = 0; i < count; ++i) {
     if (!Hs[i] || Hs[i]->ctx != ctx) return H2_ERROR_INVALID_ARGUMENT;
@@ -302,7 +460,7 @@ h2_status h2_factor_batched(h2_context_t ctx, int count, const h2_matrix_t* Hs, 
   h2_status st = guard(ctx, [&] {
     H2_HIP(hipSetDevice(ctx->device));
     std::vector<h2_matrix_s*> hs(Hs, Hs + count);
-    out = h2drv::factor(ctx, hs, tol, prec);
+    out = h2drv::factor(ctx, hs, tol, prec, o);
   });
   if (st == H2_SUCCESS)
     for (int i = 0; i < count; ++i) Fs[i] = out[i];
@@ -390,6 +548,19 @@ h2_status h2_factor_export_ints(h2_factor_t F, int level, h2_int_kind kind, int6
         v.push_back(pr.first + P->a);
         v.push_back(pr.second + P->a);
       }
+    } else if (kind == H2_INT_OFFSETS) {
+      for (int j = 0; j < P->nl; ++j)
+        for (int64_t e = P->pptr[j]; e < P->pptr[j + 1]; ++e) {
+          v.push_back(j + P->a);
+          v.push_back(P->pcol[e] + P->a);
+          v.push_back(P->isF[e] ? 1 : 0);
+          v.push_back(P->poff[e]);
+        }
+    } else if (kind == H2_INT_CLUSTER_OFFSETS) {
+      for (int64_t x : P->offQ) v.push_back(x);
+    } else if (kind == H2_INT_OWNERS) {
+      if (!F->keep_owners) return H2_ERROR_INVALID_ARGUMENT;
+      v = P->owners;
     } else {
       return H2_ERROR_INVALID_ARGUMENT;
     }
@@ -451,6 +622,8 @@ h2_status h2_factor_export_matrix(h2_factor_t F, int level, h2_mat_kind kind, in
 h2_status h2_factor_get_stats(h2_factor_t F, h2_stats* s) {
   if (!F || !s) return H2_ERROR_INVALID_ARGUMENT;
   *s = F->stats;
+  s->solves = F->splan ? F->splan->uses() : 0;
+  s->solve_graph_launches = F->splan ? F->splan->graph_uses() : 0;
   return H2_SUCCESS;
 }
 

@@ -10,7 +10,7 @@ void matvec(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int
             int64_t ldy);
 
 std::vector<h2_factor_s*> factor(h2_context_s* ctx, const std::vector<h2_matrix_s*>& Hs,
-                                 double tol, h2_prec prec);
+                                 double tol, h2_prec prec, const h2_factor_opts& opts);
 
 void solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
            const std::vector<const double*>& B, const std::vector<int64_t>& ldb, int nrhs,

@@ -273,6 +273,7 @@ template <class T> struct Inst {
   size_t li = 0;             // index of the current level in F->plans
   DevArray<T> Fbuf;          // fill blocks of the current level
   DevArray<T> Vbuf;          // bases of the current level
+  double norm = 0;           // ||A||_2 of eps_fill = tol ||A||_2
   double flops = 0;
   double pflops[H2_PHASES] = {0}, pbytes[H2_PHASES] = {0};
 };
@@ -381,6 +382,8 @@ template <class T> struct ColourPlan {
   std::vector<GOut<T>> outs;
   std::vector<GCon<T>> cons;
   int64_t gtiles = 0;
+  // Schur target lists of the colour per level plan (kept on request)
+  std::vector<std::pair<LevelPlan*, std::vector<int64_t>>> owners;
 };
 
 // colours planned ahead of the launches
@@ -388,14 +391,15 @@ constexpr int kPlanAhead = 8;
 
 
 template <class T>
-static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double tol) {
+static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double tol,
+                       DevTracker* calltr) {
   hipStream_t s = ctx->stream;
-  // FP32 with the Gram augmentation (Section 3, first option): the fill row
+  // FP32 with the Gram augmentation (Section 2.1, first option): the fill row
   // enters the augmentation as its FP64 Gram matrix; otherwise the QR route
   const bool gram_mode = sizeof(T) == 4 && !insts.empty() && insts[0].F->prec == H2_PREC_FP32_GRAM;
   DescArena& ar = ctx->arena;
   ar.s = s;
-  H2_HIP(hipMemsetAsync(ctx->d_err, 0, sizeof(int), s));
+  H2_HIP(hipMemsetAsync(ctx->d_err.p, 0, sizeof(int), s));
   const auto t_start = std::chrono::steady_clock::now();
   double plan_ms = 0;
   auto ms_since = [](std::chrono::steady_clock::time_point t0) {
@@ -471,7 +475,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       maxc = std::max(maxc, P.ncolors);
     }
     DevArray<int32_t> rdev;
-    rdev.alloc(total, nullptr);
+    rdev.alloc(total, calltr);
     launch_fill<int32_t>(rdev.p, total, 0, s);
     int maxn_all = 1;
     for (auto* I : act)
@@ -507,9 +511,9 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       gwmax = std::max(gwmax, gw);
     }
     DevArray<T> work;
-    work.alloc(wmax, &act[0]->F->tr);
+    work.alloc(wmax, calltr);
     DevArray<double> gwork;  // Gram matrices of a colour (FP32 path)
-    gwork.alloc(gwmax, &act[0]->F->tr);
+    gwork.alloc(gwmax, calltr);
     plan_ms += ms_since(t0);
 
     // (phase, start, end) events around each phase's launches
@@ -561,7 +565,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           woff += aug_work_elems(ni) * (gram_mode ? 2 : 1);
           at.n = ni;
           at.k = P.k[i];
-          at.eps = tol * I->H->norm2;  // eps_fill of the task's own matrix
+          at.eps = tol * I->norm;  // eps_fill of the task's own matrix
           std::vector<FillRef<T>> cur;
           for (int64_t e = P.pptr[i]; e < P.pptr[i + 1]; ++e) {
             if (!P.isF[e] || P.firstc[e] >= c) continue;  // zero until a later colour
@@ -775,6 +779,25 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
             g.k1d = rb + i;
             g.transA = 0;
           }
+          if (I->F->keep_owners) {
+            // (c, j, k, m, contributors...) per target, targets ascending
+            std::vector<size_t> ord(ent.size());
+            std::iota(ord.begin(), ord.end(), 0);
+            std::sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return ent[x] < ent[y]; });
+            std::vector<int64_t> rec;
+            for (size_t o : ord) {
+              const int64_t e = ent[o];
+              const int j = (int)(std::upper_bound(P.pptr.begin(), P.pptr.end(), e) - P.pptr.begin()) - 1;
+              rec.push_back(c);
+              rec.push_back(j + P.a);
+              rec.push_back(P.pcol[e] + P.a);
+              rec.push_back(beg[o + 1] - beg[o]);
+              // contributors in the order their products are summed (ascending i)
+              for (int32_t q = beg[o]; q < beg[o + 1]; ++q)
+                rec.push_back(cons[cbase + q].k1d - rb + P.a);
+            }
+            cp.owners.push_back({&P, std::move(rec)});
+          }
           for (size_t o = 0; o < ent.size(); ++o) {
             const int64_t e = ent[o];
             slot[e] = -1;
@@ -832,6 +855,8 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       auto& outs = cp.outs;
       auto& cons = cp.cons;
       const int64_t gtiles = cp.gtiles;
+      for (auto& ow : cp.owners)
+        ow.first->owners.insert(ow.first->owners.end(), ow.second.begin(), ow.second.end());
       if (aug.empty()) continue;
       int maxn = 1, maxn_aug = 1;
       for (auto& t : aug) maxn_aug = std::max(maxn_aug, t.n);
@@ -853,7 +878,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         close_mark(m0);
       }
       auto m1 = mark(1);
-      launch_augment<T>(ar.put(aug), (int)aug.size(), rdev.p, ctx->d_err, maxn_aug, gram, s);
+      launch_augment<T>(ar.put(aug), (int)aug.size(), rdev.p, ctx->d_err.p, maxn_aug, gram, s);
       close_mark(m1);
       launches[0] += gram ? 1 : (int64_t)rst.size();
       launches[1] += 1;
@@ -875,7 +900,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         for (auto& t : lus) maxr = std::max(maxr, (int)t.lda);
         const LUTask<T>* dl = ar.put(lus);
         auto m3 = mark(3);
-        launch_lu<T>(dl, (int)lus.size(), dyn, ctx->d_err, maxr, s);
+        launch_lu<T>(dl, (int)lus.size(), dyn, ctx->d_err.p, maxr, s);
         close_mark(m3);
       }
       {
@@ -907,7 +932,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     H2_HIP(hipStreamSynchronize(s));
     {
       int herr = 0;
-      H2_HIP(hipMemcpy(&herr, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost));
+      H2_HIP(hipMemcpy(&herr, ctx->d_err.p, sizeof(int), hipMemcpyDeviceToHost));
       if (herr & 1) throw H2Error(H2_ERROR_SINGULAR, "zero pivot in a redundant block");
       if (herr & 2) throw H2Error(H2_ERROR_NUMERIC, "non-finite singular value in augmentation");
     }
@@ -1181,7 +1206,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       const int nb = 64;
       for (int64_t j0 = 0; j0 < n; j0 += nb) {
         const int w = (int)std::min<int64_t>(nb, n - j0);
-        launch_panel_lu<T>(M.p, n, n, j0, w, F->top_piv.p, ctx->d_err, s);
+        launch_panel_lu<T>(M.p, n, n, j0, w, F->top_piv.p, ctx->d_err.p, s);
         launch_laswp<T>(M.p, n, n, j0, w, F->top_piv.p, j0, j0 + w, s);
         const int64_t rest = n - j0 - w;
         if (rest > 0) {
@@ -1227,7 +1252,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     H2_HIP(hipEventElapsedTime(&ms, et0, et1));
     phase_ms[7] += ms;
     int herr = 0;
-    H2_HIP(hipMemcpy(&herr, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost));
+    H2_HIP(hipMemcpy(&herr, ctx->d_err.p, sizeof(int), hipMemcpyDeviceToHost));
     if (herr & 1) throw H2Error(H2_ERROR_SINGULAR, "zero pivot in the dense top block");
     ar.reset();
   }
@@ -1251,14 +1276,29 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
 }
 
 std::vector<h2_factor_s*> factor(h2_context_s* ctx, const std::vector<h2_matrix_s*>& Hs,
-                                 double tol, h2_prec prec) {
+                                 double tol, h2_prec prec, const h2_factor_opts& opts) {
   std::vector<h2_factor_s*> out;
   std::vector<std::unique_ptr<h2_factor_s>> own;
+  // the call's byte accounting: every factor's storage and the shared
+  // workspaces count against opts.pool_bytes
+  DevTracker calltr;
+  calltr.mem = &ctx->mem;
+  calltr.cap = opts.pool_bytes;
+  struct Detach {  // factors outlive the call's tracker
+    std::vector<std::unique_ptr<h2_factor_s>>& fs;
+    ~Detach() {
+      for (auto& f : fs)
+        if (f) f->tr.parent = nullptr;
+    }
+  } detach{own};
   for (auto* H : Hs) {
     own.emplace_back(new h2_factor_s());
     h2_factor_s* F = own.back().get();
     F->ctx = ctx;
     F->prec = prec;
+    F->tr.mem = &ctx->mem;
+    F->tr.parent = &calltr;
+    F->keep_owners = opts.keep_owner_lists != 0;
     F->N = H->N;
     F->L = H->L;
     F->top = H->top;
@@ -1271,26 +1311,33 @@ std::vector<h2_factor_s*> factor(h2_context_s* ctx, const std::vector<h2_matrix_
     H2_HIP(hipMemcpyAsync(F->perm_d.p, H->perm_d.p, sizeof(int64_t) * H->N,
                           hipMemcpyDeviceToDevice, ctx->stream));
   }
+  auto norm_of = [&](const h2_matrix_s* H) { return opts.norm2 > 0 ? opts.norm2 : H->norm2; };
   if (prec == H2_PREC_FP64) {
     std::vector<Inst<double>> insts(Hs.size());
     for (size_t i = 0; i < Hs.size(); ++i) {
       insts[i].H = Hs[i];
       insts[i].F = own[i].get();
       insts[i].data = Hs[i]->data.p;
+      insts[i].norm = norm_of(Hs[i]);
     }
-    run_factor<double>(ctx, insts, tol);
+    run_factor<double>(ctx, insts, tol, &calltr);
   } else {
     std::vector<Inst<float>> insts(Hs.size());
     for (size_t i = 0; i < Hs.size(); ++i) {
       insts[i].H = Hs[i];
       insts[i].F = own[i].get();
-      insts[i].data_conv.alloc(Hs[i]->ndata, &own[i]->tr);
+      insts[i].data_conv.alloc(Hs[i]->ndata, &calltr);
       launch_convert<float>(insts[i].data_conv.p, Hs[i]->data.p, Hs[i]->ndata, ctx->stream);
       insts[i].data = insts[i].data_conv.p;
+      insts[i].norm = norm_of(Hs[i]);
     }
-    run_factor<float>(ctx, insts, tol);
+    run_factor<float>(ctx, insts, tol, &calltr);
   }
   H2_HIP(hipStreamSynchronize(ctx->stream));
+  for (auto& p : own) {
+    p->stats.peak_bytes = calltr.peak;
+    p->tr.parent = nullptr;
+  }
   for (auto& p : own) out.push_back(p.release());
   return out;
 }

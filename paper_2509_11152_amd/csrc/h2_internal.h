@@ -25,9 +25,60 @@ struct H2Error : std::runtime_error {
                     std::string(#call) + ": " + hipGetErrorString(e_));                \
   } while (0)
 
-// device allocation with byte accounting
+// Device memory of a context: the caller's allocator callbacks, or the
+// device's default stream-ordered memory pool (hipMallocAsync / hipFreeAsync
+// on the context's stream, freed blocks kept in the pool for reuse).  Either
+// way a block released here may be handed out again to later work of the
+// same stream, so releases need no synchronisation.
+struct DevMem {
+  h2_alloc_fn fa = nullptr;
+  h2_free_fn ff = nullptr;
+  void* user = nullptr;
+  hipStream_t s = nullptr;
+  void* get(size_t bytes) {
+    void* p = nullptr;
+    if (fa) {
+      p = fa(bytes, (void*)s, user);
+    } else if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+    }
+    if (!p)
+      throw H2Error(H2_ERROR_OUT_OF_MEMORY,
+                    "device allocation of " + std::to_string(bytes) + " bytes failed");
+    return p;
+  }
+  void put(void* p, size_t bytes) {
+    if (!p) return;
+    if (ff)
+      ff(p, bytes, (void*)s, user);
+    else
+      (void)hipFreeAsync(p, s);
+  }
+};
+
+// Byte accounting of one owner (a matrix, a factor, a context's work
+// arrays).  `cap` > 0 limits the bytes held at once; a tracker with a parent
+// also counts against the parent (one factorization call over several
+// instances shares one cap).
 struct DevTracker {
-  int64_t cur = 0, peak = 0;
+  DevMem* mem = nullptr;
+  int64_t cur = 0, peak = 0, cap = 0;
+  DevTracker* parent = nullptr;
+  void add(int64_t b) {
+    for (DevTracker* t = this; t; t = t->parent)
+      if (t->cap > 0 && t->cur + b > t->cap)
+        throw H2Error(H2_ERROR_OUT_OF_MEMORY,
+                      "device memory cap of " + std::to_string(t->cap) + " bytes reached (" +
+                          std::to_string(t->cur) + " held, " + std::to_string(b) + " requested)");
+    for (DevTracker* t = this; t; t = t->parent) {
+      t->cur += b;
+      if (t->cur > t->peak) t->peak = t->cur;
+    }
+  }
+  void sub(int64_t b) {
+    for (DevTracker* t = this; t; t = t->parent) t->cur -= b;
+  }
 };
 
 template <class T> struct DevArray {
@@ -56,26 +107,22 @@ template <class T> struct DevArray {
   void alloc(int64_t count, DevTracker* t) {
     release();
     tr = t;
-    n = count;
     if (count > 0) {
-      hipError_t e = hipMalloc((void**)&p, sizeof(T) * (size_t)count);
-      if (e != hipSuccess) {
-        p = nullptr;
-        n = 0;
-        (void)hipGetLastError();
-        throw H2Error(H2_ERROR_OUT_OF_MEMORY,
-                      "device allocation of " + std::to_string(sizeof(T) * count) + " bytes failed");
+      const int64_t b = (int64_t)sizeof(T) * count;
+      tr->add(b);
+      try {
+        p = (T*)tr->mem->get((size_t)b);
+      } catch (...) {
+        tr->sub(b);
+        throw;
       }
-      if (tr) {
-        tr->cur += (int64_t)sizeof(T) * count;
-        if (tr->cur > tr->peak) tr->peak = tr->cur;
-      }
+      n = count;
     }
   }
   void release() {
     if (p) {
-      (void)hipFree(p);
-      if (tr) tr->cur -= (int64_t)sizeof(T) * n;
+      tr->mem->put(p, (size_t)bytes());
+      tr->sub(bytes());
     }
     p = nullptr;
     n = 0;
@@ -97,11 +144,12 @@ struct DescArena {
   std::vector<Chunk> chunks;
   size_t cur = 0, used = 0;  // chunk being filled and bytes used in it
   hipStream_t s = nullptr;
+  DevMem* mem = nullptr;
   ~DescArena() { free_all(); }
   void free_all() {
     for (auto& c : chunks) {
       if (c.h) (void)hipHostFree(c.h);
-      if (c.d) (void)hipFree(c.d);
+      if (c.d) mem->put(c.d, c.cap);
     }
     chunks.clear();
     cur = used = 0;
@@ -119,11 +167,11 @@ struct DescArena {
       Chunk c;
       c.cap = std::max(need, (size_t)64 << 20);
       H2_HIP(hipHostMalloc((void**)&c.h, c.cap, hipHostMallocDefault));
-      hipError_t e = hipMalloc((void**)&c.d, c.cap);
-      if (e != hipSuccess) {
+      try {
+        c.d = (char*)mem->get(c.cap);
+      } catch (...) {
         (void)hipHostFree(c.h);
-        (void)hipGetLastError();
-        throw H2Error(H2_ERROR_OUT_OF_MEMORY, "descriptor arena allocation failed");
+        throw;
       }
       chunks.push_back(c);
       used = 0;
@@ -140,8 +188,11 @@ struct DescArena {
 struct h2_context_s {
   int device = 0;
   hipStream_t stream = nullptr;
+  bool own_stream = false;  // created by the context (destroyed with it)
   std::string err;
-  int* d_err = nullptr;  // device error word: bit0 zero pivot, bit1 non-finite
+  DevMem mem;
+  DevTracker tr;            // the context's own work arrays
+  DevArray<int> d_err;      // device error word: bit0 zero pivot, bit1 non-finite
   DescArena arena;
   // partial tiles of split skinny GEMMs (grown on demand, after a stream sync)
   DevArray<float> parts32;
@@ -195,6 +246,8 @@ struct LevelPlan {
   int64_t nD = 0, nF = 0, nQ = 0, nV = 0, nPiv = 0;
   std::vector<int> r;          // redundant counts (host copy after the level)
   std::vector<std::pair<int, int>> fill_pairs;  // (j, k) local, sorted (integer output)
+  // Schur target lists, kept on request: records (c, j, k, m, i_1..i_m), global ids
+  std::vector<int64_t> owners;
   int64_t find(int i, int j) const {
     int64_t lo = pptr[i], hi = pptr[i + 1];
     while (lo < hi) {
@@ -213,6 +266,8 @@ template <class T> struct LevelStore {
 // a solve's recorded launch sequence, kept with its factor (h2_solve.cpp)
 struct SolvePlanBase {
   virtual ~SolvePlanBase() = default;
+  virtual int64_t uses() const = 0;        // solves served by the plan
+  virtual int64_t graph_uses() const = 0;  // of those, one graph launch each
 };
 
 struct h2_factor_s {
@@ -236,5 +291,6 @@ struct h2_factor_s {
   DevArray<int32_t> top_piv;
   DevTracker tr;
   h2_stats stats{};
+  bool keep_owners = false;
   std::unique_ptr<SolvePlanBase> splan;  // last recorded solve
 };

@@ -63,7 +63,7 @@ template <class T> struct FillRef {
   int32_t ncols, d0;
 };
 
-// One stage of the tall-skinny QR of a fill row Y (Section 3, QR-based
+// One stage of the tall-skinny QR of a fill row Y (Section 2.1, QR-based
 // augmentation): the R factor of the rows of Y^T held by a group of fill
 // blocks.  It is written as an n x n fill block, out[col + t n] = R[t][col],
 // so a later stage can read the factors like fill blocks; later stages merge

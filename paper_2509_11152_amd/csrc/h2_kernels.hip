@@ -488,7 +488,7 @@ void launch_strip(const STask<T>* tasks, int ntasks, const int32_t* dyn, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// Basis augmentation and complement (Section 3, QR-based augmentation).
+// Basis augmentation and complement (Section 2.1, QR-based augmentation).
 //  1. R = R-factor of Y^T, Y = [F_ij] the fill row, as a tall-skinny QR: the
 //     workgroups of k_rfactor reduce groups of fill blocks (Householder on
 //     stacked [R; next chunk of Y^T rows], triangle-on-top structured
@@ -785,7 +785,7 @@ void launch_rfactor(const RTask<T>* tasks, int ntasks, const FillRef<T>* refs,
 }
 
 // ---------------------------------------------------------------------------
-// Gram matrix of a cluster's fill row for the FP32 factorization (Section 3,
+// Gram matrix of a cluster's fill row for the FP32 factorization (Section 2.1,
 // first augmentation option): G = Y Y^T over the active columns of the fill
 // blocks, in FP64 from the FP32 entries (their products are exact), on FP64
 // MFMA.  Workgroup = one 64 x 64 tile of G; each wave owns a 32 x 32 quarter

@@ -87,7 +87,7 @@ template <class T> struct Emit {
         DevArray<T>& P = parts_of<T>(ctx);
         if (P.n < need) {
           H2_HIP(hipStreamSynchronize(s));  // earlier launches may still read it
-          P.alloc(std::max(need, 2 * P.n), nullptr);
+          P.alloc(std::max(need, 2 * P.n), &ctx->tr);
         }
         parts = P.p;
       }
@@ -283,7 +283,8 @@ template <class T> struct SolveInst {
 
 // Work vectors of one instance: per level the cluster segments (leaf level
 // first), then the top vector.
-template <class T> void solve_setup(SolveInst<T>& S, h2_factor_s* F, int nrhs) {
+template <class T>
+void solve_setup(SolveInst<T>& S, h2_factor_s* F, int nrhs, DevTracker* tr) {
   S.F = F;
   const size_t nlev = F->plans.size();
   S.vec = std::vector<DevArray<T>>(nlev + 1);
@@ -298,11 +299,11 @@ template <class T> void solve_setup(SolveInst<T>& S, h2_factor_s* F, int nrhs) {
       o += P.n[i];
     }
     S.vlen[li] = o;
-    S.vec[li].alloc(std::max<int64_t>(o, 1) * nrhs, nullptr);
+    S.vec[li].alloc(std::max<int64_t>(o, 1) * nrhs, tr);
   }
   S.voff[nlev] = F->top_off;
   S.vlen[nlev] = F->n_top;
-  S.vec[nlev].alloc(std::max<int64_t>(F->n_top, 1) * nrhs, nullptr);
+  S.vec[nlev].alloc(std::max<int64_t>(F->n_top, 1) * nrhs, tr);
 }
 
 // Algorithm 3 on the work vectors (the right-hand sides already gathered in
@@ -505,10 +506,12 @@ template <class T> struct SolvePlan : SolvePlanBase {
   // the plan's second use; `replays` counts uses
   hipGraphExec_t gexec = nullptr;
   bool graph_failed = false;
-  int64_t replays = 0;
+  int64_t replays = 0, graph_replays = 0;
   ~SolvePlan() override {
     if (gexec) (void)hipGraphExecDestroy(gexec);
   }
+  int64_t uses() const override { return replays; }
+  int64_t graph_uses() const override { return graph_replays; }
   // capture the replay of the steps on stream s; false if the runtime refuses
   bool capture(hipStream_t s) {
     if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
@@ -548,7 +551,7 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
       F->splan.reset();
       auto np = std::make_unique<SolvePlan<T>>();
       np->nrhs = nrhs;
-      solve_setup<T>(np->S, F, nrhs);
+      solve_setup<T>(np->S, F, nrhs, &F->tr);
       Emit<T> em;
       em.ctx = ctx;
       em.s = s;
@@ -557,10 +560,10 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
       std::swap(one[0], np->S);
       solve_body<T>(em, one, nrhs);
       std::swap(one[0], np->S);
-      np->img.alloc(std::max<int64_t>((int64_t)em.img.size(), 1), nullptr);
+      np->img.alloc(std::max<int64_t>((int64_t)em.img.size(), 1), &F->tr);
       if (!em.img.empty())
         H2_HIP(hipMemcpy(np->img.p, em.img.data(), em.img.size(), hipMemcpyHostToDevice));
-      if (em.parts_need > 0) np->parts.alloc(em.parts_need, nullptr);
+      if (em.parts_need > 0) np->parts.alloc(em.parts_need, &F->tr);
       np->steps = std::move(em.steps);
       plan = np.get();
       F->splan = std::move(np);
@@ -570,9 +573,10 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
     // first use: replay launch by launch; from the second on, one graph launch
     if (plan->replays > 0 && !plan->gexec && !plan->graph_failed)
       plan->graph_failed = !plan->capture(s);
-    if (plan->gexec)
+    if (plan->gexec) {
       H2_HIP(hipGraphLaunch(plan->gexec, s));
-    else
+      ++plan->graph_replays;
+    } else
       for (auto& st : plan->steps) st(s, plan->img.p, plan->parts.p);
     ++plan->replays;
     launch_scatter_rows<double, T>(X[0], ldx[0], S.vec[0].p, S.vlen[0], F->perm_d.p, F->N, nrhs,
@@ -582,7 +586,7 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
   }
   std::vector<SolveInst<T>> si(Fs.size());
   for (size_t q = 0; q < Fs.size(); ++q) {
-    solve_setup<T>(si[q], Fs[q], nrhs);
+    solve_setup<T>(si[q], Fs[q], nrhs, &ctx->tr);
     launch_gather_rows<T, double>(si[q].vec[0].p, si[q].vlen[0], B[q], ldb[q], Fs[q]->perm_d.p,
                                   Fs[q]->N, nrhs, s);
   }
@@ -635,10 +639,10 @@ void matvec(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int
   }
   const int64_t N = H->N;
   DevArray<double> xt, yt, xh, yh;
-  xt.alloc(N * nrhs, nullptr);
-  yt.alloc(N * nrhs, nullptr);
-  xh.alloc(std::max<int64_t>(H->hat_total, 1) * nrhs, nullptr);
-  yh.alloc(std::max<int64_t>(H->hat_total, 1) * nrhs, nullptr);
+  xt.alloc(N * nrhs, &ctx->tr);
+  yt.alloc(N * nrhs, &ctx->tr);
+  xh.alloc(std::max<int64_t>(H->hat_total, 1) * nrhs, &ctx->tr);
+  yh.alloc(std::max<int64_t>(H->hat_total, 1) * nrhs, &ctx->tr);
   const double* d = H->data.p;
   auto hx = [&](int q) { return xh.p + H->hat_off[q] * nrhs; };
   auto hy = [&](int q) { return yh.p + H->hat_off[q] * nrhs; };
@@ -719,16 +723,16 @@ bool solve_ir(h2_context_s* ctx, h2_matrix_s* H, h2_factor_s* F, const double* B
   };
   auto A = [&](const double* in, double* out) { matvec(ctx, H, in, in == X ? ldx : N, nrhs, out, N); };
   DevArray<double> R, T1, Vb, coef, nrm;
-  R.alloc(N * nrhs, nullptr);
-  T1.alloc(N * nrhs, nullptr);
-  Vb.alloc((int64_t)(m + 1) * N * nrhs, nullptr);
-  coef.alloc((int64_t)(m + 2) * nrhs, nullptr);
-  nrm.alloc(2 * (int64_t)nrhs, nullptr);
+  R.alloc(N * nrhs, &ctx->tr);
+  T1.alloc(N * nrhs, &ctx->tr);
+  Vb.alloc((int64_t)(m + 1) * N * nrhs, &ctx->tr);
+  coef.alloc((int64_t)(m + 2) * nrhs, &ctx->tr);
+  nrm.alloc(2 * (int64_t)nrhs, &ctx->tr);
   const int64_t vs = N * nrhs;  // stride between basis vectors
   std::vector<double> bnorm(nrhs), h(nrhs), hcol((size_t)(m + 1) * nrhs);
   // x0 = M^{-1} b
   DevArray<double> Bc;
-  Bc.alloc(N * nrhs, nullptr);
+  Bc.alloc(N * nrhs, &ctx->tr);
   H2_HIP(hipMemcpy2DAsync(Bc.p, N * 8, B, ldb * 8, N * 8, nrhs, hipMemcpyDeviceToDevice, s));
   precond(Bc.p, T1.p);
   H2_HIP(hipMemcpy2DAsync(X, ldx * 8, T1.p, N * 8, N * 8, nrhs, hipMemcpyDeviceToDevice, s));

@@ -66,3 +66,37 @@ GAUSS_L32 = dict(N=3000, dim=2, seed=3001, kernel=("gauss", 0.05, 1e-3), tree="k
                  eta=0.7, tol=1e-8, nrhs=4, rhs_seed=4001, p0=10)
 GAUSS_L128 = dict(N=4096, dim=2, seed=3002, kernel=("gauss", 0.05, 1e-3), tree="kd", leaf=128,
                   eta=0.7, tol=1e-8, nrhs=4, rhs_seed=4002, p0=10)
+
+
+def data_sections(blob):
+    """Element counts of the U, E, D and S sections of a blob's data (in that
+    order at the end of the blob), from the oracle's parse of its structure."""
+    from oracle import blob as ob
+
+    H = ob.parse(blob)
+    size = H.idx_end - H.idx_begin
+    leaf0 = H.level_ptr[H.L]
+    nU = sum(int(size[q] * H.rank[q]) for q in range(leaf0, H.n_nodes))
+    nE = sum(int(H.rank[c] * H.rank[H.parent[c]]) for c in range(1, H.n_nodes))
+    nD = sum(int(size[q] * size[H.near_col[e]]) for q in range(leaf0, H.n_nodes)
+             for e in range(H.near_ptr[q], H.near_ptr[q + 1]))
+    nS = sum(int(H.rank[q] * H.rank[H.far_col[e]]) for q in range(H.n_nodes)
+             for e in range(H.far_ptr[q], H.far_ptr[q + 1]))
+    return nU, nE, nD, nS
+
+
+def scaled_blob(blob, s, scale_norm=True):
+    """The same H^2 matrix times s: near blocks D and couplings S scaled (the
+    orthonormal bases unchanged), and the header's ||A||_2 (at byte 32) scaled
+    too unless scale_norm is False."""
+    import numpy as np
+
+    b = np.array(blob, dtype=np.uint8)
+    nU, nE, nD, nS = data_sections(b)
+    start = b.nbytes - 8 * (nD + nS)
+    d = b[start:].view(np.float64) * s
+    b[start:] = d.view(np.uint8)
+    if scale_norm:
+        norm = b[32:40].view(np.float64)[0] * s
+        b[32:40] = np.array([norm]).view(np.uint8)
+    return b

@@ -69,10 +69,12 @@ def test_matvec(lib, ctx, name, spec):
 
 @pytest.mark.parametrize("name,spec", CASES)
 def test_factor_integer_outputs(lib, ctx, name, spec):
+    from oracle import factor as of
+
     print(f"[gpu] factor integers {name}", flush=True)
     H = gpu_matrix(lib, ctx, name, spec)
     tol = workload(name, spec)["spec"]["tol"]
-    F = lib.Factor(ctx, H, tol)
+    F = lib.Factor(ctx, H, tol, keep_owner_lists=True)
     Fo = oracle_factor(name, spec=spec)
     assert F.levels() == [Lf.level for Lf in Fo.levels]
     for Lf in Fo.levels:
@@ -82,6 +84,12 @@ def test_factor_integer_outputs(lib, ctx, name, spec):
         fill = F.ints(lev, lib.INT_FILL).reshape(-1, 2)
         assert [tuple(x) for x in fill.tolist()] == Lf.fpat
         assert F.ints(lev, lib.INT_RANKS).tolist() == [Lf.kt[q] for q in Lf.nodes]
+        # Section 2.2's layout (prefix sums of block dimension products) and
+        # the per-colour Schur target lists
+        lay = F.ints(lev, lib.INT_OFFSETS).reshape(-1, 4)
+        assert [tuple(x) for x in lay.tolist()] == of.block_layout(Lf)
+        assert F.ints(lev, lib.INT_CLUSTER_OFFSETS).tolist() == of.cluster_offsets(Lf)
+        assert F.ints(lev, lib.INT_OWNERS).tolist() == of.owner_records(Lf)
     assert int(F.ints(0, lib.INT_NTOP)[0]) == Fo.n_top
 
 
@@ -159,6 +167,10 @@ def test_solve_graph_replays_match_eager(lib, ctx, prec):
         ctx.sync()
     X2 = F.solve(2 * B).cpu().numpy()
     assert np.array_equal(X2, 2 * X0)
+    st = F.stats()
+    # five solves through the recorded plan, every one after the first as a
+    # single graph launch
+    assert st["solves"] == 5 and st["solve_graph_launches"] == 4, st
     Xd = lib.solve_batched(ctx, [F, F], [B, B])
     assert np.array_equal(Xd[0].cpu().numpy(), X0)
     assert np.array_equal(Xd[1].cpu().numpy(), X0)

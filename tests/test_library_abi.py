@@ -37,4 +37,4 @@ def test_status_strings_and_argument_errors():
     assert lib.h2_context_destroy(None) == 1
     assert lib.h2_matrix_destroy(None) == 1
     assert lib.h2_factor_destroy(None) == 1
-    assert lib.h2_context_create(0, None, None) == 1
+    assert lib.h2_context_create(None, None) == 1

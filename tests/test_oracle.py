@@ -160,3 +160,62 @@ def test_gmres_ir_reaches_1e12():
     Xd = np.linalg.solve(h2ops.dense(H), B)
     assert np.linalg.norm(X - Xd) <= 1e-9 * np.linalg.norm(Xd)
     assert all(k > 0 for k in its)
+
+
+@pytest.mark.parametrize("s", [1e3, 1024.0])
+def test_truncation_threshold_scales_with_the_norm(s):
+    """eps_fill = eps_lu ||A|| (Section 2.1): the same matrix times s, with its
+    norm times s, keeps every augmented rank, and its solution is X / s.  With
+    the norm left unscaled the threshold no longer follows the matrix and the
+    ranks change, so a threshold that dropped the norm fails this test."""
+    from conftest import scaled_blob
+    from oracle import blob as ob
+
+    w = workload("exp3d_4096", EXP3D_4096)
+    tol = w["spec"]["tol"]
+    Fo = oracle_factor("exp3d_4096", spec=EXP3D_4096)
+    Hs = ob.parse(scaled_blob(w["blob"], s))
+    assert Hs.norm2 == pytest.approx(s * oracle_matrix("exp3d_4096", EXP3D_4096).norm2, rel=1e-15)
+    Fs = of.factor(Hs, tol)
+    for La, Lb in zip(Fo.levels, Fs.levels):
+        assert [La.kt[q] for q in La.nodes] == [Lb.kt[q] for q in Lb.nodes]
+    X = of.solve(Fo, w["B"])
+    Xs = of.solve(Fs, w["B"])
+    assert np.linalg.norm(s * Xs - X) <= 1e-12 * np.linalg.norm(X)
+    Fu = of.factor(ob.parse(scaled_blob(w["blob"], s, scale_norm=False)), tol)
+    ku = [Lb.kt[q] for Lb in Fu.levels for q in Lb.nodes]
+    ko = [La.kt[q] for La in Fo.levels for q in La.nodes]
+    assert ku != ko and sum(ku) > sum(ko)
+
+
+def test_linear_time_and_memory():
+    """Section 2.4 and Section 3.3: factor + solve time and memory grow
+    linearly with N.  Oracle wall time and peak traced memory (numpy buffers
+    allocated during factor + solve) over N = 4096 ... 32768 (2D exponential
+    covariance, binary KD tree, leaf 64, tol 1e-8): the fitted log-log slopes
+    lie near 1 (fixed per-call costs pull the time slope below 1 at the small
+    end)."""
+    import time
+    import tracemalloc
+
+    from h2gen import workloads
+    from oracle import blob as ob
+
+    base = dict(workloads.WORKLOADS["exp2d_4096"], tree="kd")
+    Ns, ts, ms = [4096, 8192, 16384, 32768], [], []
+    for N in Ns:
+        spec = dict(base, N=N)
+        w = workloads.make(spec)
+        H = ob.parse(w["blob"])
+        tracemalloc.start()
+        t0 = time.perf_counter()
+        Fz = of.factor(H, spec["tol"])
+        of.solve(Fz, w["B"])
+        ts.append(time.perf_counter() - t0)
+        ms.append(tracemalloc.get_traced_memory()[1])
+        tracemalloc.stop()
+    lt = np.polyfit(np.log(Ns), np.log(ts), 1)[0]
+    lm = np.polyfit(np.log(Ns), np.log(ms), 1)[0]
+    print(f"time slope {lt:.3f} ({ts}), memory slope {lm:.3f} ({ms})")
+    assert 0.8 <= lt <= 1.2
+    assert 0.85 <= lm <= 1.2
