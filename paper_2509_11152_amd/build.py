@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libh2rss.so")
-SOURCES = ["h2_kernels.hip", "h2_api.cpp", "h2_factor.cpp", "h2_solve.cpp"]
+# every HIP and C++ source of csrc/ (the C++ ones are compiled as HIP too)
+SOURCES = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
     # no packed FP32 instructions in any device code

@@ -9,6 +9,10 @@ namespace h2drv {
 void matvec(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int nrhs, double* Y,
             int64_t ldy);
 
+// the product with its work arrays in caller-provided device memory
+void matvec_in(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int nrhs,
+               double* Y, int64_t ldy, char* scratch, int64_t cap);
+
 std::vector<h2_factor_s*> factor(h2_context_s* ctx, const std::vector<h2_matrix_s*>& Hs,
                                  double tol, h2_prec prec, const h2_factor_opts& opts);
 

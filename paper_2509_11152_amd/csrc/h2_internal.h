@@ -185,6 +185,14 @@ struct DescArena {
   }
 };
 
+// a recorded launch sequence (a solve kept with its factor, a product kept
+// with its matrix; h2_solve.cpp)
+struct PlanBase {
+  virtual ~PlanBase() = default;
+  virtual int64_t uses() const = 0;        // calls served by the plan
+  virtual int64_t graph_uses() const = 0;  // of those, one graph launch each
+};
+
 struct h2_context_s {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -223,10 +231,11 @@ struct h2_matrix_s {
     while (l + 1 < (int)lp.size() && lp[l + 1] <= q) ++l;
     return l;
   }
-  // matvec plan (built lazily)
+  // matvec layout (built lazily) and the last recorded product
   bool mv_ready = false;
   std::vector<int64_t> hat_off;  // per node offset (in units of rank) into the hat vectors
   int64_t hat_total = 0;
+  std::unique_ptr<PlanBase> mvplan;
 };
 
 // ---- factorization data of one skeletonized level of one matrix ----
@@ -263,12 +272,6 @@ template <class T> struct LevelStore {
   DevArray<int32_t> piv;
 };
 
-// a solve's recorded launch sequence, kept with its factor (h2_solve.cpp)
-struct SolvePlanBase {
-  virtual ~SolvePlanBase() = default;
-  virtual int64_t uses() const = 0;        // solves served by the plan
-  virtual int64_t graph_uses() const = 0;  // of those, one graph launch each
-};
 
 struct h2_factor_s {
   h2_context_s* ctx = nullptr;
@@ -292,5 +295,5 @@ struct h2_factor_s {
   DevTracker tr;
   h2_stats stats{};
   bool keep_owners = false;
-  std::unique_ptr<SolvePlanBase> splan;  // last recorded solve
+  std::unique_ptr<PlanBase> splan;  // last recorded solve
 };

@@ -496,22 +496,28 @@ void solve_body(Emit<T>& em, std::vector<SolveInst<T>>& si, int nrhs) {
   }
 }
 
-template <class T> struct SolvePlan : SolvePlanBase {
-  int nrhs = 0;
-  SolveInst<T> S;
+// A recorded launch sequence: the descriptors in one device image, each
+// launch a replay step.  The first use replays the steps launch by launch;
+// the second captures them as one HIP graph (kernel nodes only) and later
+// uses launch the graph.  If the runtime refuses the capture, the steps keep
+// being replayed one by one.
+template <class T> struct Replay {
   DevArray<char> img;  // recorded descriptors
   DevArray<T> parts;   // partial tiles of split products
   std::vector<typename Emit<T>::Step> steps;
-  // the steps captured as one HIP graph (kernel nodes only), instantiated on
-  // the plan's second use; `replays` counts uses
   hipGraphExec_t gexec = nullptr;
   bool graph_failed = false;
-  int64_t replays = 0, graph_replays = 0;
-  ~SolvePlan() override {
+  int64_t uses = 0, graph_uses = 0;
+  ~Replay() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
   }
-  int64_t uses() const override { return replays; }
-  int64_t graph_uses() const override { return graph_replays; }
+  void take(Emit<T>& em, DevTracker* tr) {
+    img.alloc(std::max<int64_t>((int64_t)em.img.size(), 1), tr);
+    if (!em.img.empty())
+      H2_HIP(hipMemcpy(img.p, em.img.data(), em.img.size(), hipMemcpyHostToDevice));
+    if (em.parts_need > 0) parts.alloc(em.parts_need, tr);
+    steps = std::move(em.steps);
+  }
   // capture the replay of the steps on stream s; false if the runtime refuses
   bool capture(hipStream_t s) {
     if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
@@ -533,6 +539,24 @@ template <class T> struct SolvePlan : SolvePlanBase {
     }
     return true;
   }
+  void run(hipStream_t s) {
+    if (uses > 0 && !gexec && !graph_failed) graph_failed = !capture(s);
+    if (gexec) {
+      H2_HIP(hipGraphLaunch(gexec, s));
+      ++graph_uses;
+    } else {
+      for (auto& st : steps) st(s, img.p, parts.p);
+    }
+    ++uses;
+  }
+};
+
+template <class T> struct SolvePlan : PlanBase {
+  int nrhs = 0;
+  SolveInst<T> S;
+  Replay<T> rp;
+  int64_t uses() const override { return rp.uses; }
+  int64_t graph_uses() const override { return rp.graph_uses; }
 };
 
 template <class T>
@@ -560,25 +584,13 @@ void run_solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
       std::swap(one[0], np->S);
       solve_body<T>(em, one, nrhs);
       std::swap(one[0], np->S);
-      np->img.alloc(std::max<int64_t>((int64_t)em.img.size(), 1), &F->tr);
-      if (!em.img.empty())
-        H2_HIP(hipMemcpy(np->img.p, em.img.data(), em.img.size(), hipMemcpyHostToDevice));
-      if (em.parts_need > 0) np->parts.alloc(em.parts_need, &F->tr);
-      np->steps = std::move(em.steps);
+      np->rp.take(em, &F->tr);
       plan = np.get();
       F->splan = std::move(np);
     }
     SolveInst<T>& S = plan->S;
     launch_gather_rows<T, double>(S.vec[0].p, S.vlen[0], B[0], ldb[0], F->perm_d.p, F->N, nrhs, s);
-    // first use: replay launch by launch; from the second on, one graph launch
-    if (plan->replays > 0 && !plan->gexec && !plan->graph_failed)
-      plan->graph_failed = !plan->capture(s);
-    if (plan->gexec) {
-      H2_HIP(hipGraphLaunch(plan->gexec, s));
-      ++plan->graph_replays;
-    } else
-      for (auto& st : plan->steps) st(s, plan->img.p, plan->parts.p);
-    ++plan->replays;
+    plan->rp.run(s);
     launch_scatter_rows<double, T>(X[0], ldx[0], S.vec[0].p, S.vlen[0], F->perm_d.p, F->N, nrhs,
                                    s);
     H2_HIP(hipStreamSynchronize(s));
@@ -618,35 +630,30 @@ void solve(h2_context_s* ctx, const std::vector<h2_factor_s*>& Fs,
 // FP64 H^2 matvec: permute, upsweep U^T / E^T, couplings, downsweep E,
 // leaf bases U plus dense near blocks, permute back.
 // ---------------------------------------------------------------------------
-void matvec(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int nrhs, double* Y,
-            int64_t ldy) {
-  hipStream_t s = ctx->stream;
-  DescArena& ar = ctx->arena;
-  ar.s = s;
-  const int shape = nrhs > 16 ? 0 : 1;
-  Emit<double> em;
-  em.ctx = ctx;
-  em.s = s;
-  if (!H->mv_ready) {
-    H->hat_off.assign(H->nn, 0);
-    int64_t o = 0;
-    for (int q = 0; q < H->nn; ++q) {
-      H->hat_off[q] = o;
-      o += H->rank[q];
-    }
-    H->hat_total = o;
-    H->mv_ready = true;
+namespace {
+
+// per node offsets into the upsweep / downsweep coefficient vectors
+void matvec_layout(h2_matrix_s* H) {
+  if (H->mv_ready) return;
+  H->hat_off.assign(H->nn, 0);
+  int64_t o = 0;
+  for (int q = 0; q < H->nn; ++q) {
+    H->hat_off[q] = o;
+    o += H->rank[q];
   }
+  H->hat_total = o;
+  H->mv_ready = true;
+}
+
+// The product's launches on tree-ordered work vectors: xt (N x nrhs) in,
+// yt out, xh / yh the basis coefficients (hat_total x nrhs).
+void matvec_body(Emit<double>& em, const h2_matrix_s* H, const double* xt, double* yt, double* xh,
+                 double* yh, int nrhs) {
+  const int shape = nrhs > 16 ? 0 : 1;
   const int64_t N = H->N;
-  DevArray<double> xt, yt, xh, yh;
-  xt.alloc(N * nrhs, &ctx->tr);
-  yt.alloc(N * nrhs, &ctx->tr);
-  xh.alloc(std::max<int64_t>(H->hat_total, 1) * nrhs, &ctx->tr);
-  yh.alloc(std::max<int64_t>(H->hat_total, 1) * nrhs, &ctx->tr);
   const double* d = H->data.p;
-  auto hx = [&](int q) { return xh.p + H->hat_off[q] * nrhs; };
-  auto hy = [&](int q) { return yh.p + H->hat_off[q] * nrhs; };
-  launch_gather_rows<double, double>(xt.p, N, X, ldx, H->perm_d.p, N, nrhs, s);
+  auto hx = [&](int q) { return xh + H->hat_off[q] * nrhs; };
+  auto hy = [&](int q) { return yh + H->hat_off[q] * nrhs; };
   const int L = H->L;
   if (H->top >= 0) {
     // leaves: xh = U^T x
@@ -654,7 +661,7 @@ void matvec(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int
     for (int q = H->lp[L]; q < H->nn; ++q) {
       if (!H->rank[q]) continue;
       gb.out(hx(q), H->rank[q], 0, H->rank[q], 0, nrhs, 1.0, 0.0);
-      gb.con(d + H->offU[q], H->size(q), 1, xt.p + H->ib[q], N, 0, H->size(q));
+      gb.con(d + H->offU[q], H->size(q), 1, xt + H->ib[q], N, 0, H->size(q));
       gb.end();
     }
     gb.launch(em);
@@ -690,23 +697,104 @@ void matvec(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int
       gb.launch(em);
     }
   }
-  {
-    GemmBatch<double> gb(shape);
-    for (int q = H->lp[L]; q < H->nn; ++q) {
-      gb.out(yt.p + H->ib[q], N, 0, H->size(q), 0, nrhs, 1.0, 0.0);
-      if (H->top >= 0 && H->rank[q])
-        gb.con(d + H->offU[q], H->size(q), 0, hy(q), H->rank[q], 0, H->rank[q]);
-      for (int64_t e = H->near_ptr[q]; e < H->near_ptr[q + 1]; ++e) {
-        const int j = H->near_col[e];
-        gb.con(d + H->offD[e], H->size(q), 0, xt.p + H->ib[j], N, 0, H->size(j));
-      }
-      gb.end();
+  GemmBatch<double> gb(shape);
+  for (int q = H->lp[L]; q < H->nn; ++q) {
+    gb.out(yt + H->ib[q], N, 0, H->size(q), 0, nrhs, 1.0, 0.0);
+    if (H->top >= 0 && H->rank[q])
+      gb.con(d + H->offU[q], H->size(q), 0, hy(q), H->rank[q], 0, H->rank[q]);
+    for (int64_t e = H->near_ptr[q]; e < H->near_ptr[q + 1]; ++e) {
+      const int j = H->near_col[e];
+      gb.con(d + H->offD[e], H->size(q), 0, xt + H->ib[j], N, 0, H->size(j));
     }
-    gb.launch(em);
+    gb.end();
   }
-  launch_scatter_rows<double, double>(Y, ldy, yt.p, N, H->perm_d.p, N, nrhs, s);
+  gb.launch(em);
+}
+
+struct MatvecPlan : PlanBase {
+  int nrhs = 0;
+  DevArray<double> xt, yt, xh, yh;
+  Replay<double> rp;
+  int64_t uses() const override { return rp.uses; }
+  int64_t graph_uses() const override { return rp.graph_uses; }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// FP64 H^2 matvec: permute, upsweep U^T / E^T, couplings, downsweep E,
+// leaf bases U plus dense near blocks, permute back.  The launch sequence is
+// recorded once per (matrix, nrhs) with its work vectors and replayed (as one
+// graph from the second call on).
+// ---------------------------------------------------------------------------
+void matvec(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int nrhs, double* Y,
+            int64_t ldy) {
+  hipStream_t s = ctx->stream;
+  matvec_layout(H);
+  auto* plan = dynamic_cast<MatvecPlan*>(H->mvplan.get());
+  if (!plan || plan->nrhs != nrhs) {
+    H->mvplan.reset();
+    auto np = std::make_unique<MatvecPlan>();
+    np->nrhs = nrhs;
+    const int64_t N = H->N;
+    np->xt.alloc(N * nrhs, &H->tr);
+    np->yt.alloc(N * nrhs, &H->tr);
+    np->xh.alloc(std::max<int64_t>(H->hat_total, 1) * nrhs, &H->tr);
+    np->yh.alloc(std::max<int64_t>(H->hat_total, 1) * nrhs, &H->tr);
+    Emit<double> em;
+    em.ctx = ctx;
+    em.s = s;
+    em.rec = true;
+    matvec_body(em, H, np->xt.p, np->yt.p, np->xh.p, np->yh.p, nrhs);
+    np->rp.take(em, &H->tr);
+    plan = np.get();
+    H->mvplan = std::move(np);
+  }
+  launch_gather_rows<double, double>(plan->xt.p, H->N, X, ldx, H->perm_d.p, H->N, nrhs, s);
+  plan->rp.run(s);
+  launch_scatter_rows<double, double>(Y, ldy, plan->yt.p, H->N, H->perm_d.p, H->N, nrhs, s);
+}
+
+// The product with every work array in caller-provided device memory
+// `scratch` of `cap` bytes (256-byte aligned): [xt | yt | xh | yh | the
+// descriptor image | partial tiles].  Allocates no device memory; the
+// descriptors are recorded on the host and copied in.  Synchronizes before
+// returning.
+void matvec_in(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, int nrhs,
+               double* Y, int64_t ldy, char* scratch, int64_t cap) {
+  hipStream_t s = ctx->stream;
+  matvec_layout(H);
+  auto up = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+  const int64_t N = H->N, nh = std::max<int64_t>(H->hat_total, 1);
+  const int64_t vec = up(8 * (2 * N + 2 * nh) * nrhs);
+  if (vec > cap)
+    throw H2Error(H2_ERROR_UNSUPPORTED, "the product's vectors need " + std::to_string(vec) +
+                                            " bytes of scratch, more than the " +
+                                            std::to_string(cap) + " available");
+  double* xt = reinterpret_cast<double*>(scratch);
+  double* yt = xt + N * nrhs;
+  double* xh = yt + N * nrhs;
+  double* yh = xh + nh * nrhs;
+  Emit<double> em;
+  em.ctx = ctx;
+  em.s = s;
+  em.rec = true;
+  matvec_body(em, H, xt, yt, xh, yh, nrhs);
+  const int64_t img = up((int64_t)em.img.size());
+  const int64_t need = vec + img + 8 * em.parts_need;
+  if (need > cap)
+    throw H2Error(H2_ERROR_UNSUPPORTED, "the product needs " + std::to_string(need) +
+                                            " bytes of scratch, more than the " +
+                                            std::to_string(cap) + " available");
+  char* dimg = scratch + vec;
+  double* parts = reinterpret_cast<double*>(dimg + img);
+  if (!em.img.empty())
+    H2_HIP(hipMemcpyAsync(dimg, em.img.data(), em.img.size(), hipMemcpyHostToDevice, s));
+  launch_gather_rows<double, double>(xt, N, X, ldx, H->perm_d.p, N, nrhs, s);
+  for (auto& st : em.steps) st(s, dimg, parts);
+  launch_scatter_rows<double, double>(Y, ldy, yt, N, H->perm_d.p, N, nrhs, s);
+  // the host image must outlive its copy
   H2_HIP(hipStreamSynchronize(s));
-  ar.reset();
 }
 
 // ---------------------------------------------------------------------------
