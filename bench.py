@@ -2,19 +2,26 @@
 
 One step = the whole hot path on one synthetic system: FP32 factorization
 (MFMA, FP32 accumulation) followed by FP64 GMRES-IR to a backward error of
-1e-12 (the FP64 H^2 product supplies the residuals).  The FP64 path (FP64
-factor + the same refinement, and the plain FP64 factor + solve) is timed in
-the same run for comparison.  Inputs are resident in HBM before timing
-starts; construction of the synthetic H^2 matrix is not timed.
+1e-12 (the FP64 H^2 product supplies the residuals).  The default workload is
+the scale configuration: N = 2^20 points uniform in the unit cube, the
+regularised Laplace kernel 1/(4 pi (r + 1e-3)) + I, leaf size 64, tol 1e-6,
+32 right-hand sides.  The FP64 path (FP64 factor + the same refinement, and
+the plain FP64 factor + one solve) is timed in the same run for comparison.
+Inputs are resident in HBM before timing starts; construction of the
+synthetic H^2 matrix and its upload are reported under "setup_s", untimed.
 
-After the timed steps, the batched configuration (64 independent 2D systems,
-N_i log-uniform in [2048, 32768], FP64, leaf size chosen by timing) is
-factored and solved with one batched call each and reported under "batched"
-(work-model GFLOP/s).  "roofline" gives the dominant factor kernel's
-achieved rate and, from the committed PMC summary, its HBM traffic per launch.
+The whole run keeps to a wall-clock budget (--budget-s from process start):
+warm-up and timed steps stop early when the remaining ones would not fit, and
+the line reports the counts that ran ("steps", "warmup") next to the ones
+asked for.  The batched configuration (64 independent 2D systems, N_i
+log-uniform in [2048, 32768], FP64, leaf size chosen by timing; one batched
+factor and one batched solve call) runs when enough budget is left, under
+"batched" (work-model GFLOP/s).  The CPU oracle baseline runs in a child
+process on the host cores while the device works.  "roofline" gives the
+dominant factor kernel's achieved rate and, from the committed PMC summary,
+its HBM traffic per launch.
 
-Prints one JSON line (see the keys below).  Only one GPU is used: --gpus > 1
-exits with a message.
+Prints one JSON line.  Only one GPU is used: --gpus > 1 exits with a message.
 """
 import argparse
 import json
@@ -24,6 +31,7 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+T0 = time.perf_counter()
 
 METRIC = "N=2^20 factor+solve s, FP32+IR vs FP64 @ bkwd err 1e-12; batched GFLOP/s"
 PEAK = {"f64": 78.6, "f32": 157.3}  # TFLOP/s, dense MFMA
@@ -40,6 +48,17 @@ def parse():
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="exp3d_262144")
+    p.add_argument("--budget-s", type=float, default=540.0,
+                   help="wall-clock budget of the whole run from process start: warm-up and "
+                        "timed steps stop early (the line reports how many ran) when the rest "
+                        "would not fit")
+    p.add_argument("--reserve-s", type=float, default=90.0,
+                   help="part of the budget kept for the FP64 comparison and the report")
+    p.add_argument("--batched", action="store_true",
+                   help="always run the 64-instance batched measurement")
+    p.add_argument("--batched-s", type=float, default=240.0,
+                   help="run the batched measurement only when this much budget is left")
+    p.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-batched", action="store_true",
                    help="skip the 64-instance batched measurement")
@@ -186,7 +205,9 @@ def batched_bench(args, h2, ctx):
         f"{time.perf_counter() - t0:.1f} s")
     tf, ts = [], []
     Fs = Xs = None
-    for rep in range(args.warmup + args.steps):
+    # one untimed and three timed repetitions (the headline's step counts do
+    # not apply to this secondary figure)
+    for rep in range(1 + 3):
         Fs = Xs = None
         torch.cuda.synchronize()
         a = time.perf_counter()
@@ -196,7 +217,7 @@ def batched_bench(args, h2, ctx):
         Xs = h2.solve_batched(ctx, Fs, Bs)
         torch.cuda.synchronize()
         c = time.perf_counter()
-        if rep >= args.warmup:
+        if rep >= 1:
             tf.append(b - a)
             ts.append(c - b)
         log(f"[bench] batched rep {rep}: factor {b - a:.3f}s solve {c - b:.3f}s")
@@ -215,10 +236,11 @@ def batched_bench(args, h2, ctx):
             "workload": "gauss2d batch, 64 x N_i log-uniform in [2048, 32768]"}
 
 
-def cpu_baseline(spec_name):
-    """The oracle (single-threaded numpy FP64) on a bounded sample of the same
-    recipe (same kernel, tree, leaf size, tolerance and right-hand sides, fewer
-    points), extrapolated linearly in N (the method is O(N) in time)."""
+def cpu_baseline(spec_name, threads=1):
+    """The oracle (numpy FP64) on a bounded sample of the same recipe (same
+    kernel, tree, leaf size, tolerance and right-hand sides, fewer points),
+    extrapolated linearly in N (the method is O(N) in time), with its BLAS
+    limited to `threads` threads."""
     from threadpoolctl import threadpool_limits
 
     from h2gen import workloads
@@ -231,7 +253,7 @@ def cpu_baseline(spec_name):
     sample["N"] = 8192 if full["dim"] == 3 else 16384
     w = workloads.make(sample)
     H = ob.parse(w["blob"])
-    with threadpool_limits(1, user_api="blas"):
+    with threadpool_limits(threads, user_api="blas"):
         t0 = time.perf_counter()
         Fz = of.factor(H, sample["tol"])
         X, eb, its = oir.gmres_ir(H, Fz, w["B"], target=1e-12)
@@ -239,12 +261,66 @@ def cpu_baseline(spec_name):
     return {
         "value": dt * full["N"] / sample["N"],
         "unit": "s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
         "sample": f"oracle FP64 factor + GMRES-IR to 1e-12 at N={sample['N']} (same recipe, "
-                  f"{sample['nrhs']} RHS) took {dt:.2f} s on 1 core; value = that x N/{sample['N']} "
-                  f"(linear complexity)",
+                  f"{sample['nrhs']} RHS) took {dt:.2f} s with {threads} BLAS thread(s); "
+                  f"value = that x N/{sample['N']} (linear complexity)",
     }
+
+
+def host_info():
+    info = {"nproc": os.cpu_count()}
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                info["cpu"] = ln.split(":", 1)[1].strip()
+                break
+        for ln in open("/proc/meminfo"):
+            if ln.startswith("MemTotal"):
+                info["mem_gb"] = round(int(ln.split()[1]) / 1e6, 1)
+                break
+    except OSError:
+        pass
+    return info
+
+
+def cpu_baseline_main(args):
+    """Child process: the oracle baseline at one BLAS thread and at every host
+    core, printed as one JSON line."""
+    out = {"one_core": cpu_baseline(args.workload, 1)}
+    n = os.cpu_count() or 1
+    if n > 1:
+        out["all_cores"] = cpu_baseline(args.workload, n)
+    out["host"] = host_info()
+    print(json.dumps(out), flush=True)
+
+
+def start_cpu_baseline(args):
+    """Start the oracle baseline in a child process before this process touches
+    the GPU; it runs on the host cores while the device works."""
+    import subprocess
+
+    env = dict(os.environ)
+    env.setdefault("OMP_NUM_THREADS", str(os.cpu_count() or 1))
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
+                             "--workload", args.workload], stdout=subprocess.PIPE,
+                            stderr=subprocess.DEVNULL, text=True, env=env)
+
+
+def finish_cpu_baseline(proc, wait_s):
+    if proc is None:
+        return None
+    try:
+        out, _ = proc.communicate(timeout=max(wait_s, 1.0))
+    except Exception:
+        proc.kill()
+        proc.communicate()
+        return None
+    for ln in reversed(out.splitlines()):
+        if ln.startswith("{"):
+            return json.loads(ln)
+    return None
 
 
 def main():
@@ -252,15 +328,22 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.cpu_baseline_only:
+        cpu_baseline_main(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
               "described but not built", file=sys.stderr)
         sys.exit(2)
+    cpu_proc = None if args.no_cpu_baseline else start_cpu_baseline(args)
     import numpy as np
     import torch
 
     import paper_2509_11152_amd as h2
     from h2gen import workloads
+
+    def left():
+        return args.budget_s - (time.perf_counter() - T0)
 
     spec = workloads.WORKLOADS[args.workload]
     t0 = time.perf_counter()
@@ -275,45 +358,88 @@ def main():
         log(f"[bench] constructing {args.workload} (N={spec['N']}) on {args.construct_device}")
         w = workloads.make(spec, device=args.construct_device, verbose=True)
         w.pop("h", None)
+        torch.cuda.empty_cache()
         log(f"[bench] construction {time.perf_counter() - t0:.1f} s, blob {w['blob'].nbytes / 1e9:.2f} GB")
         if args.save_blob:
             np.save(args.save_blob + ".blob.npy", w["blob"])
             np.save(args.save_blob + ".rhs.npy", w["B"])
             log(f"[bench] wrote {args.save_blob}.blob.npy / .rhs.npy")
+    t_construct = time.perf_counter() - t0
     dev = torch.device("cuda:0")
     ctx = h2.Context(0)
+    t0 = time.perf_counter()
     H = h2.Matrix(ctx, w["blob"])
     B = torch.tensor(w["B"], dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t_load = time.perf_counter() - t0
+    blob_gb = w["blob"].nbytes / 1e9
+    del w
+    log(f"[bench] load + upload {t_load:.1f} s; {left():.0f} s of the budget left")
     tol = spec["tol"]
 
     def step32():
-        F = h2.Factor(ctx, H, tol, h2.H2_PREC_FP32)
-        X, rep = h2.solve_ir(ctx, H, F, B, target=1e-12)
-        return F, X, rep
-
-    def step64():
-        F = h2.Factor(ctx, H, tol, h2.H2_PREC_FP64)
-        X, rep = h2.solve_ir(ctx, H, F, B, target=1e-12)
-        return F, X, rep
-
-    for i in range(args.warmup):
-        log(f"[bench] warmup {i}")
-        step32()
-        step64()
-    t32, t64, t64p, tf32, tf64 = [], [], [], [], []
-    rep32 = rep64 = None
-    F32 = F64 = None
-    for i in range(args.steps):
         torch.cuda.synchronize()
         a = time.perf_counter()
-        F32 = h2.Factor(ctx, H, tol, h2.H2_PREC_FP32)
+        F = h2.Factor(ctx, H, tol, h2.H2_PREC_FP32)
         torch.cuda.synchronize()
         b = time.perf_counter()
-        X32, rep32 = h2.solve_ir(ctx, H, F32, B, target=1e-12)
+        X, rep = h2.solve_ir(ctx, H, F, B, target=1e-12)
         torch.cuda.synchronize()
         c = time.perf_counter()
-        t32.append(c - a)
-        tf32.append(b - a)
+        return F, X, rep, b - a, c - a
+
+    # FP32 factor + FP64 GMRES-IR: warm-up steps (at least one: first-use
+    # allocations), then the timed steps; both stop early, and say so, when
+    # the remaining steps would not fit in the time budget
+    reserve = args.reserve_s
+    per = None
+    warm = 0
+    while warm < max(args.warmup, 1):
+        if warm >= 1 and left() - reserve < 2.5 * per:
+            break
+        log(f"[bench] warmup {warm}")
+        a = time.perf_counter()
+        F32, X32, rep32, _, _ = step32()
+        del F32, X32
+        per = time.perf_counter() - a
+        warm += 1
+    t32, tf32 = [], []
+    F32 = X32 = rep32 = None
+    for i in range(args.steps):
+        if i >= 1 and left() - reserve < 1.5 * max(t32):
+            log(f"[bench] time budget: {i} of {args.steps} steps timed")
+            break
+        F32 = X32 = None
+        F32, X32, rep32, tf, tt = step32()
+        t32.append(tt)
+        tf32.append(tf)
+        log(f"[bench] step {i}: fp32+IR {tt:.3f}s (factor {tf:.3f}s); {left():.0f} s left")
+    s32 = F32.stats()
+    med = lambda v: float(np.median(v)) if v else None
+
+    def bkwd(X):
+        R = B - H.matvec(X)
+        return float((torch.linalg.norm(R, dim=0) / torch.linalg.norm(B, dim=0)).max())
+
+    eb32 = bkwd(X32)
+    del F32, X32
+    torch.cuda.empty_cache()
+    # the FP64 path: FP64 factor + the same refinement, and the plain FP64
+    # factor + one solve (its backward error stated), timed once after an
+    # untimed run when the budget allows
+    fp64 = {}
+    t64 = t64p = tf64 = None
+    eb64 = eb64p = None
+    s64 = None
+    reps64 = 0
+    est64 = 2.0 * value_or(med(t32), 1.0)
+    for rep in range(2):
+        if rep == 0 and left() - est64 * 2 < 60:
+            continue  # no time for an untimed run
+        if left() < est64 + 30:
+            break
+        torch.cuda.synchronize()
+        a = time.perf_counter()
         F64 = h2.Factor(ctx, H, tol, h2.H2_PREC_FP64)
         torch.cuda.synchronize()
         d = time.perf_counter()
@@ -323,30 +449,25 @@ def main():
         X64, rep64 = h2.solve_ir(ctx, H, F64, B, target=1e-12)
         torch.cuda.synchronize()
         f = time.perf_counter()
-        tf64.append(d - c)
-        t64p.append(e - c)
-        t64.append((f - e) + (d - c))
-        log(f"[bench] step {i}: fp32+IR {t32[-1]:.3f}s  fp64+IR {t64[-1]:.3f}s  fp64 {t64p[-1]:.3f}s")
-    # backward errors with the FP64 product
-    def bkwd(X):
-        R = B - H.matvec(X)
-        return float((torch.linalg.norm(R, dim=0) / torch.linalg.norm(B, dim=0)).max())
-
-    eb32, eb64, eb64p = bkwd(X32), bkwd(X64), bkwd(X64p)
-    s32 = F32.stats()
-    s64 = F64.stats()
-    med = lambda v: float(np.median(v))
+        tf64, t64p, t64 = d - a, e - a, (f - e) + (d - a)
+        est64 = t64 + t64p - tf64
+        reps64 = rep + 1
+        eb64, eb64p = bkwd(X64), bkwd(X64p)
+        s64 = F64.stats()
+        fp64 = {"ir": rep64}
+        del F64, X64, X64p
+        torch.cuda.empty_cache()
+        log(f"[bench] fp64 run {rep}: fp64+IR {t64:.3f}s plain fp64 {t64p:.3f}s; {left():.0f} s left")
     value = med(t32)
     roof, phases = roofline(s32, "f32")
     roof["traffic"] = measured_traffic(args.workload, roof["phase"])
-    _, phases64 = roofline(s64, "f64")
     out = {
         "metric": METRIC,
         "value": value,
         "unit": "s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": len(t32),
+        "warmup": warm,
         "ms_per_step": value * 1e3,
         "higher_is_better": False,
         "scaling": "weak",
@@ -357,29 +478,49 @@ def main():
             "workload": args.workload,
             "N": spec["N"], "dim": spec["dim"], "kernel": list(spec["kernel"]), "tree": spec["tree"],
             "leaf": spec["leaf"], "tol": tol, "nrhs": spec["nrhs"], "eta": spec["eta"],
+            "p0": spec["p0"],
         },
+        "steps_requested": args.steps,
+        "warmup_requested": args.warmup,
+        "setup_s": {"construct": t_construct, "load_upload": t_load, "blob_gb": blob_gb},
         "fp32_ir": {"factor_s": med(tf32), "total_s": value, "bkwd": eb32, "ir": rep32,
                     "factor_gflops": s32["factor_flops"] / med(tf32) / 1e9,
                     "phase_ms": dict(zip(h2.PHASES, s32["time_ms"])),
-                    "peak_bytes": s32["peak_bytes"]},
-        "fp64_ir": {"factor_s": med(tf64), "total_s": med(t64), "bkwd": eb64, "ir": rep64,
-                    "phase_ms": dict(zip(h2.PHASES, s64["time_ms"])),
-                    "peak_bytes": s64["peak_bytes"]},
-        "fp64_plain": {"total_s": med(t64p), "bkwd": eb64p},
+                    "peak_bytes": s32["peak_bytes"], "matrix_bytes": H.device_bytes},
         "n_top": s32["n_top"],
         "roofline": roof,
         "phases_fp32": phases,
-        "phases_fp64": phases64,
     }
-    if not args.no_batched:
-        del X32, X64, X64p, F32, F64, H
+    if s64 is not None:
+        _, phases64 = roofline(s64, "f64")
+        out["fp64_ir"] = {"factor_s": tf64, "total_s": t64, "bkwd": eb64, "ir": fp64["ir"],
+                          "runs": reps64, "phase_ms": dict(zip(h2.PHASES, s64["time_ms"])),
+                          "peak_bytes": s64["peak_bytes"]}
+        out["fp64_plain"] = {"total_s": t64p, "bkwd": eb64p}
+        out["phases_fp64"] = phases64
+    else:
+        out["fp64_ir"] = {"skipped": "time budget"}
+    if args.batched or (not args.no_batched and left() > args.batched_s):
+        del H, B
         torch.cuda.empty_cache()
         out["batched"] = batched_bench(args, h2, ctx)
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle sample)")
-        cb = cpu_baseline(args.workload)
-        out["cpu_baseline"] = cb
+    else:
+        out["batched"] = {"skipped": f"time budget ({left():.0f} s left, the batched leg needs "
+                                     f"about {args.batched_s:.0f} s)"}
+    cb = finish_cpu_baseline(cpu_proc, min(left(), 120.0))
+    if cb is not None:
+        best = cb.get("all_cores") if cb.get("all_cores", {}).get("value", 1e300) < \
+            cb["one_core"]["value"] else cb["one_core"]
+        out["cpu_baseline"] = dict(best)
+        out["cpu_baseline"]["one_core_value"] = cb["one_core"]["value"]
+        if "all_cores" in cb:
+            out["cpu_baseline"]["all_cores_value"] = cb["all_cores"]["value"]
+        out["cpu_baseline"]["host"] = cb.get("host")
     print(json.dumps(out), flush=True)
+
+
+def value_or(v, d):
+    return d if v is None else v
 
 
 if __name__ == "__main__":

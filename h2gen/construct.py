@@ -266,9 +266,10 @@ def construct(pts, kernel, leaf_size=64, tree_kind="kd", eta=0.7, adm_kind=0,
                 slot = np.arange(starts[n0], starts[n1]) - starts[ii]
                 idx_n = torch.as_tensor(ii - n0, device=dev)
                 idx_r = torch.as_tensor(slot, device=dev)
-                tmp = blocks[:, :int(cnt.max()) * k1].reshape(n1 - n0, -1, k1, k1)
+                # a view of the stacked blocks (slot, k1 x k1): the indexed
+                # assignment writes through to `blocks`
+                tmp = blocks[:, :int(cnt.max()) * k1].view(n1 - n0, int(cnt.max()), k1, k1)
                 tmp[idx_n, idx_r] = Sp.transpose(1, 2)
-                blocks[:, :int(cnt.max()) * k1] = tmp.reshape(n1 - n0, -1, k1)
             if l > top:
                 par = torch.as_tensor(t.parent[lp[l] + np.arange(n0, n1)] - lp[l - 1], device=dev).long()
                 EW = torch.bmm(Lv.E1[n0:n1], lev[l - 1].W[par])  # (nb, k1, kp)

@@ -147,7 +147,12 @@ typedef struct {
   int32_t keep_owner_lists; /* nonzero: keep every colour's Schur target lists for
                                h2_factor_export_ints(H2_INT_OWNERS) (host memory grows
                                with the number of targets) */
-  int32_t pad0;
+  int32_t lds_limit_kib;    /* > 0: on-chip (LDS) bytes per workgroup, in KiB, that the
+                               kernels of the fill-row QR, the augmentation, the LU of
+                               D_RR and the multipliers may assume, if below the default
+                               150; working sets beyond it take the global-memory
+                               variants of those kernels (same results up to rounding
+                               order).  For exercising those variants at small orders. */
 } h2_factor_opts;
 
 /*

@@ -75,7 +75,7 @@ class _CtxOpts(ctypes.Structure):
 
 class _FactorOpts(ctypes.Structure):
     _fields_ = [("norm2", ctypes.c_double), ("pool_bytes", ctypes.c_int64),
-                ("keep_owner_lists", ctypes.c_int32), ("pad0", ctypes.c_int32)]
+                ("keep_owner_lists", ctypes.c_int32), ("lds_limit_kib", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -238,8 +238,9 @@ class Matrix:
             pass
 
 
-def _factor_opts(norm2=None, pool_bytes=None, keep_owner_lists=False):
-    return _FactorOpts(float(norm2 or 0.0), int(pool_bytes or 0), int(bool(keep_owner_lists)), 0)
+def _factor_opts(norm2=None, pool_bytes=None, keep_owner_lists=False, lds_limit_kib=0):
+    return _FactorOpts(float(norm2 or 0.0), int(pool_bytes or 0), int(bool(keep_owner_lists)),
+                       int(lds_limit_kib))
 
 
 class Factor:

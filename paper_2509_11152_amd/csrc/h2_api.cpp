@@ -450,7 +450,8 @@ h2_status h2_factor_batched(h2_context_t ctx, int count, const h2_matrix_t* Hs, 
     return H2_ERROR_INVALID_ARGUMENT;
   h2_factor_opts o{};
   if (opts) o = *opts;
-  if (std::isnan(o.norm2) || !std::isfinite(o.norm2) || o.norm2 < 0 || o.pool_bytes < 0)
+  if (std::isnan(o.norm2) || !std::isfinite(o.norm2) || o.norm2 < 0 || o.pool_bytes < 0 ||
+      o.lds_limit_kib < 0)
     return H2_ERROR_INVALID_ARGUMENT;
   for (int i = 0; i < count; ++i) {
     if (!Hs[i] || Hs[i]->ctx != ctx) return H2_ERROR_INVALID_ARGUMENT;

@@ -355,8 +355,8 @@ static std::vector<std::pair<int, int>> rf_groups(const std::vector<int>& rows, 
 // blocks have the given widths: one n x n factor per task of every stage
 // (groups of blocks, then pairs of factors), plus the global-memory
 // reduction space when R does not fit in LDS.
-template <class T> static int64_t rf_scratch(int n, const std::vector<int>& rows) {
-  const int64_t per = (int64_t)n * n + (rf_in_lds<T>(n) ? 0 : (int64_t)(n + kAugChunk) * n);
+template <class T> static int64_t rf_scratch(int n, const std::vector<int>& rows, int lds) {
+  const int64_t per = (int64_t)n * n + (rf_in_lds<T>(n, lds) ? 0 : (int64_t)(n + kAugChunk) * n);
   int64_t g = (int64_t)rf_groups(rows, rf_group_rows(n)).size();
   int64_t tot = g * per;
   for (; g > 1; g = (g + 1) / 2) tot += (g / 2) * per;
@@ -392,7 +392,7 @@ constexpr int kPlanAhead = 8;
 
 template <class T>
 static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double tol,
-                       DevTracker* calltr) {
+                       DevTracker* calltr, int lds) {
   hipStream_t s = ctx->stream;
   // FP32 with the Gram augmentation (Section 2.1, first option): the fill row
   // enters the augmentation as its FP64 Gram matrix; otherwise the QR route
@@ -503,7 +503,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
             w += 2 * aug_work_elems(P.n[i]);  // FP64 arithmetic in FP32 units
             gw += (int64_t)P.n[i] * P.n[i];
           } else {
-            w += aug_work_elems(P.n[i]) + rf_scratch<T>(P.n[i], rows);
+            w += aug_work_elems(P.n[i]) + rf_scratch<T>(P.n[i], rows, lds);
           }
         }
       }
@@ -593,7 +593,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           }
           // stages of the tall-skinny QR: groups of fill blocks, then groups of
           // the previous stage's factors, until one factor remains
-          const bool rf_glob = !rf_in_lds<T>(ni);
+          const bool rf_glob = !rf_in_lds<T>(ni, lds);
           for (size_t st = 0; !gram_mode; ++st) {
             // stage 0: groups of fill blocks; later stages: pairs of factors
             // (an odd one passes to the next stage as it is)
@@ -874,11 +874,11 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         auto m0 = mark(0);
         for (size_t st = 0; st < rst.size(); ++st)
           launch_rfactor<T>(ar.put(rst[st]), (int)rst[st].size(), ar.put(rrefs[st]), rdev.p,
-                            rmaxn[st], s);
+                            rmaxn[st], s, lds);
         close_mark(m0);
       }
       auto m1 = mark(1);
-      launch_augment<T>(ar.put(aug), (int)aug.size(), rdev.p, ctx->d_err.p, maxn_aug, gram, s);
+      launch_augment<T>(ar.put(aug), (int)aug.size(), rdev.p, ctx->d_err.p, maxn_aug, gram, s, lds);
       close_mark(m1);
       launches[0] += gram ? 1 : (int64_t)rst.size();
       launches[1] += 1;
@@ -900,7 +900,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         for (auto& t : lus) maxr = std::max(maxr, (int)t.lda);
         const LUTask<T>* dl = ar.put(lus);
         auto m3 = mark(3);
-        launch_lu<T>(dl, (int)lus.size(), dyn, ctx->d_err.p, maxr, s);
+        launch_lu<T>(dl, (int)lus.size(), dyn, ctx->d_err.p, maxr, s, lds);
         close_mark(m3);
       }
       {
@@ -911,7 +911,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         }
         const TrsmTask<T>* dt = ar.put(trs);
         auto m4 = mark(4);
-        launch_trsm<T>(dt, (int)trs.size(), dyn, maxr, maxcols, s);
+        launch_trsm<T>(dt, (int)trs.size(), dyn, maxr, maxcols, s, lds);
         close_mark(m4);
       }
       {
@@ -1312,6 +1312,8 @@ std::vector<h2_factor_s*> factor(h2_context_s* ctx, const std::vector<h2_matrix_
                           hipMemcpyDeviceToDevice, ctx->stream));
   }
   auto norm_of = [&](const h2_matrix_s* H) { return opts.norm2 > 0 ? opts.norm2 : H->norm2; };
+  // LDS bytes per workgroup the kernels' path choices assume
+  const int lds = opts.lds_limit_kib > 0 ? std::min(kLdsBytes, opts.lds_limit_kib * 1024) : kLdsBytes;
   if (prec == H2_PREC_FP64) {
     std::vector<Inst<double>> insts(Hs.size());
     for (size_t i = 0; i < Hs.size(); ++i) {
@@ -1320,7 +1322,7 @@ std::vector<h2_factor_s*> factor(h2_context_s* ctx, const std::vector<h2_matrix_
       insts[i].data = Hs[i]->data.p;
       insts[i].norm = norm_of(Hs[i]);
     }
-    run_factor<double>(ctx, insts, tol, &calltr);
+    run_factor<double>(ctx, insts, tol, &calltr, lds);
   } else {
     std::vector<Inst<float>> insts(Hs.size());
     for (size_t i = 0; i < Hs.size(); ++i) {
@@ -1331,7 +1333,7 @@ std::vector<h2_factor_s*> factor(h2_context_s* ctx, const std::vector<h2_matrix_
       insts[i].data = insts[i].data_conv.p;
       insts[i].norm = norm_of(Hs[i]);
     }
-    run_factor<float>(ctx, insts, tol, &calltr);
+    run_factor<float>(ctx, insts, tol, &calltr, lds);
   }
   H2_HIP(hipStreamSynchronize(ctx->stream));
   for (auto& p : own) {

@@ -155,8 +155,10 @@ template <class T> __host__ __device__ inline int64_t rf_lds_elems(int n) {
   return (int64_t)n * (n + 1) / 2 + 2 * (int64_t)rf_xstride<T>();
 }
 // whether the fill-row reduction of order n runs in LDS (else in `work`)
-template <class T> __host__ __device__ inline bool rf_in_lds(int n) {
-  return n <= 256 && rf_lds_elems<T>(n) <= kLdsBytes / (int64_t)sizeof(T);
+// with `lds` bytes of LDS per workgroup (kLdsBytes unless a factorization
+// asks for less)
+template <class T> __host__ __device__ inline bool rf_in_lds(int n, int lds = kLdsBytes) {
+  return n <= 256 && rf_lds_elems<T>(n) <= lds / (int64_t)sizeof(T);
 }
 // largest cluster order the augmentation supports (lanes x registers of a
 // Jacobi pair)
@@ -185,22 +187,25 @@ void launch_gemm_reduce(const GOut<T>* routs, int nouts, const T* parts, int64_t
 template <class T>
 void launch_strip(const STask<T>* tasks, int ntasks, const int32_t* dyn, int64_t nstrips,
                   int maxn, hipStream_t s);
+// `lds`: LDS bytes per workgroup the path choices of the fill-row QR, the
+// augmentation, the LU and the multipliers may assume (at most kLdsBytes);
+// working sets beyond it take the global-memory variants
 template <class T>
 void launch_rfactor(const RTask<T>* tasks, int ntasks, const FillRef<T>* refs,
-                    const int32_t* dyn, int maxn, hipStream_t s);
+                    const int32_t* dyn, int maxn, hipStream_t s, int lds = kLdsBytes);
 template <class T>
 void launch_gram(const GramTask<T>* tasks, int ntasks, const FillRef<T>* refs,
                  const int32_t* dyn, int64_t ntiles, hipStream_t s);
 // gram: the tasks carry G (FP32 storage only), arithmetic in FP64
 template <class T>
 void launch_augment(const AugTask<T>* tasks, int ntasks, int32_t* r, int* err, int maxn, bool gram,
-                    hipStream_t s);
+                    hipStream_t s, int lds = kLdsBytes);
 template <class T>
 void launch_lu(const LUTask<T>* tasks, int ntasks, const int32_t* dyn, int* err, int maxr,
-               hipStream_t s);
+               hipStream_t s, int lds = kLdsBytes);
 template <class T>
 void launch_trsm(const TrsmTask<T>* tasks, int ntasks, const int32_t* dyn, int maxr, int maxcols,
-                 hipStream_t s);
+                 hipStream_t s, int lds = kLdsBytes);
 template <class T, class S>
 void launch_copy(const CTask<T, S>* tasks, int ntasks, int64_t ntiles, hipStream_t s);
 template <class T>

@@ -611,7 +611,7 @@ template <> __device__ inline double lane_value<double>(double v, int l) {
 template <class T>
 __global__ __launch_bounds__(256) void k_rfactor(const RTask<T>* __restrict__ tasks,
                                                  const FillRef<T>* __restrict__ refs,
-                                                 const int32_t* __restrict__ dyn) {
+                                                 const int32_t* __restrict__ dyn, int lds) {
   extern __shared__ char rf_smem[];
   const RTask<T> tk = tasks[blockIdx.x];
   const int n = tk.n;
@@ -621,7 +621,7 @@ __global__ __launch_bounds__(256) void k_rfactor(const RTask<T>* __restrict__ ta
   // same test as the host's (which gives `work` to the others); the launch
   // provides LDS for every in-LDS order of the launch and 64 threads per 64
   // columns
-  if (rf_in_lds<T>(n)) {
+  if (rf_in_lds<T>(n, lds)) {
     constexpr int RPT = rf_chunk<T>();
     const int col = tid, lane = tid & 63;
     const bool one_wave = nthr == 64;
@@ -766,14 +766,15 @@ __global__ __launch_bounds__(256) void k_rfactor(const RTask<T>* __restrict__ ta
 
 template <class T>
 void launch_rfactor(const RTask<T>* tasks, int ntasks, const FillRef<T>* refs,
-                    const int32_t* dyn, int maxn, hipStream_t s) {
+                    const int32_t* dyn, int maxn, hipStream_t s, int lds) {
   if (ntasks <= 0) return;
+  lds = std::min(lds, kLdsBytes);
   // every order of the launch fits in LDS: 64 threads per 64 columns of the
   // largest and its LDS; otherwise 256 threads (enough for every in-LDS
   // order) and the full LDS allowance
-  const bool lds = rf_in_lds<T>(maxn);
-  const int threads = lds ? 64 * ((maxn + 63) / 64) : 256;
-  const int64_t need = lds ? rf_lds_elems<T>(maxn) : kLdsBytes / (int64_t)sizeof(T);
+  const bool in_lds = rf_in_lds<T>(maxn, lds);
+  const int threads = in_lds ? 64 * ((maxn + 63) / 64) : 256;
+  const int64_t need = in_lds ? rf_lds_elems<T>(maxn) : lds / (int64_t)sizeof(T);
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)k_rfactor<T>,
@@ -781,7 +782,7 @@ void launch_rfactor(const RTask<T>* tasks, int ntasks, const FillRef<T>* refs,
     attr_set = true;
   }
   hipLaunchKernelGGL(k_rfactor<T>, dim3(ntasks), dim3(threads), (size_t)(need * sizeof(T)), s,
-                     tasks, refs, dyn);
+                     tasks, refs, dyn, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1152,9 +1153,9 @@ __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__
 
 template <class T, class A, bool GRAM>
 static void launch_augment_t(const AugTask<T>* tasks, int ntasks, int32_t* r, int* err, int maxn,
-                             hipStream_t s) {
+                             hipStream_t s, int lds) {
   // LDS: the reflectors of V and V_perp (n^2), then M' and W' (at most 2 n^2)
-  const int64_t cap = kLdsBytes / (int64_t)sizeof(A);
+  const int64_t cap = std::min(lds, kLdsBytes) / (int64_t)sizeof(A);
   const int64_t need = std::min<int64_t>(cap, 2 * (int64_t)maxn * maxn + 8);
   static bool attr_set = false;
   if (!attr_set) {
@@ -1168,15 +1169,15 @@ static void launch_augment_t(const AugTask<T>* tasks, int ntasks, int32_t* r, in
 
 template <class T>
 void launch_augment(const AugTask<T>* tasks, int ntasks, int32_t* r, int* err, int maxn, bool gram,
-                    hipStream_t s) {
+                    hipStream_t s, int lds) {
   if (ntasks <= 0) return;
   if constexpr (sizeof(T) == 4) {
     if (gram) {
-      launch_augment_t<T, double, true>(tasks, ntasks, r, err, maxn, s);
+      launch_augment_t<T, double, true>(tasks, ntasks, r, err, maxn, s, lds);
       return;
     }
   }
-  launch_augment_t<T, T, false>(tasks, ntasks, r, err, maxn, s);
+  launch_augment_t<T, T, false>(tasks, ntasks, r, err, maxn, s, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1308,10 +1309,10 @@ __global__ __launch_bounds__(256) void k_lu(const LUTask<T>* __restrict__ tasks,
 
 template <class T>
 void launch_lu(const LUTask<T>* tasks, int ntasks, const int32_t* dyn, int* err, int maxr,
-               hipStream_t s) {
+               hipStream_t s, int lds) {
   if (ntasks <= 0) return;
   // blocks of order <= maxr factor in LDS when maxr^2 fits, else in place
-  const int64_t cap = kLdsBytes / (int64_t)sizeof(T);
+  const int64_t cap = std::min(lds, kLdsBytes) / (int64_t)sizeof(T);
   const int64_t need = (int64_t)maxr * maxr <= cap ? (int64_t)maxr * maxr : 0;
   static bool attr_set = false;
   if (!attr_set) {
@@ -1473,10 +1474,11 @@ __global__ __launch_bounds__(256) void k_trsm_wave(const TrsmTask<T>* __restrict
 
 template <class T>
 void launch_trsm(const TrsmTask<T>* tasks, int ntasks, const int32_t* dyn, int maxr, int maxcols,
-                 hipStream_t s) {
+                 hipStream_t s, int lds) {
   if (ntasks <= 0 || maxr <= 0 || maxcols <= 0) return;
+  lds = std::min(lds, kLdsBytes);
   const size_t wlds = (size_t)maxr * maxr * sizeof(T) + 2 * (size_t)maxr * sizeof(int);
-  if (maxcols <= 16 && maxr <= 256 && wlds <= (size_t)kLdsBytes) {
+  if (maxcols <= 16 && maxr <= 256 && wlds <= (size_t)lds) {
     static bool wattr = false;
     if (!wattr) {
       (void)hipFuncSetAttribute((const void*)k_trsm_wave<T>,
@@ -1487,9 +1489,10 @@ void launch_trsm(const TrsmTask<T>* tasks, int ntasks, const int32_t* dyn, int m
     return;
   }
   int tc = 32;
-  while (tc > 1 && (int64_t)maxr * tc * (int64_t)sizeof(T) > 96 * 1024) tc >>= 1;
+  const int64_t tile_cap = std::min(96 * 1024, lds);
+  while (tc > 1 && (int64_t)maxr * tc * (int64_t)sizeof(T) > tile_cap) tc >>= 1;
   tc = std::min(tc, maxcols);
-  const size_t lds = (size_t)maxr * tc * sizeof(T) + 2 * (size_t)maxr * sizeof(int);
+  const size_t tlds = (size_t)maxr * tc * sizeof(T) + 2 * (size_t)maxr * sizeof(int);
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)k_trsm<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1497,7 +1500,7 @@ void launch_trsm(const TrsmTask<T>* tasks, int ntasks, const int32_t* dyn, int m
     attr_set = true;
   }
   const int tiles = (maxcols + tc - 1) / tc;
-  hipLaunchKernelGGL(k_trsm<T>, dim3(ntasks, tiles), dim3(256), lds, s, tasks, dyn, tc);
+  hipLaunchKernelGGL(k_trsm<T>, dim3(ntasks, tiles), dim3(256), tlds, s, tasks, dyn, tc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1859,13 +1862,15 @@ void launch_check_finite(const double* X, int64_t n, int* flag, hipStream_t s) {
   template void launch_strip<T>(const STask<T>*, int, const int32_t*, int64_t, int,           \
                                 hipStream_t);                                                 \
   template void launch_rfactor<T>(const RTask<T>*, int, const FillRef<T>*, const int32_t*, int, \
-                                  hipStream_t);                                               \
+                                  hipStream_t, int);                                          \
   template void launch_gram<T>(const GramTask<T>*, int, const FillRef<T>*, const int32_t*,    \
                                int64_t, hipStream_t);                                         \
   template void launch_augment<T>(const AugTask<T>*, int, int32_t*, int*, int, bool,          \
-                                  hipStream_t);                                               \
-  template void launch_lu<T>(const LUTask<T>*, int, const int32_t*, int*, int, hipStream_t);  \
-  template void launch_trsm<T>(const TrsmTask<T>*, int, const int32_t*, int, int, hipStream_t); \
+                                  hipStream_t, int);                                          \
+  template void launch_lu<T>(const LUTask<T>*, int, const int32_t*, int*, int, hipStream_t,   \
+                             int);                                                            \
+  template void launch_trsm<T>(const TrsmTask<T>*, int, const int32_t*, int, int, hipStream_t, \
+                               int);                                                          \
   template void launch_copy<T, double>(const CTask<T, double>*, int, int64_t, hipStream_t);   \
   template void launch_copy<T, float>(const CTask<T, float>*, int, int64_t, hipStream_t);     \
   template void launch_fill<T>(T*, int64_t, T, hipStream_t);                                  \

@@ -48,6 +48,9 @@ def test_invalid_tolerance(lib, ctx):
         with pytest.raises(lib.H2Error) as e:
             lib.Factor(ctx, H, tol)
         assert e.value.code == H2_ERROR_INVALID_ARGUMENT
+    with pytest.raises(lib.H2Error) as e:
+        lib.Factor(ctx, H, 1e-8, lds_limit_kib=-1)
+    assert e.value.code == H2_ERROR_INVALID_ARGUMENT
 
 
 def test_memory_cap(lib, ctx):
