@@ -137,6 +137,23 @@ h2_status h2_matrix_get_info(h2_matrix_t H, h2_matrix_info* info);
 h2_status h2_matvec(h2_context_t ctx, h2_matrix_t H, const double* X, int64_t ldx, int nrhs,
                     double* Y, int64_t ldy);
 
+/*
+ * The product of h2_matvec for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels, with every work array (tree-ordered vectors,
+ * basis coefficients, launch descriptors, partial tiles) in a library-owned
+ * static device array of 64 MiB per device instead of allocated memory.  It
+ * calls no device allocator.  Needs about 8 (2 N + 2 K) nrhs bytes for the
+ * vectors (K = sum of the cluster ranks) plus the descriptors, about
+ * 50 bytes per near and far block; larger problems fail with
+ * H2_ERROR_UNSUPPORTED and a message giving the size.  Every call on one
+ * device shares that device's array: calls that overlap in time on one GPU
+ * (from any context or thread) race and give wrong results.  Synchronizes
+ * with the context's stream before returning.  X and Y as for h2_matvec.
+ */
+h2_status h2_matvec_noalloc(h2_context_t ctx, h2_matrix_t H, const double* X, int64_t ldx,
+                            int nrhs, double* Y, int64_t ldy);
+
 /* Options of a factorization call (NULL = all defaults). */
 typedef struct {
   double norm2;       /* > 0: ||A||_2 used in eps_fill = tol ||A||_2 in place of

@@ -98,6 +98,7 @@ _SIG = {
     "h2_matrix_destroy": (ctypes.c_int, [_P]),
     "h2_matrix_get_info": (ctypes.c_int, [_P, ctypes.POINTER(_Info)]),
     "h2_matvec": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, _P, _I64]),
+    "h2_matvec_noalloc": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, _P, _I64]),
     "h2_factor": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int,
                                  ctypes.POINTER(_FactorOpts), ctypes.POINTER(_P)]),
     "h2_factor_destroy": (ctypes.c_int, [_P]),
@@ -227,6 +228,18 @@ class Matrix:
         _check(lib.h2_matvec(self.ctx.ptr, self.ptr, _P(Xc.data_ptr()), self.n, nrhs,
                              _P(Y.data_ptr()), self.n), self.ctx)
         self.ctx.sync()
+        return Y.t()
+
+    def matvec_noalloc(self, X):
+        """The product through h2_matvec_noalloc (work arrays in the library's
+        static device scratch; the output tensor is the caller's)."""
+        import torch
+
+        Xc = _colmajor(X)
+        nrhs = Xc.shape[0]
+        Y = torch.empty_like(Xc)
+        _check(lib.h2_matvec_noalloc(self.ctx.ptr, self.ptr, _P(Xc.data_ptr()), self.n, nrhs,
+                                     _P(Y.data_ptr()), self.n), self.ctx)
         return Y.t()
 
     def __del__(self):

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <atomic>
+#include <mutex>
 #include <thread>
 
 #include "h2_driver.h"
@@ -29,6 +30,41 @@ template <class F> h2_status guard(h2_context_s* ctx, F&& f) {
 }
 
 void fail_format(const std::string& m) { throw H2Error(H2_ERROR_FORMAT, m); }
+
+// ---- scratch of the allocation-free product (h2_matvec_noalloc) ----
+// A file-scope device array: every GPU the library runs on holds its own copy
+// until the process ends.  Host code never passes the array's name to a kernel
+// or a copy (on the host it is only a stand-in for the symbol); its device
+// address on each device is looked up once, at the first context created on
+// that device, and kept in g_scratch.
+constexpr int64_t kNoAllocScratchBytes = (int64_t)64 << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxScratchDevices] = {};
+hipError_t g_scratch_err[kMaxScratchDevices] = {};
+
+// with `dev` current: look up this device's copy of the array (once)
+void map_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxScratchDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[dev]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  g_scratch_err[dev] = e;
+  if (e == hipSuccess) g_scratch[dev] = p;
+}
+
+void* scratch_of(int dev) {
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    throw H2Error(H2_ERROR_UNSUPPORTED, "no allocation-free scratch for device " +
+                                            std::to_string(dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev])
+    throw H2Error(H2_ERROR_HIP, std::string("hipGetSymbolAddress of the scratch array: ") +
+                                    hipGetErrorString(g_scratch_err[dev]));
+  return g_scratch[dev];
+}
 
 struct Reader {
   const uint8_t* p;
@@ -316,6 +352,7 @@ h2_status h2_context_create(const h2_context_opts* opts, h2_context_t* out) {
     ctx->d_err.alloc(1, &ctx->tr);
     h2k::launch_fill<int32_t>(ctx->d_err.p, 1, 0, ctx->stream);
     H2_HIP(hipStreamSynchronize(ctx->stream));
+    map_scratch(o.device);
   });
   if (st != H2_SUCCESS) {
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -434,6 +471,19 @@ h2_status h2_matvec(h2_context_t ctx, h2_matrix_t H, const double* X, int64_t ld
   return guard(ctx, [&] {
     H2_HIP(hipSetDevice(ctx->device));
     h2drv::matvec(ctx, H, X, ldx, nrhs, Y, ldy);
+  });
+}
+
+h2_status h2_matvec_noalloc(h2_context_t ctx, h2_matrix_t H, const double* X, int64_t ldx,
+                            int nrhs, double* Y, int64_t ldy) {
+  if (!ctx || !H || !X || !Y || nrhs < 0 || ldx < H->N || ldy < H->N)
+    return H2_ERROR_INVALID_ARGUMENT;
+  if ((const void*)X == (const void*)Y) return H2_ERROR_INVALID_ARGUMENT;
+  if (nrhs == 0) return H2_SUCCESS;
+  return guard(ctx, [&] {
+    H2_HIP(hipSetDevice(ctx->device));
+    h2drv::matvec_in(ctx, H, X, ldx, nrhs, Y, ldy, (char*)scratch_of(ctx->device),
+                     kNoAllocScratchBytes);
   });
 }
 
