@@ -14,14 +14,23 @@ Steps (textbook H^2 recompression, Boerm):
   2. orthogonalisation upsweep: QR of the leaf bases and of the stacked
      R_c E_c; couplings become R_s S R_t^T;
   3. total-weight downsweep: W_t = R-factor (transposed) of
-     [S_ts for s in far(t), E_t W_parent];
+     [S_ts^T for s in far(t); (E_t W_parent)^T];
   4. truncation upsweep: SVD of W_t (leaves) or of [T_c E_c] W_t (inner
      nodes), keeping singular values > eps * ||A||; couplings T_s S T_t^T.
+When eps >= 1e-7 the weights are kept as Gram matrices instead:
+W_t W_t^T = sum over far s of S_ts S_ts^T + E_t (W_p W_p^T) E_t^T, and the
+truncation takes the eigendecomposition of W_t W_t^T or Z W_t W_t^T Z^T
+(Z = [T_c E_c]), whose eigenvectors and square-rooted eigenvalues are the
+left singular vectors and values; this form resolves singular values down to
+about 1e-8 of the largest, so it serves the coarser tolerances only, and it
+avoids the tall QR factorizations that dominate the construction time.
 Cluster bases above the first level with admissible blocks have rank 0.
 
-All arithmetic is float64 torch on the requested device, batched per level
-over zero-padded shapes; far-field kernel blocks are generated in chunks and
-never stored uncompressed.
+Arithmetic is float64: kernel evaluations and products in torch on the
+requested device, batched per level over zero-padded shapes; the small dense
+QR factorizations and eigendecompositions in LAPACK on the host, spread over
+its cores.  Far-field kernel blocks are generated in chunks and never stored
+uncompressed.
 """
 import numpy as np
 import torch
@@ -84,9 +93,28 @@ def _lagrange_nd(nodes1d, digits, X):
     return out
 
 
+def _host_batched(fn, A, nout):
+    """fn (a numpy LAPACK routine on stacked matrices) applied to the device
+    batch A on the host: chunks of the batch on a pool of threads, each with a
+    single-threaded BLAS (every matrix is factored on its own, so the result
+    does not depend on the chunking); outputs return to A's device."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    from threadpoolctl import threadpool_limits
+
+    a = A.detach().cpu().numpy()
+    nthr = max(1, min(os.cpu_count() or 1, 32))
+    parts = np.array_split(a, min(len(a), 4 * nthr)) if len(a) else [a]
+    with threadpool_limits(1, user_api="blas"), ThreadPoolExecutor(nthr) as ex:
+        res = list(ex.map(fn, parts))
+    outs = [np.concatenate([r[i] for r in res]) for i in range(nout)]
+    return tuple(torch.as_tensor(o, device=A.device) for o in outs)
+
+
 def _bqr(A, mode, chunk=512):
-    """Batched QR in slices of at most `chunk` matrices (large device batches
-    exhaust the solver's workspace)."""
+    """Batched QR on the device in slices of at most `chunk` matrices (large
+    batches exhaust the solver's workspace)."""
     if A.shape[0] <= chunk:
         return torch.linalg.qr(A, mode=mode)
     parts = [torch.linalg.qr(A[i:i + chunk], mode=mode) for i in range(0, A.shape[0], chunk)]
@@ -195,7 +223,7 @@ def construct(pts, kernel, leaf_size=64, tree_kind="kd", eta=0.7, adm_kind=0,
         Lv.k1 = mmax
     else:
         U0 = _lagrange_nd(Lv.nodes1d, Lv.digits, leafpts) * leafmask.unsqueeze(-1)
-        Q, R = _bqr(U0, "reduced")
+        Q, R = _host_batched(np.linalg.qr, U0, 2)
         Lv.Uq, Lv.R = Q, R
         Lv.k1 = R.shape[1]
     for l in range(L - 1, top - 1, -1):
@@ -207,7 +235,7 @@ def construct(pts, kernel, leaf_size=64, tree_kind="kd", eta=0.7, adm_kind=0,
         E0 = _lagrange_nd(Lv.nodes1d[par], Lv.digits, Lc.xi) * Lc.mask.unsqueeze(-1)
         RE = torch.bmm(Lc.R, E0)  # (nchild, kc1, kp0)
         Z = RE.reshape(Lv.n, arity * Lc.k1, Lv.k0)
-        Q, R = _bqr(Z, "reduced")
+        Q, R = _host_batched(np.linalg.qr, Z, 2)
         Lv.k1 = R.shape[1]
         Lv.R = R
         Lc.E1 = Q.reshape(Lv.n * arity, Lc.k1, Lv.k1)  # orthonormal stacked transfers
@@ -238,69 +266,128 @@ def construct(pts, kernel, leaf_size=64, tree_kind="kd", eta=0.7, adm_kind=0,
     thr = eps * norm_pre
 
     say("orthogonalisation done")
+    # The weights in Gram form resolve singular values down to about
+    # sqrt(unit roundoff) of the largest: used when the truncation threshold
+    # eps stays above that with margin (eps >= 1e-7, eps^2 about 45 unit
+    # roundoffs; the slack absorbs the rounding of tol / 10); otherwise the R
+    # factors of the stacked rows are formed (QR).
+    gram = eps >= 1e-7 * (1.0 - 1e-9)
     # ---- step 3: total-weight downsweep ----
     for l in range(top, L + 1):
-        say(f"weights, level {l}")
+        say(f"weights, level {l} ({'Gram' if gram else 'QR'})")
         Lv = lev[l]
         e, fi, fj = far_of_level(l)
         k1 = Lv.k1
-        # stacked rows per node: S'_ts^T blocks (k1 each) and the parent part
         cnt = np.bincount(fi, minlength=Lv.n)
-        W = torch.zeros(Lv.n, k1, k1, dtype=torch.float64, device=dev)
-        # process nodes in chunks to bound memory: gather all S' for the chunk
-        kp = lev[l - 1].W.shape[2] if l > top else 0
-        maxrows = int(cnt.max()) * k1 + kp
-        node_chunk = max(1, int(2e8 // max(1, maxrows * k1)))
+        cmax = max(int(cnt.max()), 1)
         order = np.argsort(fi, kind="stable")
         starts = np.concatenate([[0], np.cumsum(cnt)])
+        if gram:
+            # Gamma_t = W_t W_t^T = sum over far pairs (t, s) of S'_ts S'_ts^T
+            # plus E1_t Gamma_parent E1_t^T
+            Gm = torch.zeros(Lv.n, k1, k1, dtype=torch.float64, device=dev)
+            node_chunk = max(1, int(2e8 // max(1, cmax * k1 * k1)))
+        else:
+            W = torch.zeros(Lv.n, k1, k1, dtype=torch.float64, device=dev)
+            kp = lev[l - 1].W.shape[2] if l > top else 0
+            maxrows = int(cnt.max()) * k1 + kp
+            node_chunk = max(1, int(2e8 // max(1, maxrows * k1)))
         for n0 in range(0, Lv.n, node_chunk):
             n1 = min(Lv.n, n0 + node_chunk)
-            blocks = torch.zeros(n1 - n0, maxrows, k1, dtype=torch.float64, device=dev)
             sl = order[starts[n0]:starts[n1]]
-            if len(sl):
-                ii, jj = fi[sl], fj[sl]
-                Ri = Lv.R[ii]
-                Rj = Lv.R[jj]
-                Sp = coupling(l, ii, jj, Ri, Rj)  # (npairs, k1, k1)
-                # pair number within its row -> block slot of the stacked G^T
-                slot = np.arange(starts[n0], starts[n1]) - starts[ii]
-                idx_n = torch.as_tensor(ii - n0, device=dev)
-                idx_r = torch.as_tensor(slot, device=dev)
-                # a view of the stacked blocks (slot, k1 x k1): the indexed
-                # assignment writes through to `blocks`
-                tmp = blocks[:, :int(cnt.max()) * k1].view(n1 - n0, int(cnt.max()), k1, k1)
-                tmp[idx_n, idx_r] = Sp.transpose(1, 2)
-            if l > top:
-                par = torch.as_tensor(t.parent[lp[l] + np.arange(n0, n1)] - lp[l - 1], device=dev).long()
-                EW = torch.bmm(Lv.E1[n0:n1], lev[l - 1].W[par])  # (nb, k1, kp)
-                blocks[:, maxrows - kp:maxrows, :] = EW.transpose(1, 2)
-            R = _qr_r(blocks)
-            W[n0:n1] = R.transpose(1, 2)
-        Lv.W = W
+            if gram:
+                if len(sl):
+                    ii, jj = fi[sl], fj[sl]
+                    Sp = coupling(l, ii, jj, Lv.R[ii], Lv.R[jj])  # (npairs, k1, k1)
+                    # the node's blocks side by side, in CSR order, zero
+                    # padded: their product with their own transpose sums
+                    # S' S'^T in a fixed order (no atomics)
+                    slot = np.arange(starts[n0], starts[n1]) - starts[ii]
+                    Y = torch.zeros(n1 - n0, cmax, k1, k1, dtype=torch.float64, device=dev)
+                    Y[torch.as_tensor(ii - n0, device=dev), torch.as_tensor(slot, device=dev)] = Sp
+                    Y = Y.permute(0, 2, 1, 3).reshape(n1 - n0, k1, cmax * k1)
+                    Gm[n0:n1] = torch.bmm(Y, Y.transpose(1, 2))
+                if l > top:
+                    par = torch.as_tensor(t.parent[lp[l] + np.arange(n0, n1)] - lp[l - 1],
+                                          device=dev).long()
+                    E1 = Lv.E1[n0:n1]
+                    Gm[n0:n1] += torch.bmm(torch.bmm(E1, lev[l - 1].Gm[par]), E1.transpose(1, 2))
+            else:
+                # W_t = R^T, R the R factor of the stacked rows
+                # [S'_ts^T for s in far(t); (E1_t W_parent)^T]
+                blocks = torch.zeros(n1 - n0, maxrows, k1, dtype=torch.float64, device=dev)
+                if len(sl):
+                    ii, jj = fi[sl], fj[sl]
+                    Sp = coupling(l, ii, jj, Lv.R[ii], Lv.R[jj])
+                    slot = np.arange(starts[n0], starts[n1]) - starts[ii]
+                    # a view of the stacked blocks (slot, k1 x k1): the indexed
+                    # assignment writes through to `blocks`
+                    tmp = blocks[:, :int(cnt.max()) * k1].view(n1 - n0, int(cnt.max()), k1, k1)
+                    tmp[torch.as_tensor(ii - n0, device=dev),
+                        torch.as_tensor(slot, device=dev)] = Sp.transpose(1, 2)
+                if l > top:
+                    par = torch.as_tensor(t.parent[lp[l] + np.arange(n0, n1)] - lp[l - 1],
+                                          device=dev).long()
+                    EW = torch.bmm(Lv.E1[n0:n1], lev[l - 1].W[par])  # (nb, k1, kp)
+                    blocks[:, maxrows - kp:maxrows, :] = EW.transpose(1, 2)
+                W[n0:n1] = _qr_r(blocks).transpose(1, 2)
+        if gram:
+            Lv.Gm = Gm
+        else:
+            Lv.W = W
 
     say("weights done")
     # ---- step 4: truncation upsweep ----
     for l in range(L, top - 1, -1):
         say(f"truncation, level {l}")
         Lv = lev[l]
-        if l == L:
-            M = Lv.W
-        else:
+        if l < L:
             Lc = lev[l + 1]
             arity = Lc.n // Lv.n
             TE = torch.bmm(Lc.T, Lc.E1)  # (nchild, kc2max, k1)
             Z = TE.reshape(Lv.n, arity * Lc.T.shape[1], Lv.k1)
             Lv.Z = Z
-            M = torch.bmm(Z, Lv.W)
-        # small batched SVDs run on the host (LAPACK); the device path of some
-        # builds fails to converge on strongly graded spectra
-        Pm, sv, _ = torch.linalg.svd(M.cpu(), full_matrices=False)
-        Pm, sv = Pm.to(dev), sv.to(dev)
+        # coordinates that are padding (leaf points that do not exist, child
+        # basis vectors beyond a child's rank)
+        if l == L:
+            valid = Lv.mask if Lv.identity else torch.ones(Lv.n, Lv.k1, dtype=torch.float64,
+                                                            device=dev)
+        else:
+            kc = torch.as_tensor(Lc.k2, device=dev).view(Lv.n, arity, 1)
+            valid = (torch.arange(Lc.T.shape[1], device=dev).view(1, 1, -1) < kc)
+            valid = valid.reshape(Lv.n, -1).to(torch.float64)
+        rows = valid.shape[1]
+        if gram:
+            MM = Lv.Gm if l == L else torch.bmm(torch.bmm(Z, Lv.Gm), Z.transpose(1, 2))
+            # padding rows of M M^T are zero; a diagonal of -2 ||M M^T|| there
+            # separates them from every kept eigenvector, which then has no
+            # component on them
+            MM = 0.5 * (MM + MM.transpose(1, 2))
+            big = (MM.abs().amax(dim=(1, 2)) if rows else
+                   torch.zeros(Lv.n, dtype=torch.float64, device=dev)).clamp(min=1.0)
+            MM = MM * valid.unsqueeze(1) * valid.unsqueeze(2)
+            MM = MM - torch.diag_embed((1.0 - valid) * 2.0 * big.view(-1, 1))
+            # M M^T = P diag(sigma^2) P^T, eigenvalues descending; the small
+            # batched eigenproblems run on the host (LAPACK)
+            if rows:
+                lam, Pm = _host_batched(np.linalg.eigh, MM, 2)
+            else:
+                lam, Pm = MM.new_zeros(Lv.n, 0), MM.new_zeros(Lv.n, 0, 0)
+            lam, Pm = lam.flip(-1), Pm.flip(-1)
+            sv = torch.sqrt(torch.clamp(lam, min=0.0))
+        else:
+            M = Lv.W if l == L else torch.bmm(Z, Lv.W)
+            # the small batched SVDs run on the host (LAPACK)
+            if rows:
+                Pm, sv = _host_batched(lambda a: np.linalg.svd(a, full_matrices=False)[:2], M, 2)
+            else:
+                Pm, sv = M.new_zeros(Lv.n, 0, 0), M.new_zeros(Lv.n, 0)
         k2 = (sv > thr).sum(1).cpu().numpy()
         Lv.k2 = k2
         k2max = max(int(k2.max()), 0)
         Pk = Pm[:, :, :k2max] * (torch.arange(k2max, device=dev).view(1, 1, -1)
                                    < torch.as_tensor(k2, device=dev).view(-1, 1, 1))
+        Pk = Pk * valid.unsqueeze(2)
         Lv.Pk = Pk
         if l == L:
             Lv.T = Pk.transpose(1, 2)  # (n, k2max, k1)
