@@ -246,15 +246,18 @@ typedef enum {
   H2_INT_OFFSETS = 6,  /* block layout of the level (Section 2.2: offsets are prefix sums of
                           the products of block dimensions): for every entry of the level's
                           block pattern (near pairs and fill pairs, rows ascending, columns
-                          ascending) the record (j, k, is_fill, offset) with global node ids;
+                          ascending) the record (j, k, kind, offset) with global node ids;
                           near blocks and fill blocks have a buffer each, n_j x n_k blocks in
-                          that order */
+                          that order.  kind 0: near block; 1: fill block (j < k); 2: fill
+                          entry (j, k) with k < j, stored once as the transpose of the block
+                          (k, j) (the fill of a symmetric matrix is symmetric), whose offset
+                          it repeats */
   H2_INT_CLUSTER_OFFSETS = 7, /* per cluster of the level: offset of Q~_i (prefix sum of n_i^2) */
   H2_INT_OWNERS = 8    /* Schur/fill-in owner lists (needs opts->keep_owner_lists): for every
-                          colour c ascending and every target block (j, k) that clusters of
-                          colour c update, targets ascending, the record
-                          (c, j, k, m, i_1 .. i_m) with the m contributing clusters ascending
-                          (global ids) */
+                          colour c ascending and every stored target block (j, k) that
+                          clusters of colour c update (near pairs, and fill pairs with
+                          j < k), targets ascending, the record (c, j, k, m, i_1 .. i_m)
+                          with the m contributing clusters ascending (global ids) */
 } h2_int_kind;
 
 /* Copy an integer output of the factorization into the host buffer `buf`

@@ -392,17 +392,27 @@ def block_layout(Lf):
     pattern (near pairs and fill pairs; rows ascending, columns ascending)
     placed in one buffer for the near blocks and one for the fill blocks, each
     block n_j x n_k, at offsets that are exclusive prefix sums of the products
-    of the block dimensions.  Returns records (j, k, is_fill, offset)."""
+    of the block dimensions.  The input is symmetric (the standing assumption
+    of Section 2), so the fill is too (F_kj = F_jk^T): the fill buffer holds
+    one block per unordered pair, (j, k) with j < k, and the entry (k, j)
+    names that block.  Returns records (j, k, kind, offset): kind 0 near,
+    1 stored fill block, 2 fill entry stored as the transpose of (k, j)."""
     nearset = {(q, j) for q in Lf.nodes for j in Lf.near[q]}
     frow = {q: [] for q in Lf.nodes}
     for (a, k) in Lf.fpat:
         frow[a].append(k)
     out = []
     nxt = {False: 0, True: 0}
+    fill_off = {}
     for j in Lf.nodes:
         cols = sorted(set(Lf.near[j]) | set(frow[j]))
         for k in cols:
             isf = (j, k) not in nearset
+            if isf and k < j:
+                out.append((j, k, 2, fill_off[(k, j)]))
+                continue
+            if isf:
+                fill_off[(j, k)] = nxt[True]
             out.append((j, k, int(isf), nxt[isf]))
             nxt[isf] += Lf.n[j] * Lf.n[k]
     return out
@@ -420,9 +430,14 @@ def cluster_offsets(Lf):
 
 def owner_records(Lf):
     """Flattened (c, j, k, m, i_1..i_m) for every colour c ascending and every
-    target (j, k) ascending that clusters of colour c update."""
+    stored target (j, k) ascending that clusters of colour c update: near
+    pairs, and fill pairs with j < k (the fill block of the pair; the update
+    of (k, j) is its transpose, see block_layout)."""
+    nearset = {(q, j) for q in Lf.nodes for j in Lf.near[q]}
     rec = []
     for (c, j, k) in sorted(Lf.owners):
+        if k < j and (j, k) not in nearset:
+            continue
         con = Lf.owners[(c, j, k)]
         rec += [c, j, k, len(con)] + list(con)
     return rec

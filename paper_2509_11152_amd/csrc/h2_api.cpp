@@ -604,7 +604,7 @@ h2_status h2_factor_export_ints(h2_factor_t F, int level, h2_int_kind kind, int6
         for (int64_t e = P->pptr[j]; e < P->pptr[j + 1]; ++e) {
           v.push_back(j + P->a);
           v.push_back(P->pcol[e] + P->a);
-          v.push_back(P->isF[e] ? 1 : 0);
+          v.push_back(P->isF[e] ? (P->tr(j, e) ? 2 : 1) : 0);
           v.push_back(P->poff[e]);
         }
     } else if (kind == H2_INT_CLUSTER_OFFSETS) {

@@ -176,17 +176,24 @@ void plan_level_structure(const h2_matrix_s& H, int lev,
 }
 
 // Block layout of a level from its cluster sizes n: D entries and F entries in
-// two buffers, CSR order, n_i x n_j column-major.
+// two buffers, CSR order, n_i x n_j column-major.  The fill of the symmetric
+// matrix is symmetric (F_kj = F_jk^T), so the F buffer holds one block per
+// unordered pair, (j, k) with j < k; the entry (k, j) refers to it.
 void plan_level_layout(LevelPlan& P, const std::vector<int>& n) {
   P.n = n;
   P.poff.assign(P.pcol.size(), 0);
   P.nD = P.nF = 0;
   for (int j = 0; j < P.nl; ++j)
     for (int64_t e = P.pptr[j]; e < P.pptr[j + 1]; ++e) {
-      const int64_t sz = (int64_t)P.n[j] * P.n[P.pcol[e]];
+      const int k = P.pcol[e];
+      const int64_t sz = (int64_t)P.n[j] * P.n[k];
       if (P.isF[e]) {
-        P.poff[e] = P.nF;
-        P.nF += sz;
+        if (k < j) {
+          P.poff[e] = P.poff[P.find(k, j)];  // row k precedes row j
+        } else {
+          P.poff[e] = P.nF;
+          P.nF += sz;
+        }
       } else {
         P.poff[e] = P.nD;
         P.nD += sz;
@@ -285,7 +292,8 @@ template <class T> int64_t copy_tiles(int rows, int cols) {
 template <class T> struct CopyBatch {
   std::vector<CTask<T, T>> tasks;
   int64_t tiles = 0;
-  void add(const T* src, int64_t lds, T* dst, int64_t ldd, int rows, int cols, int add) {
+  void add(const T* src, int64_t lds, T* dst, int64_t ldd, int rows, int cols, int add,
+           int tr = 0) {
     if (rows <= 0 || cols <= 0) return;
     CTask<T, T> t{};
     t.src = src;
@@ -295,6 +303,7 @@ template <class T> struct CopyBatch {
     t.rows = rows;
     t.cols = cols;
     t.add = add;
+    t.tr = tr;
     t.tile0 = tiles;
     tiles += copy_tiles<T>(rows, cols);
     tasks.push_back(t);
@@ -572,7 +581,8 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
             const int j = P.pcol[e];
             FillRef<T> fr{};
             fr.F = blk(e);
-            fr.ld = ni;
+            fr.tr = P.tr(i, e) ? 1 : 0;
+            fr.ld = fr.tr ? P.n[j] : ni;  // the stored block is (j, i) when transposed
             fr.ncols = P.n[j];
             fr.d0 = wdyn(j, false);
             cur.push_back(fr);
@@ -656,11 +666,24 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
             STask<T> t{};
             t.X = blk(e);
             t.Q = S.Q.p + P.offQ[i];
-            t.ldx = ni;
             t.n = ni;
             t.ext = P.n[j];
             t.d0 = wdyn(j, false);
             t.s0 = 0;
+            if (P.tr(i, e)) {
+              // fill stored as (j, i): its column side, F_ji <- F_ji Q~ (the
+              // one update of the pair's block by cluster i)
+              if (P.n[j] > 0 && ni > 0) {
+                t.ldx = P.n[j];
+                t.side = 1;
+                t.trans = 0;
+                t.strip0 = nsr;
+                nsr += (P.n[j] + kStrip - 1) / kStrip;
+                sr.push_back(t);
+              }
+              continue;
+            }
+            t.ldx = ni;
             t.side = 0;
             t.trans = 1;
             t.strip0 = nsl;
@@ -668,11 +691,13 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
             if (P.n[j] > 0 && ni > 0) sl.push_back(t);
             else nsl -= (P.n[j] + kStrip - 1) / kStrip;
           }
-          // column i: entries (j, i) for j in the pattern row of i (symmetric pattern)
+          // column i: entries (j, i) for j in the pattern row of i (symmetric
+          // pattern); fill blocks are stored once per pair and were updated
+          // above
           for (int64_t e = P.pptr[i]; e < P.pptr[i + 1]; ++e) {
             const int j = P.pcol[e];
             const int64_t et = P.find(j, i);
-            if (P.isF[et] && P.firstc[et] >= c && j != i) continue;
+            if (P.isF[et]) continue;
             STask<T> t{};
             t.X = blk(et);
             t.Q = S.Q.p + P.offQ[i];
@@ -745,6 +770,9 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
                 while (e < e1 && P.pcol[e] < k) ++e;
                 if (e == e1 || P.pcol[e] != k)
                   throw H2Error(H2_ERROR_FORMAT, "fill pattern misses a Schur target");
+                // fill (j, k) with k < j is the transpose of the stored (k, j),
+                // which receives the transposed update
+                if (P.tr(j, e)) continue;
                 incs.push_back(e);
                 incA.push_back(eji[qj]);
                 incB.push_back(eik[qk]);
@@ -1080,6 +1108,9 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         ld = PN->n[t];
         if (e < 0) throw H2Error(H2_ERROR_FORMAT, "close-out destination missing from the pattern");
         (void)near_pair;
+        // fill (t, s2) with s2 < t is the stored (s2, t): the mirror entry
+        // writes it
+        if (PN->tr(t, e)) return (T*)nullptr;
         return (PN->isF[e] ? Fn : Dn) + PN->poff[e];
       };
       for (int j = 0; j < Pc.nl; ++j) {
@@ -1090,12 +1121,20 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           const int k = Pc.pcol[e];
           const int ps = H.parent[Pc.a + k] - pa;
           const int rk = Pc.r[k], ktk = Pc.n[k] - rk;
-          const T* src = (Pc.isF[e] ? I->Fbuf.p : Sc->D.p) + Pc.poff[e] + rj + (int64_t)rk * Pc.n[j];
           int64_t ld = 0;
           T* d = dest(pt, ps, true, ld);
+          if (!d) continue;
           d += offc[j] + (int64_t)offc[k] * ld;
-          // near: copy; fill: accumulate (a far pair also receives its coupling)
-          cb.add(src, Pc.n[j], d, ld, ktj, ktk, Pc.isF[e] ? 1 : 0);
+          // near: copy; fill: accumulate (a far pair also receives its
+          // coupling); a fill entry (j, k) with k < j is read as the
+          // transpose of the stored (k, j)
+          if (Pc.tr(j, e)) {
+            const T* src = I->Fbuf.p + Pc.poff[e] + rk + (int64_t)rj * Pc.n[k];
+            cb.add(src, Pc.n[k], d, ld, ktj, ktk, 1, 1);
+          } else {
+            const T* src = (Pc.isF[e] ? I->Fbuf.p : Sc->D.p) + Pc.poff[e] + rj + (int64_t)rk * Pc.n[j];
+            cb.add(src, Pc.n[j], d, ld, ktj, ktk, Pc.isF[e] ? 1 : 0);
+          }
         }
         // couplings of far pairs into the skeleton blocks: S~ = [S 0; 0 0]
         for (int64_t e = H.far_ptr[gj]; e < H.far_ptr[gj + 1]; ++e) {
@@ -1103,6 +1142,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           const int ps = H.parent[Pc.a + k] - pa;
           int64_t ld = 0;
           T* d = dest(pt, ps, true, ld);
+          if (!d) throw H2Error(H2_ERROR_FORMAT, "parents of a far pair are not a near pair");
           d += offc[j] + (int64_t)offc[k] * ld;
           cb2.add(I->data + H.offS[e], H.rank[gj], d, ld, H.rank[gj], H.rank[Pc.a + k], 1);
         }

@@ -249,7 +249,8 @@ struct LevelPlan {
   std::vector<int64_t> pptr;
   std::vector<int> pcol;
   std::vector<char> isF;
-  std::vector<int64_t> poff;   // element offset in the D or F buffer
+  std::vector<int64_t> poff;   // element offset in the D or F buffer (a fill entry (j, k)
+                               // with k < j: offset of the stored block (k, j))
   std::vector<int> firstc;     // fill entries: first colour that writes it (-1 lifted)
   std::vector<int64_t> offQ, offV, offPiv;
   int64_t nD = 0, nF = 0, nQ = 0, nV = 0, nPiv = 0;
@@ -257,6 +258,9 @@ struct LevelPlan {
   std::vector<std::pair<int, int>> fill_pairs;  // (j, k) local, sorted (integer output)
   // Schur target lists, kept on request: records (c, j, k, m, i_1..i_m), global ids
   std::vector<int64_t> owners;
+  // fill is stored once per unordered pair, as the block (j, k) with j < k;
+  // entry e of row j is then the transpose of its stored block
+  bool tr(int j, int64_t e) const { return isF[e] && pcol[e] < j; }
   int64_t find(int i, int j) const {
     int64_t lo = pptr[i], hi = pptr[i + 1];
     while (lo < hi) {

@@ -55,13 +55,23 @@ template <class T> struct STask {
   int64_t strip0;       // first strip index in the launch
 };
 
-// One column block of the fill row of a cluster: columns c0..ncols-1 of F
-// (n rows, leading dimension ld), c0 = dyn[d0] or 0.
+// One column block of the fill row of a cluster: columns c0..ncols-1 of the
+// n x ncols block F_ij, c0 = dyn[d0] or 0.  Entry (a, c) is F[a + c ld], or
+// F[c + a ld] when `tr` is set (the fill of a symmetric matrix is stored once
+// per unordered pair: F_ij is then the transpose of the stored F_ji).
 template <class T> struct FillRef {
   const T* F;
   int64_t ld;
   int32_t ncols, d0;
+  int32_t tr, pad0;
 };
+// strides of entry (a, c) of a fill block: a * rs + c * cs
+template <class T> __host__ __device__ inline int64_t fr_rs(const FillRef<T>& f) {
+  return f.tr ? f.ld : 1;
+}
+template <class T> __host__ __device__ inline int64_t fr_cs(const FillRef<T>& f) {
+  return f.tr ? 1 : f.ld;
+}
 
 // One stage of the tall-skinny QR of a fill row Y (Section 2.1, QR-based
 // augmentation): the R factor of the rows of Y^T held by a group of fill
@@ -122,13 +132,14 @@ template <class T> struct TrsmTask {
   int32_t pad0;
 };
 
-// dst[0:rows, 0:cols] (=|+=) src[0:rows, 0:cols]; element types may differ.
+// dst[0:rows, 0:cols] (=|+=) src[0:rows, 0:cols], or the transpose of
+// src[0:cols, 0:rows] when `tr` is set; element types may differ.
 template <class T, class S> struct CTask {
   const S* src;
   T* dst;
   int64_t lds, ldd;
   int32_t rows, cols;
-  int32_t add, pad0;
+  int32_t add, tr;
   int64_t tile0;
 };
 

@@ -566,10 +566,11 @@ __device__ inline int rf_load_chunk(T (&cr)[RPT], const FillRef<T>* __restrict__
     const FillRef<T> fr = refs[f];
     const int take = min(RPT - fill, fr.ncols - c0);
     if (take > 0 && col < n) {
-      const gptr<const T> src = gmem(fr.F) + col + (int64_t)(c0 - fill) * fr.ld;
+      const int64_t cs = fr_cs(fr);
+      const gptr<const T> src = gmem(fr.F) + col * fr_rs(fr) + (int64_t)(c0 - fill) * cs;
 #pragma unroll
       for (int u = 0; u < RPT; ++u)
-        if (u >= fill && u < fill + take) cr[u] = src[(int64_t)u * fr.ld];
+        if (u >= fill && u < fill + take) cr[u] = src[(int64_t)u * cs];
     }
     fill += max(take, 0);
     c0 += max(take, 0);
@@ -742,9 +743,10 @@ __global__ __launch_bounds__(256) void k_rfactor(const RTask<T>* __restrict__ ta
       int c = fr.d0 >= 0 ? dyn[fr.d0] : 0;
       while (c < fr.ncols) {
         const int take = min(kAugChunk - fill, fr.ncols - c);
+        const int64_t rs = fr_rs(fr), cs = fr_cs(fr);
         for (int e = tid; e < take * n; e += nthr) {
           const int tt = e / n, col = e % n;
-          C[(fill + tt) + (int64_t)col * ldw] = fr.F[col + (int64_t)(c + tt) * fr.ld];
+          C[(fill + tt) + (int64_t)col * ldw] = fr.F[col * rs + (int64_t)(c + tt) * cs];
         }
         fill += take;
         c += take;
@@ -818,22 +820,23 @@ __global__ __launch_bounds__(256) void k_gram(const GramTask<T>* __restrict__ ta
     const FillRef<T> fr = refs[f];
     const int k0 = fr.d0 >= 0 ? dyn[fr.d0] : 0;
     const int k1 = fr.ncols;
+    const int64_t rs = fr_rs(fr), cs = fr_cs(fr);
     for (int kk = k0; kk < k1; kk += 16) {
       double av[4][2], bv[4][2];
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
         const int kx = kk + 4 * s4 + kq;
         const bool kok = kx < k1;
-        const T* col = fr.F + (int64_t)kx * fr.ld;
+        const T* col = fr.F + (int64_t)kx * cs;
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
           const int row = wr + a * 16 + l16;
-          av[s4][a] = (kok && row < n) ? double(col[row]) : 0.0;
+          av[s4][a] = (kok && row < n) ? double(col[row * rs]) : 0.0;
         }
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           const int cc = wc + b * 16 + l16;
-          bv[s4][b] = (kok && cc < n) ? double(col[cc]) : 0.0;
+          bv[s4][b] = (kok && cc < n) ? double(col[cc * rs]) : 0.0;
         }
       }
       // G = Y Y^T: the "B" operand is Y^T, whose (k, col) entry is Y[col][k];
@@ -1163,7 +1166,11 @@ static void launch_augment_t(const AugTask<T>* tasks, int ntasks, int32_t* r, in
                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_augment<T, A, GRAM>), dim3(ntasks), dim3(1024),
+  // workgroup size from the largest order: the Jacobi rotates (n - k) / 2
+  // column pairs per round, a group of 8 to 64 lanes each, and a round ends
+  // with a barrier over every wave, so small clusters take fewer waves
+  const int threads = maxn <= 64 ? 128 : maxn <= 128 ? 256 : maxn <= 256 ? 512 : 1024;
+  hipLaunchKernelGGL((k_augment<T, A, GRAM>), dim3(ntasks), dim3(threads),
                      (size_t)(need * sizeof(A)), s, tasks, r, err, (int)need);
 }
 
@@ -1478,7 +1485,7 @@ void launch_trsm(const TrsmTask<T>* tasks, int ntasks, const int32_t* dyn, int m
   if (ntasks <= 0 || maxr <= 0 || maxcols <= 0) return;
   lds = std::min(lds, kLdsBytes);
   const size_t wlds = (size_t)maxr * maxr * sizeof(T) + 2 * (size_t)maxr * sizeof(int);
-  if (maxcols <= 16 && maxr <= 256 && wlds <= (size_t)lds) {
+  if (maxcols <= 64 && maxr <= 256 && wlds <= (size_t)lds) {
     static bool wattr = false;
     if (!wattr) {
       (void)hipFuncSetAttribute((const void*)k_trsm_wave<T>,
@@ -1517,9 +1524,18 @@ __global__ __launch_bounds__(256) void k_copy(const CTask<T, S>* __restrict__ ta
   const CTask<T, S>& tk = tasks[lo];
   const int64_t base = (tile - tk.tile0) * kCopyTile;
   const int64_t tot = (int64_t)tk.rows * tk.cols;
+  // a transposed source is read along its columns (element e runs down a
+  // destination row) so that both sides of the copy stay coalesced enough
   for (int64_t e = base + threadIdx.x; e < min(base + kCopyTile, tot); e += blockDim.x) {
-    const int64_t r = e % tk.rows, c = e / tk.rows;
-    const T v = (T)tk.src[r + c * tk.lds];
+    int64_t r, c;
+    if (tk.tr) {
+      c = e % tk.cols;
+      r = e / tk.cols;
+    } else {
+      r = e % tk.rows;
+      c = e / tk.rows;
+    }
+    const T v = (T)(tk.tr ? tk.src[c + r * tk.lds] : tk.src[r + c * tk.lds]);
     T* d = tk.dst + r + c * tk.ldd;
     *d = tk.add ? *d + v : v;
   }

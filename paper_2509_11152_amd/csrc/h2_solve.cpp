@@ -19,6 +19,11 @@ namespace {
 
 // contributor K per chunk above which a skinny output is split over workgroups
 constexpr int64_t kSplitK = 192;
+// right-hand sides up to which the block products use the skinny 64 x 16
+// tiles (K split over the four waves and long contributor lists over
+// workgroups); wider blocks use 64 x 64 tiles
+constexpr int kSkinnyCols = 64;
+inline int product_shape(int nrhs) { return nrhs <= kSkinnyCols ? 1 : 0; }
 
 // Where a solve's launches go: straight to the stream (descriptors staged
 // through the context's arena), or into a plan that later solves with the
@@ -311,7 +316,7 @@ void solve_setup(SolveInst<T>& S, h2_factor_s* F, int nrhs, DevTracker* tr) {
 // dense top solve, then backward.
 template <class T>
 void solve_body(Emit<T>& em, std::vector<SolveInst<T>>& si, int nrhs) {
-  const int shape = nrhs > 16 ? 0 : 1;
+  const int shape = product_shape(nrhs);
   size_t maxlev = 0;
   for (auto& S : si) maxlev = std::max(maxlev, S.F->plans.size());
   // ---- forward, level by level from the leaves ----
@@ -649,7 +654,7 @@ void matvec_layout(h2_matrix_s* H) {
 // yt out, xh / yh the basis coefficients (hat_total x nrhs).
 void matvec_body(Emit<double>& em, const h2_matrix_s* H, const double* xt, double* yt, double* xh,
                  double* yh, int nrhs) {
-  const int shape = nrhs > 16 ? 0 : 1;
+  const int shape = product_shape(nrhs);
   const int64_t N = H->N;
   const double* d = H->data.p;
   auto hx = [&](int q) { return xh + H->hat_off[q] * nrhs; };

@@ -116,6 +116,36 @@ def test_solve_fp64(lib, ctx, name, spec):
     assert rel <= 1e-10 and res <= 1e-10 and ew <= 1e-10
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_wide_right_hand_sides(lib, ctx, prec):
+    """40 right-hand sides (products tiled over three 16-column tiles, several
+    columns per wave in the triangular solves): solve and product against the
+    oracle column by column."""
+    from oracle import factor as of
+    from oracle import h2ops
+
+    name, spec = "exp3d_4096", EXP3D_4096
+    print(f"[gpu] 40 right-hand sides {prec} {name}", flush=True)
+    w = workload(name, spec)
+    H = gpu_matrix(lib, ctx, name, spec)
+    Ho = oracle_matrix(name, spec)
+    B = np.random.default_rng(40).standard_normal((Ho.N, 40))
+    Y = H.matvec(_cuda(B)).cpu().numpy()
+    Yo = h2ops.matvec(Ho, B)
+    assert np.linalg.norm(Y - Yo) <= 1e-13 * np.linalg.norm(Yo)
+    if prec == "fp64":
+        X = lib.Factor(ctx, H, w["spec"]["tol"]).solve(_cuda(B)).cpu().numpy()
+        Xo = of.solve(oracle_factor(name, spec=spec), B)
+        ew = np.abs(X - Xo).max() / np.abs(Xo).max()
+        rel = np.linalg.norm(X - Xo, axis=0) / np.linalg.norm(Xo, axis=0)
+        assert rel.max() <= 1e-10 and ew <= 1e-10, (rel.max(), ew)
+    else:
+        F32 = lib.Factor(ctx, H, w["spec"]["tol"], lib.H2_PREC_FP32)
+        X, rep = lib.solve_ir(ctx, H, F32, _cuda(B), target=1e-12)
+        eb = h2ops.backward_error(Ho, X.cpu().numpy(), B)
+        assert rep["converged"] and eb.max() <= 1e-12, (rep, eb.max())
+
+
 # LDS budgets (KiB) below the default 150: at 8 KiB every fill-row QR, augmentation, LU of
 # D_RR and multiplier solve of order above ~40 (FP64) runs its global-memory variant; at
 # 48 KiB the launches mix both variants (orders up to ~110 in LDS, larger ones in global

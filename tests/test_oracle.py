@@ -219,3 +219,30 @@ def test_linear_time_and_memory():
     print(f"time slope {lt:.3f} ({ts}), memory slope {lm:.3f} ({ms})")
     assert 0.8 <= lt <= 1.2
     assert 0.85 <= lm <= 1.2
+
+
+def test_block_layout_prefix_sums_and_symmetric_fill():
+    """Section 2.2's layout: offsets are exclusive prefix sums of the block
+    sizes in pattern order, near and fill blocks in separate buffers; the
+    fill, symmetric like the matrix, has one stored block per unordered pair
+    and the mirrored entry names it."""
+    Fz = oracle_factor("exp2d_4096")
+    for Lf in Fz.levels:
+        lay = of.block_layout(Lf)
+        nearset = {(q, j) for q in Lf.nodes for j in Lf.near[q]}
+        assert {(j, k) for j, k, _, _ in lay} == nearset | set(Lf.fpat)
+        nxt = {0: 0, 1: 0}
+        stored = {}
+        for j, k, kind, off in lay:
+            if kind == 2:
+                assert k < j and (j, k) not in nearset
+                continue
+            assert kind == int((j, k) not in nearset) and off == nxt[kind]
+            nxt[kind] += Lf.n[j] * Lf.n[k]
+            if kind == 1:
+                assert j < k
+                stored[(j, k)] = off
+        for j, k, kind, off in lay:
+            if kind == 2:
+                assert off == stored[(k, j)]
+        assert 2 * len(stored) == len(Lf.fpat)
