@@ -47,7 +47,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", default="exp3d_262144")
+    p.add_argument("--workload", default="laplace3d_1048576")
     p.add_argument("--budget-s", type=float, default=540.0,
                    help="wall-clock budget of the whole run from process start: warm-up and "
                         "timed steps stop early (the line reports how many ran) when the rest "

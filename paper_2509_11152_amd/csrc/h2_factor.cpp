@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <deque>
+#include <exception>
 #include <future>
 #include <memory>
 #include <numeric>
@@ -183,16 +184,23 @@ void plan_level_layout(LevelPlan& P, const std::vector<int>& n) {
   P.n = n;
   P.poff.assign(P.pcol.size(), 0);
   P.nD = P.nF = 0;
+  // cur[k]: next entry of row k whose column is still to come; entries (k, j)
+  // with j < k are met in ascending j as rows j are visited, so a cursor per
+  // row finds the mirror of every stored fill block without a search
+  std::vector<int64_t> cur(P.pptr.begin(), P.pptr.end() - 1);
   for (int j = 0; j < P.nl; ++j)
     for (int64_t e = P.pptr[j]; e < P.pptr[j + 1]; ++e) {
       const int k = P.pcol[e];
       const int64_t sz = (int64_t)P.n[j] * P.n[k];
       if (P.isF[e]) {
-        if (k < j) {
-          P.poff[e] = P.poff[P.find(k, j)];  // row k precedes row j
-        } else {
+        if (k > j) {
           P.poff[e] = P.nF;
           P.nF += sz;
+          int64_t& m = cur[k];  // the mirror (k, j), after the entries of row k below j
+          while (m < P.pptr[k + 1] && P.pcol[m] < j) ++m;
+          if (m == P.pptr[k + 1] || P.pcol[m] != j || !P.isF[m])
+            throw H2Error(H2_ERROR_FORMAT, "fill pattern is not symmetric");
+          P.poff[m] = P.poff[e];
         }
       } else {
         P.poff[e] = P.nD;
@@ -307,6 +315,13 @@ template <class T> struct CopyBatch {
     t.tile0 = tiles;
     tiles += copy_tiles<T>(rows, cols);
     tasks.push_back(t);
+  }
+  // append another batch's tasks (its tiles numbered after this one's)
+  void append(const CopyBatch& o) {
+    const size_t n0 = tasks.size();
+    tasks.insert(tasks.end(), o.tasks.begin(), o.tasks.end());
+    for (size_t q = n0; q < tasks.size(); ++q) tasks[q].tile0 += tiles;
+    tiles += o.tiles;
   }
   void launch(DescArena& ar, hipStream_t s) {
     if (tasks.empty()) return;
@@ -553,7 +568,6 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       auto& cons = cp.cons;
       int64_t& gtiles = cp.gtiles;
       int64_t woff = 0, goff = 0;
-      std::vector<int32_t> slotbuf;  // pattern entry -> output of the colour
       for (auto* I : act) {
         LevelPlan& P = I->F->plans[I->li];
         if (c >= P.ncolors) continue;
@@ -740,119 +754,135 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           }
         }
         // ---- Schur complement / fill-in targets, owner-computes ----
-        // target (j, k) collects every i of the colour with j, k in N(i);
-        // outputs in first-touch order, contributors in ascending i
+        // target (j, k) collects every i of the colour with j, k in N(i), i.e.
+        // the colour's clusters i in N(j) whose near list holds k; targets in
+        // ascending (j, k), contributors in ascending i.  Rows j are planned
+        // on worker threads and appended in row order.
         {
-          std::vector<int32_t>& slot = slotbuf;  // entries are reset after use
-          if (slot.size() != P.pcol.size()) slot.assign(P.pcol.size(), -1);
-          std::vector<int64_t> ent;      // output -> pattern entry
-          std::vector<int32_t> cnt;
-          // every incidence (i, j, k) in loop order: target (j, k), operands (j, i), (i, k)
-          std::vector<int64_t> incs, incA, incB;
-          std::vector<int32_t> inci, incj;
-          std::vector<int64_t> eji, eik;
-          for (int i : P.members[c]) {
-            const std::vector<int>& nbi = P.nb[i];  // sorted
-            const size_t m = nbi.size();
-            eji.resize(m);
-            eik.resize(m);
-            for (size_t q = 0; q < m; ++q) {
-              eji[q] = P.find(nbi[q], i);
-              eik[q] = P.find(i, nbi[q]);
-            }
-            for (size_t qj = 0; qj < m; ++qj) {
-              const int j = nbi[qj];
-              // (j, k) for every k of nbi: merge the sorted pattern row of j
+          std::vector<int> rows;  // rows touched by the colour
+          {
+            std::vector<char> mark(P.nl, 0);
+            for (int i : P.members[c])
+              for (int j : P.nb[i]) mark[j] = 1;
+            for (int j = 0; j < P.nl; ++j)
+              if (mark[j]) rows.push_back(j);
+          }
+          struct Part {
+            std::vector<GOut<T>> outs;
+            std::vector<GCon<T>> cons;
+            std::vector<int64_t> rec;
+            int64_t tiles = 0;
+          };
+          const bool keep = I->F->keep_owners;
+          auto plan_rows = [&](size_t r0, size_t r1, Part& pt) {
+            std::vector<int> stamp(P.nl, -1), conts, tk;
+            std::vector<int64_t> econt;  // entry (j, i) of each contributor
+            for (size_t q = r0; q < r1; ++q) {
+              const int j = rows[q];
+              conts.clear();
+              econt.clear();
+              tk.clear();
+              for (int i : P.nb[j])
+                if (P.color[i] == c) {
+                  conts.push_back(i);
+                  econt.push_back(P.find(j, i));
+                }
+              for (int i : conts)
+                for (int k : P.nb[i])
+                  if (stamp[k] != j) {
+                    stamp[k] = j;
+                    tk.push_back(k);
+                  }
+              std::sort(tk.begin(), tk.end());
               int64_t e = P.pptr[j];
               const int64_t e1 = P.pptr[j + 1];
-              for (size_t qk = 0; qk < m; ++qk) {
-                const int k = nbi[qk];
+              for (int k : tk) {
                 while (e < e1 && P.pcol[e] < k) ++e;
                 if (e == e1 || P.pcol[e] != k)
                   throw H2Error(H2_ERROR_FORMAT, "fill pattern misses a Schur target");
                 // fill (j, k) with k < j is the transpose of the stored (k, j),
                 // which receives the transposed update
                 if (P.tr(j, e)) continue;
-                incs.push_back(e);
-                incA.push_back(eji[qj]);
-                incB.push_back(eik[qk]);
-                inci.push_back(i);
-                incj.push_back(j);
-                if (slot[e] < 0) {
-                  slot[e] = (int32_t)ent.size();
-                  ent.push_back(e);
-                  cnt.push_back(0);
+                const int cb0 = (int)pt.cons.size();
+                for (size_t x = 0; x < conts.size(); ++x) {
+                  const int i = conts[x];
+                  const int64_t eik = P.find(i, k);
+                  if (eik < 0 || P.isF[eik]) continue;  // k not near i
+                  GCon<T> g{};
+                  g.A = S.D.p + P.poff[econt[x]];
+                  g.lda = P.n[j];
+                  g.B = S.D.p + P.poff[eik];
+                  g.ldb = P.n[i];
+                  g.k = P.n[i];
+                  g.k0d = -1;
+                  g.k0s = 0;
+                  g.k1d = rb + i;
+                  g.transA = 0;
+                  pt.cons.push_back(g);
                 }
-                cnt[slot[e]]++;
+                const int ce0 = (int)pt.cons.size();
+                if (keep) {
+                  pt.rec.push_back(c);
+                  pt.rec.push_back(j + P.a);
+                  pt.rec.push_back(k + P.a);
+                  pt.rec.push_back(ce0 - cb0);
+                  for (int x = cb0; x < ce0; ++x) pt.rec.push_back(pt.cons[x].k1d - rb + P.a);
+                }
+                GOut<T> ou{};
+                ou.C = blk(e);
+                ou.ldc = P.n[j];
+                ou.m = P.n[j];
+                ou.n = P.n[k];
+                ou.m0d = wdyn(j, true);
+                ou.m0s = 0;
+                ou.m1d = -1;
+                ou.n0d = wdyn(k, true);
+                ou.n0s = 0;
+                ou.cbeg = cb0;
+                ou.cend = ce0;
+                ou.tm = (ou.m + 63) / 64;
+                ou.tn = (ou.n + 63) / 64;
+                ou.tile0 = pt.tiles;
+                ou.alpha = T(-1);
+                ou.beta = T(1);
+                if (ou.tm > 0 && ou.tn > 0) {
+                  pt.tiles += (int64_t)ou.tm * ou.tn;
+                  pt.outs.push_back(ou);
+                }
               }
             }
-          }
-          std::vector<int32_t> beg(ent.size() + 1, 0);
-          for (size_t o = 0; o < ent.size(); ++o) beg[o + 1] = beg[o] + cnt[o];
-          const int cbase = (int)cons.size();
-          cons.resize(cons.size() + incs.size());
-          std::vector<int32_t> fillpos(beg.begin(), beg.end() - 1);
-          for (size_t q = 0; q < incs.size(); ++q) {
-            const int64_t e = incs[q];
-            const int i = inci[q];
-            GCon<T>& g = cons[cbase + fillpos[slot[e]]++];
-            g = GCon<T>{};
-            g.A = S.D.p + P.poff[incA[q]];
-            g.lda = P.n[incj[q]];
-            g.B = S.D.p + P.poff[incB[q]];
-            g.ldb = P.n[i];
-            g.k = P.n[i];
-            g.k0d = -1;
-            g.k0s = 0;
-            g.k1d = rb + i;
-            g.transA = 0;
-          }
-          if (I->F->keep_owners) {
-            // (c, j, k, m, contributors...) per target, targets ascending
-            std::vector<size_t> ord(ent.size());
-            std::iota(ord.begin(), ord.end(), 0);
-            std::sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return ent[x] < ent[y]; });
-            std::vector<int64_t> rec;
-            for (size_t o : ord) {
-              const int64_t e = ent[o];
-              const int j = (int)(std::upper_bound(P.pptr.begin(), P.pptr.end(), e) - P.pptr.begin()) - 1;
-              rec.push_back(c);
-              rec.push_back(j + P.a);
-              rec.push_back(P.pcol[e] + P.a);
-              rec.push_back(beg[o + 1] - beg[o]);
-              // contributors in the order their products are summed (ascending i)
-              for (int32_t q = beg[o]; q < beg[o + 1]; ++q)
-                rec.push_back(cons[cbase + q].k1d - rb + P.a);
+          };
+          const int nth = (int)std::max(1u, std::min(4u, std::thread::hardware_concurrency()));
+          const int nt = std::max(1, std::min(nth, (int)(rows.size() / 256)));
+          std::vector<Part> parts(nt);
+          std::vector<std::exception_ptr> errs(nt);
+          auto run = [&](int t) {
+            try {
+              plan_rows(rows.size() * t / nt, rows.size() * (t + 1) / nt, parts[t]);
+            } catch (...) {
+              errs[t] = std::current_exception();
             }
-            cp.owners.push_back({&P, std::move(rec)});
-          }
-          for (size_t o = 0; o < ent.size(); ++o) {
-            const int64_t e = ent[o];
-            slot[e] = -1;
-            const int j = (int)(std::upper_bound(P.pptr.begin(), P.pptr.end(), e) - P.pptr.begin()) - 1;
-            const int k = P.pcol[e];
-            GOut<T> ou{};
-            ou.C = blk(e);
-            ou.ldc = P.n[j];
-            ou.m = P.n[j];
-            ou.n = P.n[k];
-            ou.m0d = wdyn(j, true);
-            ou.m0s = 0;
-            ou.m1d = -1;
-            ou.n0d = wdyn(k, true);
-            ou.n0s = 0;
-            ou.cbeg = cbase + beg[o];
-            ou.cend = cbase + beg[o + 1];
-            ou.tm = (ou.m + 63) / 64;
-            ou.tn = (ou.n + 63) / 64;
-            ou.tile0 = gtiles;
-            ou.alpha = T(-1);
-            ou.beta = T(1);
-            if (ou.tm > 0 && ou.tn > 0) {
-              gtiles += (int64_t)ou.tm * ou.tn;
-              outs.push_back(ou);
+          };
+          std::vector<std::thread> th;
+          for (int t = 1; t < nt; ++t) th.emplace_back(run, t);
+          run(0);
+          for (auto& x : th) x.join();
+          for (auto& e : errs)
+            if (e) std::rethrow_exception(e);
+          std::vector<int64_t> rec;
+          for (auto& pt : parts) {
+            const int cbase = (int)cons.size();
+            for (auto o : pt.outs) {
+              o.cbeg += cbase;
+              o.cend += cbase;
+              o.tile0 += gtiles;
+              outs.push_back(o);
             }
+            gtiles += pt.tiles;
+            cons.insert(cons.end(), pt.cons.begin(), pt.cons.end());
+            rec.insert(rec.end(), pt.rec.begin(), pt.rec.end());
           }
+          if (keep) cp.owners.push_back({&P, std::move(rec)});
         }
       }
       return cp;
@@ -1113,46 +1143,75 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         if (PN->tr(t, e)) return (T*)nullptr;
         return (PN->isF[e] ? Fn : Dn) + PN->poff[e];
       };
-      for (int j = 0; j < Pc.nl; ++j) {
-        const int gj = Pc.a + j;
-        const int pt = H.parent[gj] - pa;
-        const int rj = Pc.r[j], ktj = Pc.n[j] - rj;
-        for (int64_t e = Pc.pptr[j]; e < Pc.pptr[j + 1]; ++e) {
-          const int k = Pc.pcol[e];
-          const int ps = H.parent[Pc.a + k] - pa;
-          const int rk = Pc.r[k], ktk = Pc.n[k] - rk;
-          int64_t ld = 0;
-          T* d = dest(pt, ps, true, ld);
-          if (!d) continue;
-          d += offc[j] + (int64_t)offc[k] * ld;
-          // near: copy; fill: accumulate (a far pair also receives its
-          // coupling); a fill entry (j, k) with k < j is read as the
-          // transpose of the stored (k, j)
-          if (Pc.tr(j, e)) {
-            const T* src = I->Fbuf.p + Pc.poff[e] + rk + (int64_t)rj * Pc.n[k];
-            cb.add(src, Pc.n[k], d, ld, ktj, ktk, 1, 1);
-          } else {
-            const T* src = (Pc.isF[e] ? I->Fbuf.p : Sc->D.p) + Pc.poff[e] + rj + (int64_t)rk * Pc.n[j];
-            cb.add(src, Pc.n[j], d, ld, ktj, ktk, Pc.isF[e] ? 1 : 0);
+      // copy tasks of rows [j0, j1) of the level into (cbl, cb2l); rows run
+      // on worker threads and their batches are appended in row order
+      auto close_rows = [&](int j0, int j1, CopyBatch<T>& cbl, CopyBatch<T>& cb2l) {
+        for (int j = j0; j < j1; ++j) {
+          const int gj = Pc.a + j;
+          const int pt = H.parent[gj] - pa;
+          const int rj = Pc.r[j], ktj = Pc.n[j] - rj;
+          for (int64_t e = Pc.pptr[j]; e < Pc.pptr[j + 1]; ++e) {
+            const int k = Pc.pcol[e];
+            const int ps = H.parent[Pc.a + k] - pa;
+            const int rk = Pc.r[k], ktk = Pc.n[k] - rk;
+            int64_t ld = 0;
+            T* d = dest(pt, ps, true, ld);
+            if (!d) continue;
+            d += offc[j] + (int64_t)offc[k] * ld;
+            // near: copy; fill: accumulate (a far pair also receives its
+            // coupling); a fill entry (j, k) with k < j is read as the
+            // transpose of the stored (k, j)
+            if (Pc.tr(j, e)) {
+              const T* src = I->Fbuf.p + Pc.poff[e] + rk + (int64_t)rj * Pc.n[k];
+              cbl.add(src, Pc.n[k], d, ld, ktj, ktk, 1, 1);
+            } else {
+              const T* src =
+                  (Pc.isF[e] ? I->Fbuf.p : Sc->D.p) + Pc.poff[e] + rj + (int64_t)rk * Pc.n[j];
+              cbl.add(src, Pc.n[j], d, ld, ktj, ktk, Pc.isF[e] ? 1 : 0);
+            }
+          }
+          // couplings of far pairs into the skeleton blocks: S~ = [S 0; 0 0]
+          for (int64_t e = H.far_ptr[gj]; e < H.far_ptr[gj + 1]; ++e) {
+            const int k = H.far_col[e] - Pc.a;
+            const int ps = H.parent[Pc.a + k] - pa;
+            int64_t ld = 0;
+            T* d = dest(pt, ps, true, ld);
+            if (!d) throw H2Error(H2_ERROR_FORMAT, "parents of a far pair are not a near pair");
+            d += offc[j] + (int64_t)offc[k] * ld;
+            cb2l.add(I->data + H.offS[e], H.rank[gj], d, ld, H.rank[gj], H.rank[Pc.a + k], 1);
+          }
+          // parent basis: rows of child j are [E_j; 0]
+          if (!is_top) {
+            const int tau = H.parent[gj];
+            const int kp = H.rank[tau];
+            const int t = tau - pa;
+            cb2l.add(I->data + H.offE[gj], H.rank[gj], Vnext.p + PN->offV[t] + offc[j],
+                     PN->n[t], H.rank[gj], kp, 0);
           }
         }
-        // couplings of far pairs into the skeleton blocks: S~ = [S 0; 0 0]
-        for (int64_t e = H.far_ptr[gj]; e < H.far_ptr[gj + 1]; ++e) {
-          const int k = H.far_col[e] - Pc.a;
-          const int ps = H.parent[Pc.a + k] - pa;
-          int64_t ld = 0;
-          T* d = dest(pt, ps, true, ld);
-          if (!d) throw H2Error(H2_ERROR_FORMAT, "parents of a far pair are not a near pair");
-          d += offc[j] + (int64_t)offc[k] * ld;
-          cb2.add(I->data + H.offS[e], H.rank[gj], d, ld, H.rank[gj], H.rank[Pc.a + k], 1);
-        }
-        // parent basis: rows of child j are [E_j; 0]
-        if (!is_top) {
-          const int tau = H.parent[gj];
-          const int kp = H.rank[tau];
-          const int t = tau - pa;
-          cb2.add(I->data + H.offE[gj], H.rank[gj], Vnext.p + PN->offV[t] + offc[j], PN->n[t],
-                  H.rank[gj], kp, 0);
+      };
+      {
+        const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        const int nt = std::max(1, std::min(nth, Pc.nl / 64));
+        std::vector<CopyBatch<T>> pc(nt), pc2(nt);
+        std::vector<std::thread> th;
+        std::vector<std::exception_ptr> errs(nt);
+        auto run = [&](int t) {
+          try {
+            close_rows((int)((int64_t)Pc.nl * t / nt), (int)((int64_t)Pc.nl * (t + 1) / nt), pc[t],
+                       pc2[t]);
+          } catch (...) {
+            errs[t] = std::current_exception();
+          }
+        };
+        for (int t = 1; t < nt; ++t) th.emplace_back(run, t);
+        run(0);
+        for (auto& x : th) x.join();
+        for (auto& e : errs)
+          if (e) std::rethrow_exception(e);
+        for (int t = 0; t < nt; ++t) {
+          cb.append(pc[t]);
+          cb2.append(pc2[t]);
         }
       }
       // hand over buffers: current F and V retire after the copies complete
