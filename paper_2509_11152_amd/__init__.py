@@ -134,7 +134,40 @@ def _load():
 lib = _load()
 
 
+# Handles that the garbage collector releases while the library is inside one
+# of its allocator callbacks (a collection can run in the callback's Python
+# code) are destroyed once the library call has returned, never from inside
+# it: the library is not re-entrant.
+# A context released by the collector is destroyed at the next library call,
+# after any matrix or factor that the same collection released (they must go
+# first).
+_in_callback = [0]
+_deferred = []  # (order, destroy function, handle): factors, matrices, contexts
+
+
+def _release(order, fn, ptr, keep=None):
+    """keep: objects the destroy call needs alive (a context's allocator
+    callbacks)."""
+    if _in_callback[0] or order == 2:
+        _deferred.append((order, fn, ptr, keep))
+    else:
+        fn(ptr)
+
+
+def _flush_deferred():
+    if not _deferred or _in_callback[0]:
+        return
+    items = sorted(_deferred, key=lambda x: x[0])
+    _deferred.clear()
+    for _, fn, ptr, _keep in items:
+        try:
+            fn(ptr)
+        except Exception:
+            pass
+
+
 def _check(code, ctx=None):
+    _flush_deferred()
     if code != 0:
         msg = lib.h2_last_error(ctx.ptr).decode() if ctx is not None else ""
         raise H2Error(code, msg)
@@ -169,16 +202,22 @@ class Context:
         opts.stream = stream.cuda_stream if stream is not None else None
         if allocator == "torch":
             def _alloc(nbytes, strm, user):
+                _in_callback[0] += 1
                 try:
                     return torch.cuda.caching_allocator_alloc(int(nbytes), device, int(strm or 0))
                 except Exception:
                     return None
+                finally:
+                    _in_callback[0] -= 1
 
             def _free(ptr, nbytes, strm, user):
+                _in_callback[0] += 1
                 try:
                     torch.cuda.caching_allocator_delete(int(ptr))
                 except Exception:
                     pass
+                finally:
+                    _in_callback[0] -= 1
 
             self._cbs = (_ALLOC_FN(_alloc), _FREE_FN(_free))
             opts.alloc, opts.free = self._cbs
@@ -192,7 +231,7 @@ class Context:
 
     def close(self):
         if self.ptr:
-            lib.h2_context_destroy(self.ptr)
+            _release(2, lib.h2_context_destroy, self.ptr, self._cbs)
             self.ptr = _P()
 
     def __del__(self):
@@ -245,7 +284,7 @@ class Matrix:
     def __del__(self):
         try:
             if self.ptr:
-                lib.h2_matrix_destroy(self.ptr)
+                _release(1, lib.h2_matrix_destroy, self.ptr)
                 self.ptr = _P()
         except Exception:
             pass
@@ -320,7 +359,7 @@ class Factor:
     def __del__(self):
         try:
             if self.ptr:
-                lib.h2_factor_destroy(self.ptr)
+                _release(0, lib.h2_factor_destroy, self.ptr)
                 self.ptr = _P()
         except Exception:
             pass

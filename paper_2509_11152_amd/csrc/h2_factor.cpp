@@ -403,9 +403,6 @@ template <class T> struct ColourPlan {
   int64_t nsl = 0, nsr = 0;
   std::vector<LUTask<T>> lus;
   std::vector<TrsmTask<T>> trs;
-  std::vector<GOut<T>> outs;
-  std::vector<GCon<T>> cons;
-  int64_t gtiles = 0;
   // Schur target lists of the colour per level plan (kept on request)
   std::vector<std::pair<LevelPlan*, std::vector<int64_t>>> owners;
 };
@@ -501,6 +498,42 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     DevArray<int32_t> rdev;
     rdev.alloc(total, calltr);
     launch_fill<int32_t>(rdev.p, total, 0, s);
+    // each instance's block pattern on the device, for the Schur and fill-in
+    // updates that are enumerated there (staged through the arena, which is
+    // reset only after the level's last launch has completed)
+    std::vector<SchurLevel<T>> lvh(act.size());
+    int64_t schur_rows = 0, schur_nnz = 0;
+    for (size_t q = 0; q < act.size(); ++q) {
+      Inst<T>* I = act[q];
+      LevelPlan& P = I->F->plans[I->li];
+      std::vector<int8_t> kind(P.pcol.size());
+      for (int j = 0; j < P.nl; ++j)
+        for (int64_t e = P.pptr[j]; e < P.pptr[j + 1]; ++e)
+          kind[e] = P.isF[e] ? (P.tr(j, e) ? 2 : 1) : 0;
+      SchurLevel<T>& L = lvh[q];
+      L.pptr = ar.put(P.pptr);
+      L.pcol = ar.put(P.pcol);
+      L.poff = ar.put(P.poff);
+      L.kind = ar.put(kind);
+      L.color = ar.put(P.color);
+      L.n = ar.put(P.n);
+      L.r = rdev.p + I->rbase;
+      L.D = store_of<T>(I->F, I->li).D.p;
+      L.F = I->Fbuf.p;
+      L.nl = P.nl;
+      L.rows0 = schur_rows;
+      schur_rows += P.nl;
+      schur_nnz += (int64_t)P.pcol.size();
+    }
+    const SchurLevel<T>* lvdev = ar.put(lvh);
+    // the device's Schur target lists: every row's contributors of the colour
+    // being processed, and at most one target per pattern entry
+    DevArray<SchurRow> schur_rowtab;
+    DevArray<SchurTarget> schur_targets;
+    DevArray<int64_t> schur_count;
+    schur_rowtab.alloc(std::max<int64_t>(schur_rows, 1), calltr);
+    schur_targets.alloc(std::max<int64_t>(schur_nnz, 1), calltr);
+    schur_count.alloc(1, calltr);
     int maxn_all = 1;
     for (auto* I : act)
       for (int x : I->F->plans[I->li].n) maxn_all = std::max(maxn_all, x);
@@ -564,9 +597,6 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       int64_t& nsr = cp.nsr;
       auto& lus = cp.lus;
       auto& trs = cp.trs;
-      auto& outs = cp.outs;
-      auto& cons = cp.cons;
-      int64_t& gtiles = cp.gtiles;
       int64_t woff = 0, goff = 0;
       for (auto* I : act) {
         LevelPlan& P = I->F->plans[I->li];
@@ -753,136 +783,44 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
             trs.push_back(tt);
           }
         }
-        // ---- Schur complement / fill-in targets, owner-computes ----
-        // target (j, k) collects every i of the colour with j, k in N(i), i.e.
-        // the colour's clusters i in N(j) whose near list holds k; targets in
-        // ascending (j, k), contributors in ascending i.  Rows j are planned
-        // on worker threads and appended in row order.
-        {
-          std::vector<int> rows;  // rows touched by the colour
-          {
-            std::vector<char> mark(P.nl, 0);
-            for (int i : P.members[c])
-              for (int j : P.nb[i]) mark[j] = 1;
-            for (int j = 0; j < P.nl; ++j)
-              if (mark[j]) rows.push_back(j);
-          }
-          struct Part {
-            std::vector<GOut<T>> outs;
-            std::vector<GCon<T>> cons;
-            std::vector<int64_t> rec;
-            int64_t tiles = 0;
-          };
-          const bool keep = I->F->keep_owners;
-          auto plan_rows = [&](size_t r0, size_t r1, Part& pt) {
-            std::vector<int> stamp(P.nl, -1), conts, tk;
-            std::vector<int64_t> econt;  // entry (j, i) of each contributor
-            for (size_t q = r0; q < r1; ++q) {
-              const int j = rows[q];
-              conts.clear();
-              econt.clear();
-              tk.clear();
-              for (int i : P.nb[j])
-                if (P.color[i] == c) {
-                  conts.push_back(i);
-                  econt.push_back(P.find(j, i));
-                }
-              for (int i : conts)
-                for (int k : P.nb[i])
-                  if (stamp[k] != j) {
-                    stamp[k] = j;
-                    tk.push_back(k);
-                  }
-              std::sort(tk.begin(), tk.end());
-              int64_t e = P.pptr[j];
-              const int64_t e1 = P.pptr[j + 1];
-              for (int k : tk) {
-                while (e < e1 && P.pcol[e] < k) ++e;
-                if (e == e1 || P.pcol[e] != k)
-                  throw H2Error(H2_ERROR_FORMAT, "fill pattern misses a Schur target");
-                // fill (j, k) with k < j is the transpose of the stored (k, j),
-                // which receives the transposed update
-                if (P.tr(j, e)) continue;
-                const int cb0 = (int)pt.cons.size();
-                for (size_t x = 0; x < conts.size(); ++x) {
-                  const int i = conts[x];
-                  const int64_t eik = P.find(i, k);
-                  if (eik < 0 || P.isF[eik]) continue;  // k not near i
-                  GCon<T> g{};
-                  g.A = S.D.p + P.poff[econt[x]];
-                  g.lda = P.n[j];
-                  g.B = S.D.p + P.poff[eik];
-                  g.ldb = P.n[i];
-                  g.k = P.n[i];
-                  g.k0d = -1;
-                  g.k0s = 0;
-                  g.k1d = rb + i;
-                  g.transA = 0;
-                  pt.cons.push_back(g);
-                }
-                const int ce0 = (int)pt.cons.size();
-                if (keep) {
-                  pt.rec.push_back(c);
-                  pt.rec.push_back(j + P.a);
-                  pt.rec.push_back(k + P.a);
-                  pt.rec.push_back(ce0 - cb0);
-                  for (int x = cb0; x < ce0; ++x) pt.rec.push_back(pt.cons[x].k1d - rb + P.a);
-                }
-                GOut<T> ou{};
-                ou.C = blk(e);
-                ou.ldc = P.n[j];
-                ou.m = P.n[j];
-                ou.n = P.n[k];
-                ou.m0d = wdyn(j, true);
-                ou.m0s = 0;
-                ou.m1d = -1;
-                ou.n0d = wdyn(k, true);
-                ou.n0s = 0;
-                ou.cbeg = cb0;
-                ou.cend = ce0;
-                ou.tm = (ou.m + 63) / 64;
-                ou.tn = (ou.n + 63) / 64;
-                ou.tile0 = pt.tiles;
-                ou.alpha = T(-1);
-                ou.beta = T(1);
-                if (ou.tm > 0 && ou.tn > 0) {
-                  pt.tiles += (int64_t)ou.tm * ou.tn;
-                  pt.outs.push_back(ou);
-                }
-              }
-            }
-          };
-          const int nth = (int)std::max(1u, std::min(4u, std::thread::hardware_concurrency()));
-          const int nt = std::max(1, std::min(nth, (int)(rows.size() / 256)));
-          std::vector<Part> parts(nt);
-          std::vector<std::exception_ptr> errs(nt);
-          auto run = [&](int t) {
-            try {
-              plan_rows(rows.size() * t / nt, rows.size() * (t + 1) / nt, parts[t]);
-            } catch (...) {
-              errs[t] = std::current_exception();
-            }
-          };
-          std::vector<std::thread> th;
-          for (int t = 1; t < nt; ++t) th.emplace_back(run, t);
-          run(0);
-          for (auto& x : th) x.join();
-          for (auto& e : errs)
-            if (e) std::rethrow_exception(e);
+        // ---- Schur complement / fill-in targets ----
+        // enumerated on the device (launch_schur); the owner lists are formed
+        // here only when they are exported: target (j, k) collects every i of
+        // the colour with j, k in N(i), i.e. the colour's clusters i in N(j)
+        // whose near list holds k; targets in ascending (j, k) (fill entries
+        // when stored, j < k), contributors in ascending i
+        if (I->F->keep_owners) {
           std::vector<int64_t> rec;
-          for (auto& pt : parts) {
-            const int cbase = (int)cons.size();
-            for (auto o : pt.outs) {
-              o.cbeg += cbase;
-              o.cend += cbase;
-              o.tile0 += gtiles;
-              outs.push_back(o);
+          std::vector<int> stamp(P.nl, -1), conts, tk;
+          for (int j = 0; j < P.nl; ++j) {
+            conts.clear();
+            tk.clear();
+            for (int i : P.nb[j])
+              if (P.color[i] == c) conts.push_back(i);
+            for (int i : conts)
+              for (int k : P.nb[i])
+                if (stamp[k] != j) {
+                  stamp[k] = j;
+                  tk.push_back(k);
+                }
+            std::sort(tk.begin(), tk.end());
+            for (int k : tk) {
+              const int64_t e = P.find(j, k);
+              if (e < 0) throw H2Error(H2_ERROR_FORMAT, "fill pattern misses a Schur target");
+              if (P.tr(j, e)) continue;
+              const size_t at = rec.size();
+              rec.push_back(c);
+              rec.push_back(j + P.a);
+              rec.push_back(k + P.a);
+              rec.push_back(0);
+              for (int i : conts) {
+                const int64_t eik = P.find(i, k);
+                if (eik >= 0 && !P.isF[eik]) rec.push_back(i + P.a);
+              }
+              rec[at + 3] = (int64_t)(rec.size() - at - 4);
             }
-            gtiles += pt.tiles;
-            cons.insert(cons.end(), pt.cons.begin(), pt.cons.end());
-            rec.insert(rec.end(), pt.rec.begin(), pt.rec.end());
           }
-          if (keep) cp.owners.push_back({&P, std::move(rec)});
+          cp.owners.push_back({&P, std::move(rec)});
         }
       }
       return cp;
@@ -910,9 +848,6 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       const int64_t nsl = cp.nsl, nsr = cp.nsr;
       auto& lus = cp.lus;
       auto& trs = cp.trs;
-      auto& outs = cp.outs;
-      auto& cons = cp.cons;
-      const int64_t gtiles = cp.gtiles;
       for (auto& ow : cp.owners)
         ow.first->owners.insert(ow.first->owners.end(), ow.second.begin(), ow.second.end());
       if (aug.empty()) continue;
@@ -973,13 +908,9 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         close_mark(m4);
       }
       {
-        // one workgroup per target block unless some block spans many tiles
-        int32_t maxt = 0;
-        for (const auto& o : outs) maxt = std::max(maxt, o.tm * o.tn);
-        const GOut<T>* dout = ar.put(outs);
-        const GCon<T>* dcon = ar.put(cons);
         auto m5 = mark(5);
-        launch_gemm<T>(dout, (int)outs.size(), dcon, dyn, gtiles, maxt <= 16 ? 2 : 0, s);
+        launch_schur<T>(lvdev, (int)act.size(), schur_rows, c, schur_rowtab.p, schur_targets.p,
+                        schur_count.p, ctx->d_err.p, s);
         close_mark(m5);
       }
       H2_HIP(hipGetLastError());  // a rejected launch configuration
@@ -993,6 +924,10 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       H2_HIP(hipMemcpy(&herr, ctx->d_err.p, sizeof(int), hipMemcpyDeviceToHost));
       if (herr & 1) throw H2Error(H2_ERROR_SINGULAR, "zero pivot in a redundant block");
       if (herr & 2) throw H2Error(H2_ERROR_NUMERIC, "non-finite singular value in augmentation");
+      if (herr & 4)
+        throw H2Error(H2_ERROR_UNSUPPORTED, "a block row has more than " +
+                                                std::to_string(kSchurMaxContrib) +
+                                                " Schur contributors of one colour");
     }
     {
       for (auto& m : marks) {

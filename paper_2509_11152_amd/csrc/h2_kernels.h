@@ -87,6 +87,44 @@ template <class T> struct RTask {
                         // (upper triangular in the layout of `out`)
 };
 
+// Block pattern of one level of one instance, resident on the device for the
+// Schur and fill-in updates (Algorithm 2, partial LU): the level's pattern
+// CSR (near and fill entries, rows and columns ascending), each entry's
+// element offset in the near (D) or fill (F) buffer and its kind (0 near,
+// 1 stored fill block, 2 fill entry stored as the transpose of its mirror),
+// and the clusters' colours and orders.  rows0: first global row of the
+// instance in a launch over several instances.
+template <class T> struct SchurLevel {
+  const int64_t* pptr;
+  const int32_t* pcol;
+  const int64_t* poff;
+  const int8_t* kind;
+  const int32_t* color;
+  const int32_t* n;
+  const int32_t* r;     // the level's r array (this instance's clusters)
+  T* D;
+  T* F;
+  int32_t nl;
+  int32_t pad0;
+  int64_t rows0;
+};
+constexpr int kSchurMaxContrib = 32;
+// one Schur / fill-in target found on the device: global row g (instance row
+// offset + j), pattern entry e = (j, k), contributors (bit x: the x-th
+// contributor of row g)
+struct SchurTarget {
+  int64_t e;
+  int32_t g;
+  uint32_t mask;
+};
+// contributors of one row for the colour being processed: cluster ids and
+// their entries (j, i)
+struct SchurRow {
+  int32_t nc;
+  int32_t ci[kSchurMaxContrib];
+  int64_t eji[kSchurMaxContrib];
+};
+
 // Basis augmentation + complement of one cluster (Algorithm 2, first loop),
 // given the R factor of the cluster's fill row.
 template <class T> struct AugTask {
@@ -183,21 +221,36 @@ inline int rf_group_rows(int) { return 256; }
 inline int64_t aug_work_elems(int n) { return 5 * (int64_t)n * n + 3 * (int64_t)n + 64; }
 
 // ---- launchers (stream-ordered; descriptor arrays are device pointers) ----
-// shape 0: 64 x 64 tiles; shape 1: 64 x 16 tiles (at most 16 columns), where
-// outputs with nsplit > 1 leave their chunks' partial tiles in `parts`
-// (64 x 16 each) for launch_gemm_reduce; shape 2: 64 x 64 tiles, one
-// workgroup per output (for outputs of a few tiles)
+// shape 0: 64 x 64 tiles; shape 1: 64 x 16 tiles and shape 3: 64 x 32 tiles
+// (outputs of few columns), where outputs with nsplit > 1 leave their chunks'
+// partial tiles in `parts` (64 x 16 or 64 x 32 each, column-major) for
+// launch_gemm_reduce; shape 2: 64 x 64 tiles, one workgroup per output (for
+// outputs of a few tiles)
 template <class T>
 void launch_gemm(const GOut<T>* outs, int nouts, const GCon<T>* cons, const int32_t* dyn,
                  int64_t ntiles, int shape, hipStream_t s, T* parts = nullptr);
 // C = beta C + alpha (sum of the chunks' partial tiles, in chunk order) for the
-// split outputs `routs` (tiles numbered by rtile0)
+// split outputs `routs` (tiles numbered by rtile0) of a shape 1 or 3 product
 template <class T>
 void launch_gemm_reduce(const GOut<T>* routs, int nouts, const T* parts, int64_t ntiles,
-                        hipStream_t s);
+                        int shape, hipStream_t s);
 template <class T>
 void launch_strip(const STask<T>* tasks, int ntasks, const int32_t* dyn, int64_t nstrips,
                   int maxn, hipStream_t s);
+// Schur and fill-in updates of colour c over every instance's level, found on
+// the device: the targets are the entries (j, k) of row j's pattern whose
+// block some cluster i of colour c updates (i near j and k; fill entries
+// only when stored, j < k), and each is formed as
+// C[active rows, active cols] -= sum over those i, ascending, of
+// D_{j, R_i} (D_RR^{-1} D_{R_i, k}).  Fails (err bit 4) when a row has more
+// than kSchurMaxContrib contributors.
+// Two launches: the first finds every row's contributors (rows[g]) and the
+// targets (appended to `targets`, their number counted in *count, which the
+// call clears first; `cap` entries at most, at least the levels' pattern
+// entries); the second forms the targets' updates, one workgroup each.
+template <class T>
+void launch_schur(const SchurLevel<T>* lv, int ninst, int64_t rows, int c, SchurRow* rowtab,
+                  SchurTarget* targets, int64_t* count, int* err, hipStream_t s);
 // `lds`: LDS bytes per workgroup the path choices of the fill-row QR, the
 // augmentation, the LU and the multipliers may assume (at most kLdsBytes);
 // working sets beyond it take the global-memory variants

@@ -163,19 +163,21 @@ __global__ __launch_bounds__(256) void k_gemm(const GOut<T>* __restrict__ outs, 
   }
 }
 
-// Skinny variant for outputs of at most 16 columns (the solves' right-hand
-// sides): the 64 x 16 tile is computed by all four waves, each taking every
-// fourth k-step with four row fragments in flight, and the waves' partial
+// Skinny variant for outputs of few columns (the solves' right-hand sides):
+// a 64 x TN tile (TN = 16 FN) is computed by all four waves, each taking
+// every fourth k-step with four row fragments and FN column fragments in
+// flight, so every operand element is read once per tile; the waves' partial
 // tiles are summed through LDS.  An output with nsplit > 1 has its
 // contributor list cut into nsplit chunks, one workgroup each; their partial
-// tiles go to `parts` and k_gemm_reduce adds them in chunk order.
-template <class T>
+// tiles (column-major 64 x TN) go to `parts` and k_gemm_reduce adds them in
+// chunk order.
+template <class T, int FN>
 __global__ __launch_bounds__(256) void k_gemm_skinny(const GOut<T>* __restrict__ outs, int nouts,
                                                      const GCon<T>* __restrict__ cons,
                                                      const int32_t* __restrict__ dyn,
                                                      T* __restrict__ parts) {
-  constexpr int TM = 64, TN = 16;
-  __shared__ T part[4][TM * TN];
+  constexpr int TM = 64, TN = 16 * FN;
+  __shared__ T part[2][TM * TN];
   const int64_t tile = blockIdx.x;
   int lo = 0, hi = nouts - 1;
   while (lo < hi) {
@@ -196,11 +198,11 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(const GOut<T>* __restrict__
   if (ns == 1 && (r0 >= m1 || c0 >= n1)) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, kq = lane >> 4;
-  typename Acc<T>::type acc[4];
+  typename Acc<T>::type acc[4][FN];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) acc[a] = (typename Acc<T>::type){0, 0, 0, 0};
-  const int col = c0 + l16;
-  const bool cok = col < n1;
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = (typename Acc<T>::type){0, 0, 0, 0};
   const int ncon = o.cend - o.cbeg;
   const int cps = (ncon + ns - 1) / ns;
   const int cb = o.cbeg + sidx * cps;
@@ -212,7 +214,12 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(const GOut<T>* __restrict__
     for (int kk = k0 + 4 * wave; kk < k1; kk += 16) {
       const int kx = kk + kq;
       const bool kok = kx < k1;
-      const T bv = (kok && cok) ? g.B[kx + (int64_t)col * g.ldb] : T(0);
+      T bv[FN];
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        const int col = c0 + b * 16 + l16;
+        bv[b] = (kok && col < n1) ? g.B[kx + (int64_t)col * g.ldb] : T(0);
+      }
       T av[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
@@ -222,36 +229,64 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(const GOut<T>* __restrict__
                     : T(0);
       }
 #pragma unroll
-      for (int a = 0; a < 4; ++a) acc[a] = mfma16(av[a], bv, acc[a]);
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
     }
   }
+  // sum the four waves' tiles: waves 2 and 3 hand theirs to waves 0 and 1,
+  // wave 1 to wave 0, which leaves the total in part[1] (column-major)
+  auto put = [&](T* dst) {
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) part[wave][(a * 16 + acc_row<T>(kq, i)) * TN + l16] = acc[a][i];
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          dst[(a * 16 + acc_row<T>(kq, i)) + (b * 16 + l16) * TM] = acc[a][b][i];
+  };
+  auto take = [&](const T* src) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc[a][b][i] += src[(a * 16 + acc_row<T>(kq, i)) + (b * 16 + l16) * TM];
+  };
+  if (wave >= 2) put(part[wave - 2]);
   __syncthreads();
+  if (wave < 2) take(part[wave]);
+  __syncthreads();
+  if (wave == 1) put(part[0]);
+  __syncthreads();
+  if (wave == 0) {
+    take(part[0]);
+    put(part[1]);
+  }
+  __syncthreads();
+  const T* sum = part[1];
   if (ns > 1) {
     T* dst = parts + (o.part0 + tt * ns + sidx) * (int64_t)(TM * TN);
-    for (int e = threadIdx.x; e < TM * TN; e += blockDim.x)
-      dst[e] = part[0][e] + part[1][e] + part[2][e] + part[3][e];
+    for (int e = threadIdx.x; e < TM * TN; e += blockDim.x) dst[e] = sum[e];
     return;
   }
   const T alpha = o.alpha, beta = o.beta;
   for (int e = threadIdx.x; e < TM * TN; e += blockDim.x) {
-    const int rr = e / TN, cc = e % TN;
+    const int rr = e % TM, cc = e / TM;
     const int row = r0 + rr, cl = c0 + cc;
     if (row < m1 && cl < n1) {
-      const T v = alpha * (part[0][e] + part[1][e] + part[2][e] + part[3][e]);
+      const T v = alpha * sum[e];
       T* p = o.C + row + (int64_t)cl * o.ldc;
       *p = beta == T(0) ? v : beta * *p + v;
     }
   }
 }
 
-template <class T>
+template <class T, int TN>
 __global__ __launch_bounds__(256) void k_gemm_reduce(const GOut<T>* __restrict__ outs, int nouts,
                                                      const T* __restrict__ parts) {
-  constexpr int TM = 64, TN = 16;
+  constexpr int TM = 64;
   const int64_t tile = blockIdx.x;
   int lo = 0, hi = nouts - 1;
   while (lo < hi) {
@@ -266,7 +301,7 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(const GOut<T>* __restrict__
   const T* src = parts + (o.part0 + tt * ns) * (int64_t)(TM * TN);
   const T alpha = o.alpha, beta = o.beta;
   for (int e = threadIdx.x; e < TM * TN; e += blockDim.x) {
-    const int row = r0 + e / TN, cl = c0 + e % TN;
+    const int row = r0 + e % TM, cl = c0 + e / TM;
     if (row < o.m && cl < o.n) {
       T sum = 0;
       for (int q = 0; q < ns; ++q) sum += src[(int64_t)q * (TM * TN) + e];
@@ -371,6 +406,224 @@ __global__ __launch_bounds__(256) void k_gemm_out(const GOut<T>* __restrict__ ou
   }
 }
 
+// ---------------------------------------------------------------------------
+// Schur and fill-in updates enumerated on the device (launch_schur).
+// ---------------------------------------------------------------------------
+template <class T> __global__ void k_fill(T* p, int64_t n, T v);
+
+// instance of global row g (rows0 ascending)
+template <class T> __device__ inline int schur_inst(const SchurLevel<T>* lvs, int ninst, int64_t g) {
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (lvs[mid].rows0 <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// entry (i, k) of row i of the pattern when it is a near entry, else -1
+template <class T> __device__ inline int64_t schur_near_entry(const SchurLevel<T>& L, int i, int k) {
+  int64_t a = L.pptr[i], b = L.pptr[i + 1];
+  const int64_t end = b;
+  while (a < b) {
+    const int64_t m = (a + b) >> 1;
+    if (L.pcol[m] < k) a = m + 1; else b = m;
+  }
+  return (a < end && L.pcol[a] == k && L.kind[a] == 0) ? a : -1;
+}
+
+// workgroup = row g: its contributors (near entries of colour c, in column
+// order) to rowtab[g], then its targets, in entry order, appended to the list
+template <class T>
+__global__ __launch_bounds__(256) void k_schur_enum(const SchurLevel<T>* __restrict__ lvs,
+                                                    int ninst, int c, SchurRow* rowtab,
+                                                    SchurTarget* targets, int64_t* count,
+                                                    int* err) {
+  __shared__ int ci[kSchurMaxContrib];
+  __shared__ int64_t eji[kSchurMaxContrib];
+  __shared__ int wcnt[4];
+  __shared__ int sh_nc;
+  __shared__ int64_t sh_base;
+  const int64_t g = blockIdx.x;
+  const SchurLevel<T>& L = lvs[schur_inst(lvs, ninst, g)];
+  const int j = (int)(g - L.rows0);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t e0 = L.pptr[j], e1 = L.pptr[j + 1];
+  if (tid == 0) sh_nc = 0;
+  __syncthreads();
+  // contributors, compacted in entry order
+  for (int64_t base = e0; base < e1; base += 256) {
+    const int64_t e = base + tid;
+    const bool f = e < e1 && L.kind[e] == 0 && L.color[L.pcol[e]] == c;
+    const unsigned long long bal = __ballot(f);
+    if (lane == 0) wcnt[wave] = __popcll(bal);
+    __syncthreads();
+    int off = sh_nc;
+    for (int w = 0; w < wave; ++w) off += wcnt[w];
+    off += __popcll(bal & ((1ull << lane) - 1ull));
+    if (f) {
+      if (off < kSchurMaxContrib) {
+        ci[off] = L.pcol[e];
+        eji[off] = e;
+      } else {
+        atomicOr(err, 4);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) sh_nc = min(kSchurMaxContrib, sh_nc + wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3]);
+    __syncthreads();
+  }
+  const int nc = sh_nc;
+  if (tid == 0) rowtab[g].nc = nc;
+  if (tid < nc) {
+    rowtab[g].ci[tid] = ci[tid];
+    rowtab[g].eji[tid] = eji[tid];
+  }
+  if (nc == 0) return;
+  // targets: entries whose column some contributor is near (fill entries only
+  // when stored)
+  for (int64_t base = e0; base < e1; base += 256) {
+    const int64_t e = base + tid;
+    uint32_t mask = 0;
+    if (e < e1 && L.kind[e] != 2) {
+      const int k = L.pcol[e];
+      for (int x = 0; x < nc; ++x)
+        if (schur_near_entry(L, ci[x], k) >= 0) mask |= 1u << x;
+    }
+    const unsigned long long bal = __ballot(mask != 0);
+    if (lane == 0) wcnt[wave] = __popcll(bal);
+    __syncthreads();
+    if (tid == 0)
+      sh_base = (int64_t)atomicAdd((unsigned long long*)count,
+                                   (unsigned long long)(wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3]));
+    __syncthreads();
+    int off = 0;
+    for (int w = 0; w < wave; ++w) off += wcnt[w];
+    off += __popcll(bal & ((1ull << lane) - 1ull));
+    if (mask) {
+      SchurTarget t;
+      t.e = e;
+      t.g = (int32_t)g;
+      t.mask = mask;
+      targets[sh_base + off] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// workgroups loop over the targets: C -= sum of the contributors' products,
+// contributors ascending (bit order)
+template <class T>
+__global__ __launch_bounds__(256) void k_schur_apply(const SchurLevel<T>* __restrict__ lvs,
+                                                     int ninst, int c,
+                                                     const SchurRow* __restrict__ rowtab,
+                                                     const SchurTarget* __restrict__ targets,
+                                                     const int64_t* __restrict__ count) {
+  constexpr int FM = 2, FN = 2;
+  __shared__ int64_t eik[kSchurMaxContrib];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int64_t ntarg = *count;
+  for (int64_t t0 = blockIdx.x; t0 < ntarg; t0 += gridDim.x) {
+    const SchurTarget tg = targets[t0];
+    const SchurLevel<T>& L = lvs[schur_inst(lvs, ninst, tg.g)];
+    const SchurRow& R = rowtab[tg.g];
+    const int j = (int)(tg.g - L.rows0);
+    const int k = L.pcol[tg.e];
+    const int nc = R.nc;
+    if (tid < nc) eik[tid] = ((tg.mask >> tid) & 1u) ? schur_near_entry(L, R.ci[tid], k) : -1;
+    __syncthreads();
+    const int nj = L.n[j], nk = L.n[k];
+    const int m0 = L.color[j] <= c ? L.r[j] : 0;
+    const int n0 = L.color[k] <= c ? L.r[k] : 0;
+    const gptr<const T> Dg = gmem((const T*)L.D);
+    const gptr<T> C = gmem((L.kind[tg.e] == 1 ? L.F : L.D) + L.poff[tg.e]);
+    const int64_t ldc = nj;
+    const int tm = (nj + 63) / 64, tn = (nk + 63) / 64;
+    for (int t = 0; t < tm * tn; ++t) {
+      const int r0 = m0 + (t % tm) * 64, c0 = n0 + (t / tm) * 64;
+      if (r0 >= nj || c0 >= nk) continue;
+      const int wr = r0 + (wave & 1) * 32, wc = c0 + (wave >> 1) * 32;
+      T cv[FM][FN][4];
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = wr + a * 16 + l16, col = wc + b * 16 + acc_row<T>(kq, i);
+            cv[a][b][i] = (row < nj && col < nk) ? C[row + (int64_t)col * ldc] : T(0);
+          }
+      typename Acc<T>::type acc[FM][FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = (typename Acc<T>::type){0, 0, 0, 0};
+      for (int x = 0; x < nc; ++x) {
+        const int64_t eb = eik[x];
+        if (eb < 0) continue;
+        const int i = R.ci[x];
+        const int ni = L.n[i];
+        const int k1 = L.r[i];
+        const gptr<const T> A = Dg + L.poff[R.eji[x]];  // D(j, i), n_j x n_i
+        const gptr<const T> B = Dg + L.poff[eb];        // D(i, k), n_i x n_k
+        for (int kb = 0; kb < k1; kb += 4 * kGemmKB) {
+          T av[kGemmKB][FM], bv[kGemmKB][FN];
+#pragma unroll
+          for (int qq = 0; qq < kGemmKB; ++qq) {
+            const int kx = kb + 4 * qq + kq;
+            const bool kok = kx < k1;
+#pragma unroll
+            for (int a = 0; a < FM; ++a) {
+              const int row = wr + a * 16 + l16;
+              av[qq][a] = (kok && row < nj) ? A[row + (int64_t)kx * nj] : T(0);
+            }
+#pragma unroll
+            for (int b = 0; b < FN; ++b) {
+              const int col = wc + b * 16 + l16;
+              bv[qq][b] = (kok && col < nk) ? B[kx + (int64_t)col * ni] : T(0);
+            }
+          }
+#pragma unroll
+          for (int qq = 0; qq < kGemmKB; ++qq) {
+            if (kb + 4 * qq >= k1) break;
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+              for (int b = 0; b < FN; ++b) acc[a][b] = mfma16(bv[qq][b], av[qq][a], acc[a][b]);
+          }
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < FM; ++a) {
+        const int row = wr + a * 16 + l16;
+        if (row >= nj) continue;
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int col = wc + b * 16 + acc_row<T>(kq, i);
+            if (col < nk) C[row + (int64_t)col * ldc] = cv[a][b][i] - acc[a][b][i];
+          }
+      }
+    }
+    __syncthreads();  // eik is rewritten for the next target
+  }
+}
+
+template <class T>
+void launch_schur(const SchurLevel<T>* lv, int ninst, int64_t rows, int c, SchurRow* rowtab,
+                  SchurTarget* targets, int64_t* count, int* err, hipStream_t s) {
+  if (rows <= 0 || ninst <= 0) return;
+  hipLaunchKernelGGL(k_fill<int64_t>, dim3(1), dim3(64), 0, s, count, (int64_t)1, (int64_t)0);
+  hipLaunchKernelGGL(k_schur_enum<T>, dim3((unsigned)rows), dim3(256), 0, s, lv, ninst, c, rowtab,
+                     targets, count, err);
+  // workgroups loop over however many targets the first launch found
+  hipLaunchKernelGGL(k_schur_apply<T>, dim3(8192), dim3(256), 0, s, lv, ninst, c, rowtab, targets,
+                     count);
+}
+
 template <class T>
 void launch_gemm(const GOut<T>* outs, int nouts, const GCon<T>* cons, const int32_t* dyn,
                  int64_t ntiles, int shape, hipStream_t s, T* parts) {
@@ -380,17 +633,24 @@ void launch_gemm(const GOut<T>* outs, int nouts, const GCon<T>* cons, const int3
                        nouts, cons, dyn);
   else if (shape == 2)
     hipLaunchKernelGGL((k_gemm_out<T>), dim3((unsigned)nouts), dim3(256), 0, s, outs, cons, dyn);
+  else if (shape == 3)
+    hipLaunchKernelGGL((k_gemm_skinny<T, 2>), dim3((unsigned)ntiles), dim3(256), 0, s, outs,
+                       nouts, cons, dyn, parts);
   else
-    hipLaunchKernelGGL((k_gemm_skinny<T>), dim3((unsigned)ntiles), dim3(256), 0, s, outs, nouts,
-                       cons, dyn, parts);
+    hipLaunchKernelGGL((k_gemm_skinny<T, 1>), dim3((unsigned)ntiles), dim3(256), 0, s, outs,
+                       nouts, cons, dyn, parts);
 }
 
 template <class T>
 void launch_gemm_reduce(const GOut<T>* routs, int nouts, const T* parts, int64_t ntiles,
-                        hipStream_t s) {
+                        int shape, hipStream_t s) {
   if (ntiles <= 0 || nouts <= 0) return;
-  hipLaunchKernelGGL((k_gemm_reduce<T>), dim3((unsigned)ntiles), dim3(256), 0, s, routs, nouts,
-                     parts);
+  if (shape == 3)
+    hipLaunchKernelGGL((k_gemm_reduce<T, 32>), dim3((unsigned)ntiles), dim3(256), 0, s, routs,
+                       nouts, parts);
+  else
+    hipLaunchKernelGGL((k_gemm_reduce<T, 16>), dim3((unsigned)ntiles), dim3(256), 0, s, routs,
+                       nouts, parts);
 }
 
 // ---------------------------------------------------------------------------
@@ -1874,9 +2134,12 @@ void launch_check_finite(const double* X, int64_t n, int* flag, hipStream_t s) {
 #define H2K_INST(T)                                                                           \
   template void launch_gemm<T>(const GOut<T>*, int, const GCon<T>*, const int32_t*, int64_t,  \
                                int, hipStream_t, T*);                                         \
-  template void launch_gemm_reduce<T>(const GOut<T>*, int, const T*, int64_t, hipStream_t);   \
+  template void launch_gemm_reduce<T>(const GOut<T>*, int, const T*, int64_t, int,             \
+                                      hipStream_t);                                           \
   template void launch_strip<T>(const STask<T>*, int, const int32_t*, int64_t, int,           \
                                 hipStream_t);                                                 \
+  template void launch_schur<T>(const SchurLevel<T>*, int, int64_t, int, SchurRow*,           \
+                                SchurTarget*, int64_t*, int*, hipStream_t);                   \
   template void launch_rfactor<T>(const RTask<T>*, int, const FillRef<T>*, const int32_t*, int, \
                                   hipStream_t, int);                                          \
   template void launch_gram<T>(const GramTask<T>*, int, const FillRef<T>*, const int32_t*,    \

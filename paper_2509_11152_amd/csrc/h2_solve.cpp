@@ -19,11 +19,12 @@ namespace {
 
 // contributor K per chunk above which a skinny output is split over workgroups
 constexpr int64_t kSplitK = 192;
-// right-hand sides up to which the block products use the skinny 64 x 16
-// tiles (K split over the four waves and long contributor lists over
-// workgroups); wider blocks use 64 x 64 tiles
+// block products with few right-hand sides use skinny tiles (K split over the
+// four waves, long contributor lists over workgroups): 64 x 16 up to 16
+// columns, 64 x 32 up to 64; wider blocks use 64 x 64 tiles
 constexpr int kSkinnyCols = 64;
-inline int product_shape(int nrhs) { return nrhs <= kSkinnyCols ? 1 : 0; }
+inline int product_shape(int nrhs) { return nrhs <= 16 ? 1 : nrhs <= kSkinnyCols ? 3 : 0; }
+inline int tile_cols(int shape) { return shape == 1 ? 16 : shape == 3 ? 32 : 64; }
 
 // Where a solve's launches go: straight to the stream (descriptors staged
 // through the context's arena), or into a plan that later solves with the
@@ -85,7 +86,7 @@ template <class T> struct Emit {
             int shape, int64_t ptiles, const std::vector<GOut<T>>& routs, int64_t rtiles) {
     if (outs.empty()) return;
     const int no = (int)outs.size(), nr = (int)routs.size();
-    const int64_t need = ptiles * 64 * 16;
+    const int64_t need = ptiles * 64 * tile_cols(shape);
     if (!rec) {
       T* parts = nullptr;
       if (need > 0) {
@@ -98,7 +99,7 @@ template <class T> struct Emit {
       }
       launch_gemm<T>(ctx->arena.put(outs), no, ctx->arena.put(cons), nullptr, tiles, shape, s,
                      parts);
-      if (rtiles > 0) launch_gemm_reduce<T>(ctx->arena.put(routs), nr, parts, rtiles, s);
+      if (rtiles > 0) launch_gemm_reduce<T>(ctx->arena.put(routs), nr, parts, rtiles, shape, s);
       return;
     }
     const size_t oo = stage(outs), oc = stage(cons);
@@ -108,7 +109,8 @@ template <class T> struct Emit {
       launch_gemm<T>(reinterpret_cast<const GOut<T>*>(b + oo), no,
                      reinterpret_cast<const GCon<T>*>(b + oc), nullptr, tiles, shape, st, parts);
       if (rtiles > 0)
-        launch_gemm_reduce<T>(reinterpret_cast<const GOut<T>*>(b + orr), nr, parts, rtiles, st);
+        launch_gemm_reduce<T>(reinterpret_cast<const GOut<T>*>(b + orr), nr, parts, rtiles, shape,
+                              st);
     });
   }
   void laswp(T* A, int64_t lda, int64_t ncols, int nb, const int32_t* piv) {
@@ -137,7 +139,7 @@ template <class T> struct GemmBatch {
   int64_t tiles = 0, ptiles = 0, rtiles = 0;
   int shape, TM, TN;
   bool pending = false;
-  explicit GemmBatch(int sh) : shape(sh), TM(64), TN(sh == 0 ? 64 : 16) {}
+  explicit GemmBatch(int sh) : shape(sh), TM(64), TN(tile_cols(sh)) {}
   // begin output C[m0:m, n0:n] = beta C + alpha sum ...
   void out(T* C, int64_t ldc, int m0, int m, int n0, int n, T alpha, T beta) {
     end();
@@ -189,7 +191,7 @@ template <class T> struct GemmBatch {
       return;
     }
     int ns = 1;
-    if (shape == 1) {
+    if (shape == 1 || shape == 3) {
       int64_t ks = 0;
       for (int c = o.cbeg; c < o.cend; ++c) ks += cons[c].k - cons[c].k0s;
       ns = (int)std::max<int64_t>(1, std::min<int64_t>(o.cend - o.cbeg, (ks + kSplitK - 1) / kSplitK));
