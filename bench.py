@@ -93,7 +93,7 @@ def copy_calibration():
 # device phases of the factorization (h2_stats indices 0..7) and their kernels
 PHASES = ["fill_row_qr", "augment", "project", "lu", "multipliers", "schur", "close_out", "top_lu"]
 KERNEL_OF = {"fill_row_qr": "k_rfactor", "augment": "k_augment", "project": "k_strip",
-             "lu": "k_lu", "multipliers": "k_trsm", "schur": "k_gemm_out",
+             "lu": "k_lu", "multipliers": "k_trsm", "schur": "k_schur_enum + k_schur_apply",
              "close_out": "k_copy", "top_lu": "k_panel_lu + k_laswp + k_trsm_block + k_gemm"}
 # phases whose arithmetic runs on the vector ALU (Householder reductions,
 # Jacobi rotations, small LU and triangular solves); the others are priced
@@ -138,7 +138,7 @@ def roofline(st, dt):
 # FP32 kernels of the phases whose HBM traffic the PMC summary records
 PMC_KERNEL = {"fill_row_qr": "h2k::k_rfactor<float>",
               "augment": "h2k::k_augment<float, float, false>",
-              "schur": "h2k::k_gemm_out<float>"}
+              "schur": "h2k::k_schur_apply<float>"}
 
 
 def measured_traffic(workload, phase):

@@ -325,7 +325,9 @@ template <class T> struct CopyBatch {
   }
   void launch(DescArena& ar, hipStream_t s) {
     if (tasks.empty()) return;
-    launch_copy<T, T>(ar.put(tasks), (int)tasks.size(), tiles, s);
+    const CTask<T, T>* d = ar.put(tasks);
+    ar.flush(s);
+    launch_copy<T, T>(d, (int)tasks.size(), tiles, s);
   }
 };
 
@@ -528,12 +530,25 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     const SchurLevel<T>* lvdev = ar.put(lvh);
     // the device's Schur target lists: every row's contributors of the colour
     // being processed, and at most one target per pattern entry
+    // the contributor entries of a colour's targets: at most the sum over the
+    // colour's clusters of |N(i)|^2 (maximum over colours, summed over instances)
+    int64_t schur_ncon = 0;
+    {
+      std::vector<int64_t> per(maxc, 0);
+      for (auto* I : act) {
+        const LevelPlan& P = I->F->plans[I->li];
+        for (int i = 0; i < P.nl; ++i)
+          per[P.color[i]] += (int64_t)P.nb[i].size() * (int64_t)P.nb[i].size();
+      }
+      for (int64_t x : per) schur_ncon = std::max(schur_ncon, x);
+    }
     DevArray<SchurRow> schur_rowtab;
     DevArray<SchurTarget> schur_targets;
-    DevArray<int64_t> schur_count;
+    DevArray<int64_t> schur_conts, schur_count;
     schur_rowtab.alloc(std::max<int64_t>(schur_rows, 1), calltr);
     schur_targets.alloc(std::max<int64_t>(schur_nnz, 1), calltr);
-    schur_count.alloc(1, calltr);
+    schur_conts.alloc(std::max<int64_t>(schur_ncon, 1), calltr);
+    schur_count.alloc(2, calltr);
     int maxn_all = 1;
     for (auto* I : act)
       for (int x : I->F->plans[I->li].n) maxn_all = std::max(maxn_all, x);
@@ -857,21 +872,34 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       for (auto& t : sr) maxn = std::max(maxn, t.n);
       const int32_t* dyn = rdev.p;
       const bool gram = gram_mode;
+      // every descriptor of the colour staged first, then one transfer
+      const GramTask<T>* dgram = gram ? ar.put(cp.gram) : nullptr;
+      const FillRef<T>* dgrefs = gram ? ar.put(cp.grefs) : nullptr;
+      std::vector<const RTask<T>*> drst(rst.size());
+      std::vector<const FillRef<T>*> drrefs(rst.size());
+      if (!gram)
+        for (size_t st = 0; st < rst.size(); ++st) {
+          drst[st] = ar.put(rst[st]);
+          drrefs[st] = ar.put(rrefs[st]);
+        }
+      const AugTask<T>* daug = ar.put(aug);
+      const STask<T>* dsl = ar.put(sl);
+      const STask<T>* dsr = ar.put(sr);
+      const LUTask<T>* dlus = ar.put(lus);
+      const TrsmTask<T>* dtrs = ar.put(trs);
+      ar.flush(s);
       if (gram) {
-        const GramTask<T>* dg = ar.put(cp.gram);
-        const FillRef<T>* dr = ar.put(cp.grefs);
         auto m0 = mark(0);
-        launch_gram<T>(dg, (int)cp.gram.size(), dr, rdev.p, cp.gram_tiles, s);
+        launch_gram<T>(dgram, (int)cp.gram.size(), dgrefs, rdev.p, cp.gram_tiles, s);
         close_mark(m0);
       } else {
         auto m0 = mark(0);
         for (size_t st = 0; st < rst.size(); ++st)
-          launch_rfactor<T>(ar.put(rst[st]), (int)rst[st].size(), ar.put(rrefs[st]), rdev.p,
-                            rmaxn[st], s, lds);
+          launch_rfactor<T>(drst[st], (int)rst[st].size(), drrefs[st], rdev.p, rmaxn[st], s, lds);
         close_mark(m0);
       }
       auto m1 = mark(1);
-      launch_augment<T>(ar.put(aug), (int)aug.size(), rdev.p, ctx->d_err.p, maxn_aug, gram, s, lds);
+      launch_augment<T>(daug, (int)aug.size(), rdev.p, ctx->d_err.p, maxn_aug, gram, s, lds);
       close_mark(m1);
       launches[0] += gram ? 1 : (int64_t)rst.size();
       launches[1] += 1;
@@ -880,20 +908,16 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       launches[4] += 1;
       launches[5] += 1;
       {
-        // descriptors staged before the phase's first launch
-        const STask<T>* dl = ar.put(sl);
-        const STask<T>* dr = ar.put(sr);
         auto m2 = mark(2);
-        launch_strip<T>(dl, (int)sl.size(), dyn, nsl, maxn, s);
-        launch_strip<T>(dr, (int)sr.size(), dyn, nsr, maxn, s);
+        launch_strip<T>(dsl, (int)sl.size(), dyn, nsl, maxn, s);
+        launch_strip<T>(dsr, (int)sr.size(), dyn, nsr, maxn, s);
         close_mark(m2);
       }
       {
         int maxr = 1;  // r <= n of the cluster (its D block's leading dimension)
         for (auto& t : lus) maxr = std::max(maxr, (int)t.lda);
-        const LUTask<T>* dl = ar.put(lus);
         auto m3 = mark(3);
-        launch_lu<T>(dl, (int)lus.size(), dyn, ctx->d_err.p, maxr, s, lds);
+        launch_lu<T>(dlus, (int)lus.size(), dyn, ctx->d_err.p, maxr, s, lds);
         close_mark(m3);
       }
       {
@@ -902,15 +926,14 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           maxr = std::max(maxr, (int)t.ldlu);
           maxcols = std::max(maxcols, t.ncols);
         }
-        const TrsmTask<T>* dt = ar.put(trs);
         auto m4 = mark(4);
-        launch_trsm<T>(dt, (int)trs.size(), dyn, maxr, maxcols, s, lds);
+        launch_trsm<T>(dtrs, (int)trs.size(), dyn, maxr, maxcols, s, lds);
         close_mark(m4);
       }
       {
         auto m5 = mark(5);
         launch_schur<T>(lvdev, (int)act.size(), schur_rows, c, schur_rowtab.p, schur_targets.p,
-                        schur_count.p, ctx->d_err.p, s);
+                        schur_conts.p, schur_count.p, ctx->d_err.p, s);
         close_mark(m5);
       }
       H2_HIP(hipGetLastError());  // a rejected launch configuration
@@ -1271,7 +1294,10 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           g.ldb = n;
           g.k = w;
           g.k0d = g.k1d = -1;
-          launch_gemm<T>(ar.put(outs), 1, ar.put(cons), nullptr, (int64_t)o.tm * o.tn, 0, s);
+          const GOut<T>* dout = ar.put(outs);
+          const GCon<T>* dcon = ar.put(cons);
+          ar.flush(s);
+          launch_gemm<T>(dout, 1, dcon, nullptr, (int64_t)o.tm * o.tn, 0, s);
         }
       }
       I.flops += 2.0 * (double)n * n * n / 3.0;

@@ -131,6 +131,10 @@ template <class T> struct DevArray {
 };
 
 // Descriptor arrays staged through pinned host memory into device memory.
+// put() copies an array into the pinned staging chunk and returns the device
+// address it will have; flush() issues one asynchronous copy per chunk for
+// everything put since the last flush, so a launch group's descriptors
+// travel in one transfer (flush before the launches that read them).
 // Chunks are only ever added: every array put since the last reset() stays
 // valid (several puts feed one launch, and launches queue behind each other),
 // so reset() may be called only once the stream has finished all work that
@@ -140,9 +144,11 @@ struct DescArena {
     char* h = nullptr;
     char* d = nullptr;
     size_t cap = 0;
+    size_t used = 0;     // bytes staged
+    size_t flushed = 0;  // bytes whose copy has been issued
   };
   std::vector<Chunk> chunks;
-  size_t cur = 0, used = 0;  // chunk being filled and bytes used in it
+  size_t cur = 0;  // chunk being filled
   hipStream_t s = nullptr;
   DevMem* mem = nullptr;
   ~DescArena() { free_all(); }
@@ -152,17 +158,17 @@ struct DescArena {
       if (c.d) mem->put(c.d, c.cap);
     }
     chunks.clear();
-    cur = used = 0;
+    cur = 0;
   }
-  void reset() { cur = used = 0; }
+  void reset() {
+    for (auto& c : chunks) c.used = c.flushed = 0;
+    cur = 0;
+  }
   template <class X> X* put(const std::vector<X>& v) {
     if (v.empty()) return nullptr;
     const size_t bytes = sizeof(X) * v.size();
     const size_t need = (bytes + 255) & ~(size_t)255;
-    while (cur < chunks.size() && used + need > chunks[cur].cap) {
-      ++cur;
-      used = 0;
-    }
+    while (cur < chunks.size() && chunks[cur].used + need > chunks[cur].cap) ++cur;
     if (cur == chunks.size()) {
       Chunk c;
       c.cap = std::max(need, (size_t)64 << 20);
@@ -174,14 +180,23 @@ struct DescArena {
         throw;
       }
       chunks.push_back(c);
-      used = 0;
     }
     Chunk& c = chunks[cur];
-    std::memcpy(c.h + used, v.data(), bytes);
-    H2_HIP(hipMemcpyAsync(c.d + used, c.h + used, bytes, hipMemcpyHostToDevice, s));
-    X* out = reinterpret_cast<X*>(c.d + used);
-    used += need;
+    std::memcpy(c.h + c.used, v.data(), bytes);
+    X* out = reinterpret_cast<X*>(c.d + c.used);
+    c.used += need;
     return out;
+  }
+  // issue the copies of everything staged since the last flush
+  void flush(hipStream_t st) {
+    for (size_t q = 0; q <= cur && q < chunks.size(); ++q) {
+      Chunk& c = chunks[q];
+      if (c.used > c.flushed) {
+        H2_HIP(hipMemcpyAsync(c.d + c.flushed, c.h + c.flushed, c.used - c.flushed,
+                              hipMemcpyHostToDevice, st));
+        c.flushed = c.used;
+      }
+    }
   }
 };
 

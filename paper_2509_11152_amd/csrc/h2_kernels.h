@@ -116,6 +116,7 @@ struct SchurTarget {
   int64_t e;
   int32_t g;
   uint32_t mask;
+  int64_t cbeg;  // its contributors' entries (i, k), in bit order, at conts[cbeg..]
 };
 // contributors of one row for the colour being processed: cluster ids and
 // their entries (j, i)
@@ -244,13 +245,14 @@ void launch_strip(const STask<T>* tasks, int ntasks, const int32_t* dyn, int64_t
 // C[active rows, active cols] -= sum over those i, ascending, of
 // D_{j, R_i} (D_RR^{-1} D_{R_i, k}).  Fails (err bit 4) when a row has more
 // than kSchurMaxContrib contributors.
-// Two launches: the first finds every row's contributors (rows[g]) and the
-// targets (appended to `targets`, their number counted in *count, which the
-// call clears first; `cap` entries at most, at least the levels' pattern
-// entries); the second forms the targets' updates, one workgroup each.
+// Two launches: the first finds every row's contributors (rowtab[g]), the
+// targets (appended to `targets`, at most the levels' pattern entries) and
+// each target's contributor entries (i, k) (appended to `conts`, at most the
+// colour's sum over its clusters of |N(i)|^2); count[0] and count[1] count
+// them (cleared first).  The second forms the targets' updates.
 template <class T>
 void launch_schur(const SchurLevel<T>* lv, int ninst, int64_t rows, int c, SchurRow* rowtab,
-                  SchurTarget* targets, int64_t* count, int* err, hipStream_t s);
+                  SchurTarget* targets, int64_t* conts, int64_t* count, int* err, hipStream_t s);
 // `lds`: LDS bytes per workgroup the path choices of the fill-row QR, the
 // augmentation, the LU and the multipliers may assume (at most kLdsBytes);
 // working sets beyond it take the global-memory variants

@@ -437,13 +437,13 @@ template <class T> __device__ inline int64_t schur_near_entry(const SchurLevel<T
 template <class T>
 __global__ __launch_bounds__(256) void k_schur_enum(const SchurLevel<T>* __restrict__ lvs,
                                                     int ninst, int c, SchurRow* rowtab,
-                                                    SchurTarget* targets, int64_t* count,
-                                                    int* err) {
+                                                    SchurTarget* targets, int64_t* conts,
+                                                    int64_t* count, int* err) {
   __shared__ int ci[kSchurMaxContrib];
   __shared__ int64_t eji[kSchurMaxContrib];
-  __shared__ int wcnt[4];
+  __shared__ int wcnt[4], wcon[4];
   __shared__ int sh_nc;
-  __shared__ int64_t sh_base;
+  __shared__ int64_t sh_base, sh_cbase;
   const int64_t g = blockIdx.x;
   const SchurLevel<T>& L = lvs[schur_inst(lvs, ninst, g)];
   const int j = (int)(g - L.rows0);
@@ -490,37 +490,62 @@ __global__ __launch_bounds__(256) void k_schur_enum(const SchurLevel<T>* __restr
       for (int x = 0; x < nc; ++x)
         if (schur_near_entry(L, ci[x], k) >= 0) mask |= 1u << x;
     }
+    const int nb = __popc(mask);
+    // exclusive prefix of the contributor counts within the wave
+    int incl = nb;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
     const unsigned long long bal = __ballot(mask != 0);
+    if (lane == 63) wcon[wave] = incl;
     if (lane == 0) wcnt[wave] = __popcll(bal);
     __syncthreads();
-    if (tid == 0)
+    if (tid == 0) {
       sh_base = (int64_t)atomicAdd((unsigned long long*)count,
                                    (unsigned long long)(wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3]));
+      sh_cbase = (int64_t)atomicAdd((unsigned long long*)(count + 1),
+                                    (unsigned long long)(wcon[0] + wcon[1] + wcon[2] + wcon[3]));
+    }
     __syncthreads();
-    int off = 0;
-    for (int w = 0; w < wave; ++w) off += wcnt[w];
+    int off = 0, coff = 0;
+    for (int w = 0; w < wave; ++w) {
+      off += wcnt[w];
+      coff += wcon[w];
+    }
     off += __popcll(bal & ((1ull << lane) - 1ull));
+    coff += incl - nb;
     if (mask) {
+      const int k = L.pcol[e];
       SchurTarget t;
       t.e = e;
       t.g = (int32_t)g;
       t.mask = mask;
+      t.cbeg = sh_cbase + coff;
       targets[sh_base + off] = t;
+      int q = 0;
+      for (int x = 0; x < nc; ++x)
+        if ((mask >> x) & 1u) conts[t.cbeg + q++] = schur_near_entry(L, ci[x], k);
     }
     __syncthreads();
   }
 }
 
 // workgroups loop over the targets: C -= sum of the contributors' products,
-// contributors ascending (bit order)
+// contributors ascending (bit order).  The active window of C is cut into
+// items of 16 rows x 32 columns (two 16 x 16 fragments), handed to the four
+// waves in turn, so blocks of any order up to a few hundred take no more
+// fragments than they cover; every item loads the operands of four k-steps
+// before their products.
+constexpr int kSchurKB = 4;
 template <class T>
 __global__ __launch_bounds__(256) void k_schur_apply(const SchurLevel<T>* __restrict__ lvs,
                                                      int ninst, int c,
                                                      const SchurRow* __restrict__ rowtab,
                                                      const SchurTarget* __restrict__ targets,
+                                                     const int64_t* __restrict__ conts,
                                                      const int64_t* __restrict__ count) {
-  constexpr int FM = 2, FN = 2;
-  __shared__ int64_t eik[kSchurMaxContrib];
+  constexpr int CW = 2;  // column fragments per item
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, kq = lane >> 4;
@@ -532,96 +557,78 @@ __global__ __launch_bounds__(256) void k_schur_apply(const SchurLevel<T>* __rest
     const int j = (int)(tg.g - L.rows0);
     const int k = L.pcol[tg.e];
     const int nc = R.nc;
-    if (tid < nc) eik[tid] = ((tg.mask >> tid) & 1u) ? schur_near_entry(L, R.ci[tid], k) : -1;
-    __syncthreads();
     const int nj = L.n[j], nk = L.n[k];
     const int m0 = L.color[j] <= c ? L.r[j] : 0;
     const int n0 = L.color[k] <= c ? L.r[k] : 0;
     const gptr<const T> Dg = gmem((const T*)L.D);
     const gptr<T> C = gmem((L.kind[tg.e] == 1 ? L.F : L.D) + L.poff[tg.e]);
     const int64_t ldc = nj;
-    const int tm = (nj + 63) / 64, tn = (nk + 63) / 64;
-    for (int t = 0; t < tm * tn; ++t) {
-      const int r0 = m0 + (t % tm) * 64, c0 = n0 + (t / tm) * 64;
-      if (r0 >= nj || c0 >= nk) continue;
-      const int wr = r0 + (wave & 1) * 32, wc = c0 + (wave >> 1) * 32;
-      T cv[FM][FN][4];
+    const int nrg = (nj - m0 + 15) / 16;              // row fragments of the window
+    const int ncg = (nk - n0 + 16 * CW - 1) / (16 * CW);  // column items of the window
+    for (int it = wave; it < nrg * ncg; it += 4) {
+      const int row = m0 + (it % nrg) * 16 + l16;
+      const int cb = n0 + (it / nrg) * 16 * CW;
+      typename Acc<T>::type acc[CW];
 #pragma unroll
-      for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int b = 0; b < FN; ++b)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int row = wr + a * 16 + l16, col = wc + b * 16 + acc_row<T>(kq, i);
-            cv[a][b][i] = (row < nj && col < nk) ? C[row + (int64_t)col * ldc] : T(0);
-          }
-      typename Acc<T>::type acc[FM][FN];
-#pragma unroll
-      for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int b = 0; b < FN; ++b) acc[a][b] = (typename Acc<T>::type){0, 0, 0, 0};
+      for (int b = 0; b < CW; ++b) acc[b] = (typename Acc<T>::type){0, 0, 0, 0};
+      int64_t cq = tg.cbeg;
       for (int x = 0; x < nc; ++x) {
-        const int64_t eb = eik[x];
-        if (eb < 0) continue;
+        if (!((tg.mask >> x) & 1u)) continue;
+        const int64_t eb = conts[cq++];
         const int i = R.ci[x];
         const int ni = L.n[i];
         const int k1 = L.r[i];
         const gptr<const T> A = Dg + L.poff[R.eji[x]];  // D(j, i), n_j x n_i
         const gptr<const T> B = Dg + L.poff[eb];        // D(i, k), n_i x n_k
-        for (int kb = 0; kb < k1; kb += 4 * kGemmKB) {
-          T av[kGemmKB][FM], bv[kGemmKB][FN];
+        for (int kb = 0; kb < k1; kb += 4 * kSchurKB) {
+          T av[kSchurKB], bv[kSchurKB][CW];
 #pragma unroll
-          for (int qq = 0; qq < kGemmKB; ++qq) {
+          for (int qq = 0; qq < kSchurKB; ++qq) {
             const int kx = kb + 4 * qq + kq;
             const bool kok = kx < k1;
+            av[qq] = (kok && row < nj) ? A[row + (int64_t)kx * nj] : T(0);
 #pragma unroll
-            for (int a = 0; a < FM; ++a) {
-              const int row = wr + a * 16 + l16;
-              av[qq][a] = (kok && row < nj) ? A[row + (int64_t)kx * nj] : T(0);
-            }
-#pragma unroll
-            for (int b = 0; b < FN; ++b) {
-              const int col = wc + b * 16 + l16;
+            for (int b = 0; b < CW; ++b) {
+              const int col = cb + b * 16 + l16;
               bv[qq][b] = (kok && col < nk) ? B[kx + (int64_t)col * ni] : T(0);
             }
           }
+          // operands swapped: the accumulator holds the transposed fragment,
+          // lane l16 owning row l16 (coalesced epilogue)
 #pragma unroll
-          for (int qq = 0; qq < kGemmKB; ++qq) {
+          for (int qq = 0; qq < kSchurKB; ++qq) {
             if (kb + 4 * qq >= k1) break;
 #pragma unroll
-            for (int a = 0; a < FM; ++a)
-#pragma unroll
-              for (int b = 0; b < FN; ++b) acc[a][b] = mfma16(bv[qq][b], av[qq][a], acc[a][b]);
+            for (int b = 0; b < CW; ++b) acc[b] = mfma16(bv[qq][b], av[qq], acc[b]);
           }
         }
       }
+      if (row < nj) {
 #pragma unroll
-      for (int a = 0; a < FM; ++a) {
-        const int row = wr + a * 16 + l16;
-        if (row >= nj) continue;
-#pragma unroll
-        for (int b = 0; b < FN; ++b)
+        for (int b = 0; b < CW; ++b)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int col = wc + b * 16 + acc_row<T>(kq, i);
-            if (col < nk) C[row + (int64_t)col * ldc] = cv[a][b][i] - acc[a][b][i];
+            const int col = cb + b * 16 + acc_row<T>(kq, i);
+            if (col < nk) {
+              const gptr<T> p = C + row + (int64_t)col * ldc;
+              *p = *p - acc[b][i];
+            }
           }
       }
     }
-    __syncthreads();  // eik is rewritten for the next target
   }
 }
 
 template <class T>
 void launch_schur(const SchurLevel<T>* lv, int ninst, int64_t rows, int c, SchurRow* rowtab,
-                  SchurTarget* targets, int64_t* count, int* err, hipStream_t s) {
+                  SchurTarget* targets, int64_t* conts, int64_t* count, int* err, hipStream_t s) {
   if (rows <= 0 || ninst <= 0) return;
-  hipLaunchKernelGGL(k_fill<int64_t>, dim3(1), dim3(64), 0, s, count, (int64_t)1, (int64_t)0);
+  hipLaunchKernelGGL(k_fill<int64_t>, dim3(1), dim3(64), 0, s, count, (int64_t)2, (int64_t)0);
   hipLaunchKernelGGL(k_schur_enum<T>, dim3((unsigned)rows), dim3(256), 0, s, lv, ninst, c, rowtab,
-                     targets, count, err);
+                     targets, conts, count, err);
   // workgroups loop over however many targets the first launch found
   hipLaunchKernelGGL(k_schur_apply<T>, dim3(8192), dim3(256), 0, s, lv, ninst, c, rowtab, targets,
-                     count);
+                     conts, count);
 }
 
 template <class T>
@@ -2139,7 +2146,7 @@ void launch_check_finite(const double* X, int64_t n, int* flag, hipStream_t s) {
   template void launch_strip<T>(const STask<T>*, int, const int32_t*, int64_t, int,           \
                                 hipStream_t);                                                 \
   template void launch_schur<T>(const SchurLevel<T>*, int, int64_t, int, SchurRow*,           \
-                                SchurTarget*, int64_t*, int*, hipStream_t);                   \
+                                SchurTarget*, int64_t*, int64_t*, int*, hipStream_t);         \
   template void launch_rfactor<T>(const RTask<T>*, int, const FillRef<T>*, const int32_t*, int, \
                                   hipStream_t, int);                                          \
   template void launch_gram<T>(const GramTask<T>*, int, const FillRef<T>*, const int32_t*,    \

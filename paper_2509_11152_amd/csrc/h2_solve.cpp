@@ -3,7 +3,10 @@
 // solve's task lists use static window boundaries only; all instances of a
 // batch share one launch per (height, colour step).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <exception>
+#include <thread>
 #include <cstdio>
 #include <cstring>
 #include <functional>
@@ -50,7 +53,9 @@ template <class T> struct Emit {
     if (t.empty()) return;
     const int n = (int)t.size();
     if (!rec) {
-      launch_strip<T>(ctx->arena.put(t), n, nullptr, strips, maxn, s);
+      const STask<T>* d = ctx->arena.put(t);
+      ctx->arena.flush(s);
+      launch_strip<T>(d, n, nullptr, strips, maxn, s);
       return;
     }
     const size_t o = stage(t);
@@ -62,7 +67,9 @@ template <class T> struct Emit {
     if (t.empty()) return;
     const int n = (int)t.size();
     if (!rec) {
-      launch_trsm<T>(ctx->arena.put(t), n, nullptr, maxr, ncols, s);
+      const TrsmTask<T>* d = ctx->arena.put(t);
+      ctx->arena.flush(s);
+      launch_trsm<T>(d, n, nullptr, maxr, ncols, s);
       return;
     }
     const size_t o = stage(t);
@@ -74,7 +81,9 @@ template <class T> struct Emit {
     if (t.empty()) return;
     const int n = (int)t.size();
     if (!rec) {
-      launch_copy<T, T>(ctx->arena.put(t), n, tiles, s);
+      const CTask<T, T>* d = ctx->arena.put(t);
+      ctx->arena.flush(s);
+      launch_copy<T, T>(d, n, tiles, s);
       return;
     }
     const size_t o = stage(t);
@@ -97,9 +106,12 @@ template <class T> struct Emit {
         }
         parts = P.p;
       }
-      launch_gemm<T>(ctx->arena.put(outs), no, ctx->arena.put(cons), nullptr, tiles, shape, s,
-                     parts);
-      if (rtiles > 0) launch_gemm_reduce<T>(ctx->arena.put(routs), nr, parts, rtiles, shape, s);
+      const GOut<T>* dout = ctx->arena.put(outs);
+      const GCon<T>* dcon = ctx->arena.put(cons);
+      const GOut<T>* drout = rtiles > 0 ? ctx->arena.put(routs) : nullptr;
+      ctx->arena.flush(s);
+      launch_gemm<T>(dout, no, dcon, nullptr, tiles, shape, s, parts);
+      if (rtiles > 0) launch_gemm_reduce<T>(drout, nr, parts, rtiles, shape, s);
       return;
     }
     const size_t oo = stage(outs), oc = stage(cons);
@@ -313,6 +325,36 @@ void solve_setup(SolveInst<T>& S, h2_factor_s* F, int nrhs, DevTracker* tr) {
   S.vec[nlev].alloc(std::max<int64_t>(F->n_top, 1) * nrhs, tr);
 }
 
+// one colour's solve tasks (built on a worker thread, emitted in order)
+template <class T> struct ColourTasks {
+  StripBatch<T> sb;
+  std::vector<TrsmTask<T>> trs;
+  GemmBatch<T> gb;
+  explicit ColourTasks(int shape) : gb(shape) {}
+};
+
+// f(0) .. f(n - 1) on up to 16 threads (the calling thread included), each
+// taking the next index
+template <class Fn> void parallel_for(int n, Fn f) {
+  const int nt = (int)std::max(1u, std::min({16u, std::thread::hardware_concurrency(),
+                                             (unsigned)std::max(n, 1)}));
+  std::atomic<int> next(0);
+  std::vector<std::exception_ptr> errs(nt);
+  auto run = [&](int t) {
+    try {
+      for (int q; (q = next.fetch_add(1)) < n;) f(q);
+    } catch (...) {
+      errs[t] = std::current_exception();
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(run, t);
+  run(0);
+  for (auto& x : th) x.join();
+  for (auto& e : errs)
+    if (e) std::rethrow_exception(e);
+}
+
 // Algorithm 3 on the work vectors (the right-hand sides already gathered in
 // tree order into vec[0]): forward colour by colour and level by level, the
 // dense top solve, then backward.
@@ -326,10 +368,15 @@ void solve_body(Emit<T>& em, std::vector<SolveInst<T>>& si, int nrhs) {
     int maxc = 0;
     for (auto& S : si)
       if (li < S.F->plans.size()) maxc = std::max(maxc, S.F->plans[li].ncolors);
-    for (int c = 0; c < maxc; ++c) {
-      StripBatch<T> sb;
-      std::vector<TrsmTask<T>> trs;
-      GemmBatch<T> gb(shape);
+    // each colour's task lists are built on worker threads, then emitted in
+    // colour order
+    std::vector<ColourTasks<T>> ct;
+    ct.reserve(maxc);
+    for (int c = 0; c < maxc; ++c) ct.emplace_back(shape);
+    parallel_for(maxc, [&](int c) {
+      StripBatch<T>& sb = ct[c].sb;
+      std::vector<TrsmTask<T>>& trs = ct[c].trs;
+      GemmBatch<T>& gb = ct[c].gb;
       for (auto& S : si) {
         h2_factor_s* F = S.F;
         if (li >= F->plans.size()) continue;
@@ -374,13 +421,16 @@ void solve_body(Emit<T>& em, std::vector<SolveInst<T>>& si, int nrhs) {
           a = b;
         }
       }
-      sb.launch(em);
+    });
+    for (int c = 0; c < maxc; ++c) {
+      ct[c].sb.launch(em);
+      std::vector<TrsmTask<T>>& trs = ct[c].trs;
       if (!trs.empty()) {
         int maxr = 1;
         for (auto& t : trs) maxr = std::max(maxr, t.rs);
         em.trsm(trs, maxr, nrhs);
       }
-      gb.launch(em);
+      ct[c].gb.launch(em);
     }
     // upsweep: skeleton parts of the children form the parent segments
     CopyB<T> cb;
@@ -472,9 +522,12 @@ void solve_body(Emit<T>& em, std::vector<SolveInst<T>>& si, int nrhs) {
     int maxc = 0;
     for (auto& S : si)
       if (lj < S.F->plans.size()) maxc = std::max(maxc, S.F->plans[lj].ncolors);
-    for (int c = maxc - 1; c >= 0; --c) {
-      GemmBatch<T> gb(shape);
-      StripBatch<T> sb;
+    std::vector<ColourTasks<T>> ct;
+    ct.reserve(maxc);
+    for (int c = 0; c < maxc; ++c) ct.emplace_back(shape);
+    parallel_for(maxc, [&](int c) {
+      GemmBatch<T>& gb = ct[c].gb;
+      StripBatch<T>& sb = ct[c].sb;
       for (auto& S : si) {
         h2_factor_s* F = S.F;
         if (lj >= F->plans.size()) continue;
@@ -497,8 +550,10 @@ void solve_body(Emit<T>& em, std::vector<SolveInst<T>>& si, int nrhs) {
           sb.add(v + S.voff[lj][i], ld, st.Q.p + P.offQ[i], P.n[i], nrhs, 0, 0);
         }
       }
-      gb.launch(em);
-      sb.launch(em);
+    });
+    for (int c = maxc - 1; c >= 0; --c) {
+      ct[c].gb.launch(em);
+      ct[c].sb.launch(em);
     }
   }
 }
