@@ -58,6 +58,8 @@ def parse():
                    help="always run the 64-instance batched measurement")
     p.add_argument("--batched-s", type=float, default=240.0,
                    help="run the batched measurement only when this much budget is left")
+    p.add_argument("--no-fp64", action="store_true",
+                   help="skip the FP64 comparison (profiling runs)")
     p.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-batched", action="store_true",
@@ -433,7 +435,7 @@ def main():
     s64 = None
     reps64 = 0
     est64 = 2.0 * value_or(med(t32), 1.0)
-    for rep in range(2):
+    for rep in range(0 if args.no_fp64 else 2):
         if rep == 0 and left() - est64 * 2 < 60:
             continue  # no time for an untimed run
         if left() < est64 + 30:
@@ -499,7 +501,7 @@ def main():
         out["fp64_plain"] = {"total_s": t64p, "bkwd": eb64p}
         out["phases_fp64"] = phases64
     else:
-        out["fp64_ir"] = {"skipped": "time budget"}
+        out["fp64_ir"] = {"skipped": "not asked for" if args.no_fp64 else "time budget"}
     if args.batched or (not args.no_batched and left() > args.batched_s):
         del H, B
         torch.cuda.empty_cache()
