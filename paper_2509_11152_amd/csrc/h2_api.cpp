@@ -432,6 +432,17 @@ h2_status h2_matrix_load(h2_context_t ctx, const void* blob, size_t bytes, h2_ma
     H->perm_d.alloc(H->N, &H->tr);
     H2_HIP(hipMemcpyAsync(H->perm_d.p, H->perm.data(), (size_t)H->N * 8, hipMemcpyHostToDevice,
                           ctx->stream));
+    auto up = [&](auto& dst, const auto& v) {
+      dst.alloc((int64_t)v.size(), &H->tr);
+      if (!v.empty())
+        H2_HIP(hipMemcpyAsync(dst.p, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice,
+                              ctx->stream));
+    };
+    up(H->far_ptr_d, H->far_ptr);
+    up(H->far_col_d, H->far_col);
+    up(H->offS_d, H->offS);
+    up(H->offE_d, H->offE);
+    up(H->rank_d, H->rank);
     H2_HIP(hipStreamSynchronize(ctx->stream));
   });
   if (st != H2_SUCCESS) {

@@ -331,18 +331,36 @@ template <class T> struct CopyBatch {
   }
 };
 
-// initialise the leaf level: D blocks from the blob, V = U, F = 0
-template <class T> void init_leaf(Inst<T>& I, LevelStore<T>& S, LevelPlan& P, CopyBatch<T>& cb) {
+// initialise the leaf level: D blocks from the blob, V = U (F is zeroed by
+// the caller).  The blob stores the leaf near blocks in CSR order (m_i x m_j
+// each) and the leaf bases in leaf order (m_i x k_i), which are exactly the
+// orders of the level's D buffer (near entries of the pattern in CSR order)
+// and V buffer, so each is one contiguous device-to-device copy.
+template <class T> void init_leaf(Inst<T>& I, LevelStore<T>& S, LevelPlan& P, hipStream_t s) {
   const h2_matrix_s& H = *I.H;
-  for (int i = 0; i < P.nl; ++i) {
-    const int q = P.a + i;
-    for (int64_t e = H.near_ptr[q]; e < H.near_ptr[q + 1]; ++e) {
-      const int j = H.near_col[e] - P.a;
-      const int64_t pe = P.find(i, j);
-      cb.add(I.data + H.offD[e], P.n[i], S.D.p + P.poff[pe], P.n[i], P.n[i], P.n[j], 0);
-    }
-    cb.add(I.data + H.offU[q], P.n[i], I.Vbuf.p + P.offV[i], P.n[i], P.n[i], P.k[i], 0);
-  }
+  const int q0 = P.a, q1 = P.a + P.nl;
+  const int64_t d0 = H.offD[H.near_ptr[q0]];
+  const int64_t d1 = H.near_ptr[q1] > H.near_ptr[q0]
+                         ? H.offD[H.near_ptr[q1] - 1] +
+                               (int64_t)H.size(q1 - 1) * H.size(H.near_col[H.near_ptr[q1] - 1])
+                         : d0;
+  const int64_t u0 = H.offU[q0];
+  const int64_t u1 = H.offU[q1 - 1] + (int64_t)H.size(q1 - 1) * H.rank[q1 - 1];
+  if (d1 - d0 != P.nD || u1 - u0 != P.nV)
+    throw H2Error(H2_ERROR_FORMAT, "leaf blocks do not match the level layout");
+  if (P.nD > 0)
+    H2_HIP(hipMemcpyAsync(S.D.p, I.data + d0, sizeof(T) * P.nD, hipMemcpyDeviceToDevice, s));
+  if (P.nV > 0)
+    H2_HIP(hipMemcpyAsync(I.Vbuf.p, I.data + u0, sizeof(T) * P.nV, hipMemcpyDeviceToDevice, s));
+}
+
+// entry kinds of a level's pattern: 0 near, 1 stored fill (j < k), 2 fill
+// entry (j, k) with k < j, whose block is the stored (k, j)
+std::vector<int8_t> level_kinds(const LevelPlan& P) {
+  std::vector<int8_t> kind(P.pcol.size());
+  for (int j = 0; j < P.nl; ++j)
+    for (int64_t e = P.pptr[j]; e < P.pptr[j + 1]; ++e) kind[e] = P.isF[e] ? (P.tr(j, e) ? 2 : 1) : 0;
+  return kind;
 }
 
 template <class T> void alloc_level(Inst<T>& I, LevelPlan& P) {
@@ -442,7 +460,6 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
   // ---- leaf level plans ----
   {
     const auto t0 = std::chrono::steady_clock::now();
-    CopyBatch<T> cb;
     for (auto& I : insts) {
       const h2_matrix_s& H = *I.H;
       I.lev = H.L;
@@ -461,9 +478,8 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       I.li = I.F->plans.size() - 1;
       LevelStore<T>& S = store_of<T>(I.F, I.li);
       launch_fill<T>(I.Fbuf.p, I.Fbuf.n, T(0), s);
-      init_leaf(I, S, P, cb);
+      init_leaf(I, S, P, s);
     }
-    cb.launch(ar, s);
     plan_ms += ms_since(t0);
   }
 
@@ -508,15 +524,11 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     for (size_t q = 0; q < act.size(); ++q) {
       Inst<T>* I = act[q];
       LevelPlan& P = I->F->plans[I->li];
-      std::vector<int8_t> kind(P.pcol.size());
-      for (int j = 0; j < P.nl; ++j)
-        for (int64_t e = P.pptr[j]; e < P.pptr[j + 1]; ++e)
-          kind[e] = P.isF[e] ? (P.tr(j, e) ? 2 : 1) : 0;
       SchurLevel<T>& L = lvh[q];
       L.pptr = ar.put(P.pptr);
       L.pcol = ar.put(P.pcol);
       L.poff = ar.put(P.poff);
-      L.kind = ar.put(kind);
+      L.kind = ar.put(level_kinds(P));
       L.color = ar.put(P.color);
       L.n = ar.put(P.n);
       L.r = rdev.p + I->rbase;
@@ -951,6 +963,8 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         throw H2Error(H2_ERROR_UNSUPPORTED, "a block row has more than " +
                                                 std::to_string(kSchurMaxContrib) +
                                                 " Schur contributors of one colour");
+      if (herr & 8)
+        throw H2Error(H2_ERROR_FORMAT, "close-out destination missing from the next level");
     }
     {
       for (auto& m : marks) {
@@ -960,12 +974,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       }
       marks.clear();
     }
-    ar.reset();
     // ---- close-out into the next level (or the dense top block) ----
-    // cb: skeleton blocks of near and fill entries (one source per destination
-    // sub-block); cb2, launched after cb: couplings added to far-pair
-    // sub-blocks and transfer blocks of the next bases.
-    CopyBatch<T> cb, cb2;
     for (size_t q = 0; q < act.size(); ++q) {
       Inst<T>* I = act[q];
       const auto tpl = std::chrono::steady_clock::now();
@@ -973,8 +982,10 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       h2_factor_s* F = I->F;
       LevelPlan& P = F->plans[I->li];
       for (int i = 0; i < P.nl; ++i) P.r[i] = rh[I->rbase + i];
-      // algorithmic flop model of the level
-      {
+      // algorithmic flop model of the level, on a worker thread while the
+      // close-out is planned (it reads the plan and writes only the instance's
+      // counters)
+      auto flop_model = std::async(std::launch::async, [I, &P, gm = gram_mode]() {
         for (int i = 0; i < P.nl; ++i) {
           const double n = P.n[i], k = P.k[i], r = P.r[i], kt = n - r;
           double f = 0, W = kt, Wn = 0;
@@ -991,7 +1002,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           // transpose (f x n), SVD of the n x n factor (reported as 4 n^3)
           const double qr = f >= n ? 2 * f * n * n - 2 * n * n * n / 3 : 2 * n * f * f - 2 * f * f * f / 3;
           // FP32 path: the Gram matrix Y Y^T (2 n^2 f) replaces the QR
-          const double f_qr = gram_mode ? 2 * n * n * f : (4 * n * k * f + qr) * (f > 0);
+          const double f_qr = gm ? 2 * n * n * f : (4 * n * k * f + qr) * (f > 0);
           const double f_aug = (f_qr + 4 * n * n * n) * (f > 0) +
                                2 * n * kt * kt - 2 * kt * kt * kt / 3 +
                                4 * (n * n * kt - n * kt * kt + kt * kt * kt / 3);
@@ -1010,14 +1021,14 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           // written); R, V in and Q~ out; projected blocks read + written;
           // D_RR read + written; panels read + written; Schur targets read +
           // written once per contributor group
-          I->pbytes[0] += b * n * f + (gram_mode ? 8.0 : b) * n * n;
+          I->pbytes[0] += b * n * f + (gm ? 8.0 : b) * n * n;
           I->pbytes[1] += b * (n * n + n * k + n * n);
           I->pbytes[2] += b * 2 * (n * n + n * Wn + n * f);
           I->pbytes[3] += b * 2 * r * r;
           I->pbytes[4] += b * (r * r + 2 * r * W);
           I->pbytes[5] += b * (2 * r * W + 2 * W * W);
         }
-      }
+      });
       const int lev = P.lev;
       const int plev = lev - 1;
       // sizes of the next level
@@ -1039,7 +1050,6 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       T* Fn = nullptr;
       LevelPlan* PN = nullptr;
       int64_t ldtop = 0;
-      std::vector<int64_t> toff;
       if (is_top) {
         F->top_level = plev;
         F->top_nodes.clear();
@@ -1086,129 +1096,81 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
         Fn = Fnext.p;
         Vnext.alloc(PN->nV, &F->tr);
       }
-      auto dest = [&](int t, int s2, bool near_pair, int64_t& ld) -> T* {
-        // block (t, s2) of level plev (local ids)
-        if (is_top) {
-          ld = ldtop;
-          return Dn + F->top_off[t] + F->top_off[s2] * ldtop;
-        }
-        const int64_t e = PN->find(t, s2);
-        ld = PN->n[t];
-        if (e < 0) throw H2Error(H2_ERROR_FORMAT, "close-out destination missing from the pattern");
-        (void)near_pair;
-        // fill (t, s2) with s2 < t is the stored (s2, t): the mirror entry
-        // writes it
-        if (PN->tr(t, e)) return (T*)nullptr;
-        return (PN->isF[e] ? Fn : Dn) + PN->poff[e];
-      };
-      // copy tasks of rows [j0, j1) of the level into (cbl, cb2l); rows run
-      // on worker threads and their batches are appended in row order
-      auto close_rows = [&](int j0, int j1, CopyBatch<T>& cbl, CopyBatch<T>& cb2l) {
-        for (int j = j0; j < j1; ++j) {
-          const int gj = Pc.a + j;
-          const int pt = H.parent[gj] - pa;
-          const int rj = Pc.r[j], ktj = Pc.n[j] - rj;
-          for (int64_t e = Pc.pptr[j]; e < Pc.pptr[j + 1]; ++e) {
-            const int k = Pc.pcol[e];
-            const int ps = H.parent[Pc.a + k] - pa;
-            const int rk = Pc.r[k], ktk = Pc.n[k] - rk;
-            int64_t ld = 0;
-            T* d = dest(pt, ps, true, ld);
-            if (!d) continue;
-            d += offc[j] + (int64_t)offc[k] * ld;
-            // near: copy; fill: accumulate (a far pair also receives its
-            // coupling); a fill entry (j, k) with k < j is read as the
-            // transpose of the stored (k, j)
-            if (Pc.tr(j, e)) {
-              const T* src = I->Fbuf.p + Pc.poff[e] + rk + (int64_t)rj * Pc.n[k];
-              cbl.add(src, Pc.n[k], d, ld, ktj, ktk, 1, 1);
-            } else {
-              const T* src =
-                  (Pc.isF[e] ? I->Fbuf.p : Sc->D.p) + Pc.poff[e] + rj + (int64_t)rk * Pc.n[j];
-              cbl.add(src, Pc.n[j], d, ld, ktj, ktk, Pc.isF[e] ? 1 : 0);
-            }
-          }
-          // couplings of far pairs into the skeleton blocks: S~ = [S 0; 0 0]
-          for (int64_t e = H.far_ptr[gj]; e < H.far_ptr[gj + 1]; ++e) {
-            const int k = H.far_col[e] - Pc.a;
-            const int ps = H.parent[Pc.a + k] - pa;
-            int64_t ld = 0;
-            T* d = dest(pt, ps, true, ld);
-            if (!d) throw H2Error(H2_ERROR_FORMAT, "parents of a far pair are not a near pair");
-            d += offc[j] + (int64_t)offc[k] * ld;
-            cb2l.add(I->data + H.offS[e], H.rank[gj], d, ld, H.rank[gj], H.rank[Pc.a + k], 1);
-          }
-          // parent basis: rows of child j are [E_j; 0]
-          if (!is_top) {
-            const int tau = H.parent[gj];
-            const int kp = H.rank[tau];
-            const int t = tau - pa;
-            cb2l.add(I->data + H.offE[gj], H.rank[gj], Vnext.p + PN->offV[t] + offc[j],
-                     PN->n[t], H.rank[gj], kp, 0);
-          }
-        }
-      };
+      // close-out on the device from the level's pattern (uploaded at the
+      // height start and still staged) and the next level's
+      CloseLevel<T> cl{};
       {
-        const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-        const int nt = std::max(1, std::min(nth, Pc.nl / 64));
-        std::vector<CopyBatch<T>> pc(nt), pc2(nt);
-        std::vector<std::thread> th;
-        std::vector<std::exception_ptr> errs(nt);
-        auto run = [&](int t) {
-          try {
-            close_rows((int)((int64_t)Pc.nl * t / nt), (int)((int64_t)Pc.nl * (t + 1) / nt), pc[t],
-                       pc2[t]);
-          } catch (...) {
-            errs[t] = std::current_exception();
-          }
-        };
-        for (int t = 1; t < nt; ++t) th.emplace_back(run, t);
-        run(0);
-        for (auto& x : th) x.join();
-        for (auto& e : errs)
-          if (e) std::rethrow_exception(e);
-        for (int t = 0; t < nt; ++t) {
-          cb.append(pc[t]);
-          cb2.append(pc2[t]);
+        const SchurLevel<T>& SL = lvh[q];
+        cl.pptr = SL.pptr;
+        cl.pcol = SL.pcol;
+        cl.poff = SL.poff;
+        cl.kind = SL.kind;
+        cl.n = SL.n;
+        cl.r = rdev.p + I->rbase;
+        cl.D = Sc->D.p;
+        cl.F = I->Fbuf.p;
+        std::vector<int32_t> par(Pc.nl);
+        for (int j = 0; j < Pc.nl; ++j) par[j] = H.parent[Pc.a + j] - pa;
+        cl.par = ar.put(par);
+        cl.offc = ar.put(offc);
+        cl.nl = Pc.nl;
+        cl.a = Pc.a;
+        cl.pa = pa;
+        cl.nnz = (int64_t)Pc.pcol.size();
+        cl.far_ptr = H.far_ptr_d.p;
+        cl.far_col = H.far_col_d.p;
+        cl.offS = H.offS_d.p;
+        cl.offE = H.offE_d.p;
+        cl.rank = H.rank_d.p;
+        cl.data = I->data;
+        cl.far0 = H.far_ptr[Pc.a];
+        cl.nfar = H.far_ptr[Pc.a + Pc.nl] - cl.far0;
+        if (is_top) {
+          cl.top = 1;
+          cl.top_off = ar.put(F->top_off);
+          cl.ldtop = ldtop;
+          cl.M = Dn;
+        } else {
+          cl.top = 0;
+          cl.npptr = ar.put(PN->pptr);
+          cl.npcol = ar.put(PN->pcol);
+          cl.npoff = ar.put(PN->poff);
+          cl.nkind = ar.put(level_kinds(*PN));
+          cl.nn = ar.put(PN->n);
+          cl.noffV = ar.put(PN->offV);
+          cl.Dn = Dn;
+          cl.Fn = Fn;
+          cl.Vn = Vnext.p;
         }
+        ar.flush(s);
       }
-      // hand over buffers: current F and V retire after the copies complete
-      // (keep them alive until the sync at the end of the next height)
+      flop_model.get();
       F->stats.levels = (int)F->plans.size() - (is_top ? 0 : 1);
       I->F->stats.max_colors = std::max(I->F->stats.max_colors, Pc.ncolors);
+      plan_ms += ms_since(tpl);
+      if (!is_top) launch_fill<T>(Vnext.p, Vnext.n, T(0), s);  // zero rows of [E_c; 0]
+      {
+        auto m6 = mark(6);
+        launch_closeout<T>(cl, 0, ctx->d_err.p, s);
+        launch_closeout<T>(cl, 1, ctx->d_err.p, s);
+        close_mark(m6);
+      }
       if (!is_top) {
-        // zero the V buffer before the copies of E
-        // (done through a fill ahead of the copy batch)
-        launch_fill<T>(Vnext.p, Vnext.n, T(0), s);
+        // the next level's F and V move to the instance; the current ones
+        // are released here, stream-ordered after the close-out that reads them
         std::swap(I->Vbuf, Vnext);
         std::swap(I->Fbuf, Fnext);
         I->li = F->plans.size() - 1;
         I->lev = plev;
-        // Vnext/Fnext now hold the previous level's buffers: free after the copies
-        plan_ms += ms_since(tpl);
-        auto m6 = mark(6);
-        cb.launch(ar, s);
-        cb2.launch(ar, s);
-        close_mark(m6);
-        cb = CopyBatch<T>();
-        cb2 = CopyBatch<T>();
-        H2_HIP(hipStreamSynchronize(s));
-        ar.reset();
       } else {
-        plan_ms += ms_since(tpl);
-        auto m6 = mark(6);
-        cb.launch(ar, s);
-        cb2.launch(ar, s);
-        close_mark(m6);
-        cb = CopyBatch<T>();
-        cb2 = CopyBatch<T>();
-        H2_HIP(hipStreamSynchronize(s));
-        ar.reset();
         I->done = true;
         I->Fbuf.release();
         I->Vbuf.release();
       }
     }
+    // staged descriptors of the level (patterns included) stay until here
+    H2_HIP(hipStreamSynchronize(s));
+    ar.reset();
     // the V fills must precede the E copies: the fills above were enqueued
     // before each instance's copy batch launch, so stream order holds.
     H2_HIP(hipGetLastError());
@@ -1314,6 +1276,8 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     int herr = 0;
     H2_HIP(hipMemcpy(&herr, ctx->d_err.p, sizeof(int), hipMemcpyDeviceToHost));
     if (herr & 1) throw H2Error(H2_ERROR_SINGULAR, "zero pivot in the dense top block");
+    if (herr & 8)
+      throw H2Error(H2_ERROR_FORMAT, "close-out destination missing from the next level");
     ar.reset();
   }
   phase_ms[8] = plan_ms;

@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <deque>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -215,7 +216,8 @@ struct h2_context_s {
   std::string err;
   DevMem mem;
   DevTracker tr;            // the context's own work arrays
-  DevArray<int> d_err;      // device error word: bit0 zero pivot, bit1 non-finite
+  DevArray<int> d_err;      // device error word: bit0 zero pivot, bit1 non-finite,
+                            // bit2 Schur contributors, bit3 close-out destination
   DescArena arena;
   // partial tiles of split skinny GEMMs (grown on demand, after a stream sync)
   DevArray<float> parts32;
@@ -240,6 +242,9 @@ struct h2_matrix_s {
   DevTracker tr;
   DevArray<double> data;
   DevArray<int64_t> perm_d;
+  // structure the level close-out reads on the device
+  DevArray<int64_t> far_ptr_d, offS_d, offE_d;
+  DevArray<int32_t> far_col_d, rank_d;
   int size(int q) const { return (int)(ie[q] - ib[q]); }
   int level_of(int q) const {
     int l = 0;
@@ -300,7 +305,7 @@ struct h2_factor_s {
   std::vector<int64_t> ib, ie;
   std::vector<int> lp, parent, cp;
   DevArray<int64_t> perm_d;
-  std::vector<LevelPlan> plans;          // leaf level first
+  std::deque<LevelPlan> plans;           // leaf level first (stable references)
   std::vector<LevelStore<double>> st64;  // per level (FP64 factors)
   std::vector<LevelStore<float>> st32;   // per level (FP32 factors)
   // top

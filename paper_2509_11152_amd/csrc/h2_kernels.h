@@ -108,6 +108,52 @@ template <class T> struct SchurLevel {
   int32_t pad0;
   int64_t rows0;
 };
+// Close-out of one level into the next level's blocks or the dense top block
+// (Section 2.1, level transition), found on the device from the level's
+// pattern.  Pass 0: for every pattern entry (j, k) the skeleton part, rows
+// [r_j, n_j) x columns [r_k, n_k), of D(j, k) or of the fill (stored, or the
+// stored (k, j) read transposed) goes to rows offc[j].., columns offc[k].. of
+// the parents' block (p(j), p(k)); a next-level fill entry with p(k) < p(j) is
+// written through its stored mirror instead.  Pass 1 (after pass 0): the far
+// couplings S_jk are added at the same place (S~ = [S 0; 0 0]) and the
+// transfers E_j copied to rows offc[j].. of the parent's next basis.
+template <class T> struct CloseLevel {
+  // the level being closed (a: its first global cluster, pa: the next level's)
+  const int64_t* pptr;
+  const int32_t* pcol;
+  const int64_t* poff;
+  const int8_t* kind;     // 0 near, 1 stored fill, 2 fill read from its mirror
+  const int32_t* n;
+  const int32_t* r;
+  const T* D;
+  const T* F;
+  const int32_t* par;     // local parent of each cluster
+  const int32_t* offc;    // skeleton row offset of each cluster in its parent
+  int32_t nl, a, pa, top;
+  int64_t nnz;
+  // next level (top == 0)
+  const int64_t* npptr;
+  const int32_t* npcol;
+  const int64_t* npoff;
+  const int8_t* nkind;
+  const int32_t* nn;      // next-level orders
+  const int64_t* noffV;   // next-level basis offsets
+  T* Dn;
+  T* Fn;
+  T* Vn;
+  // dense top block (top == 1)
+  const int64_t* top_off;
+  int64_t ldtop;
+  T* M;
+  // matrix: far lists, couplings, transfers (global cluster ids)
+  const int64_t* far_ptr;
+  const int32_t* far_col;
+  const int64_t* offS;
+  const int64_t* offE;
+  const int32_t* rank;
+  const T* data;
+  int64_t far0, nfar;     // far entries of the level's rows
+};
 constexpr int kSchurMaxContrib = 32;
 // one Schur / fill-in target found on the device: global row g (instance row
 // offset + j), pattern entry e = (j, k), contributors (bit x: the x-th
@@ -274,6 +320,10 @@ void launch_trsm(const TrsmTask<T>* tasks, int ntasks, const int32_t* dyn, int m
                  hipStream_t s, int lds = kLdsBytes);
 template <class T, class S>
 void launch_copy(const CTask<T, S>* tasks, int ntasks, int64_t ntiles, hipStream_t s);
+// pass 0 or 1 of the close-out; err bit 3: a destination missing from the
+// next level's pattern
+template <class T> void launch_closeout(const CloseLevel<T>& cl, int pass, int* err, hipStream_t s);
+
 template <class T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t s);
 template <class T, class S>

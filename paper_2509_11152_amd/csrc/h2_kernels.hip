@@ -1814,6 +1814,131 @@ void launch_copy(const CTask<T, S>* tasks, int ntasks, int64_t ntiles, hipStream
   hipLaunchKernelGGL((k_copy<T, S>), dim3((unsigned)ntiles), dim3(256), 0, s, tasks, ntasks);
 }
 
+// ---------------------------------------------------------------------------
+// Level close-out (CloseLevel): one wave per pattern entry (pass 0) or per far
+// entry / cluster (pass 1).
+// ---------------------------------------------------------------------------
+// row of entry e in a CSR row pointer of n rows (largest j with ptr[j] <= e)
+__device__ inline int csr_row(const int64_t* ptr, int n, int64_t e) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ptr[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// entry (t, s) of a sorted CSR pattern, or -1
+__device__ inline int64_t csr_find(const int64_t* ptr, const int32_t* col, int t, int s) {
+  int64_t a = ptr[t], b = ptr[t + 1];
+  const int64_t end = b;
+  while (a < b) {
+    const int64_t m = (a + b) >> 1;
+    if (col[m] < s) a = m + 1; else b = m;
+  }
+  return (a < end && col[a] == s) ? a : -1;
+}
+
+// dst (ldd) = or += the rows x cols block of src (lds), read transposed when
+// srcT (element (r, c) at src[c + r lds]); one wave, the source read along
+// its contiguous dimension
+template <class T>
+__device__ inline void wave_block_copy(const T* src, int64_t lds, bool srcT, T* dst, int64_t ldd,
+                                       int rows, int cols, bool add, int lane) {
+  const gptr<const T> sg = gmem(src);
+  const gptr<T> dg = gmem(dst);
+  const int tot = rows * cols;
+  for (int e = lane; e < tot; e += 64) {
+    int r, c;
+    if (srcT) {
+      c = e % cols;
+      r = e / cols;
+    } else {
+      r = e % rows;
+      c = e / rows;
+    }
+    const T v = srcT ? sg[c + (int64_t)r * lds] : sg[r + (int64_t)c * lds];
+    const gptr<T> d = dg + r + (int64_t)c * ldd;
+    *d = add ? *d + v : v;
+  }
+}
+
+// destination block of parents (pt, ps) and its leading dimension; false
+// when the block is written through its mirror (or is missing: err bit 3)
+template <class T>
+__device__ inline bool close_dest(const CloseLevel<T>& L, int pt, int ps, bool far, T*& d,
+                                  int64_t& ld, int* err) {
+  if (L.top) {
+    ld = L.ldtop;
+    d = L.M + L.top_off[pt] + L.top_off[ps] * ld;
+    return true;
+  }
+  const int64_t en = csr_find(L.npptr, L.npcol, pt, ps);
+  const int nk = en >= 0 ? L.nkind[en] : -1;
+  if (en < 0 || (far && nk != 0)) {
+    atomicOr(err, 8);
+    return false;
+  }
+  if (nk == 2) return false;
+  ld = L.nn[pt];
+  d = (nk == 1 ? L.Fn : L.Dn) + L.npoff[en];
+  return true;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_closeout(CloseLevel<T> L, int pass, int* err) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  if (pass == 0) {
+    for (int64_t e = w0; e < L.nnz; e += nw) {
+      const int j = csr_row(L.pptr, L.nl, e);
+      const int k = L.pcol[e];
+      const int nj = L.n[j], nk = L.n[k], rj = L.r[j], rk = L.r[k];
+      const int kj = nj - rj, kk = nk - rk;
+      if (kj <= 0 || kk <= 0) continue;
+      T* d;
+      int64_t ld;
+      if (!close_dest(L, L.par[j], L.par[k], false, d, ld, err)) continue;
+      d += L.offc[j] + (int64_t)L.offc[k] * ld;
+      const int kd = L.kind[e];
+      if (kd == 2)
+        wave_block_copy(L.F + L.poff[e] + rk + (int64_t)rj * nk, nk, true, d, ld, kj, kk, true,
+                        lane);
+      else
+        wave_block_copy((kd == 1 ? L.F : L.D) + L.poff[e] + rj + (int64_t)rk * nj, nj, false, d,
+                        ld, kj, kk, kd == 1, lane);
+    }
+    return;
+  }
+  const int64_t nq = L.nfar + (L.top ? 0 : L.nl);
+  for (int64_t q = w0; q < nq; q += nw) {
+    if (q < L.nfar) {
+      const int64_t e = L.far0 + q;
+      const int j = csr_row(L.far_ptr + L.a, L.nl, e);
+      const int gj = L.a + j, gk = L.far_col[e];
+      T* d;
+      int64_t ld;
+      if (!close_dest(L, L.par[j], L.par[gk - L.a], true, d, ld, err)) continue;
+      d += L.offc[j] + (int64_t)L.offc[gk - L.a] * ld;
+      wave_block_copy(L.data + L.offS[e], L.rank[gj], false, d, ld, L.rank[gj], L.rank[gk], true,
+                      lane);
+    } else {
+      const int j = (int)(q - L.nfar), gj = L.a + j;
+      const int pt = L.par[j];
+      wave_block_copy(L.data + L.offE[gj], L.rank[gj], false, L.Vn + L.noffV[pt] + L.offc[j],
+                      L.nn[pt], L.rank[gj], L.rank[L.pa + pt], false, lane);
+    }
+  }
+}
+
+template <class T> void launch_closeout(const CloseLevel<T>& cl, int pass, int* err, hipStream_t s) {
+  const int64_t nq = pass == 0 ? cl.nnz : cl.nfar + (cl.top ? 0 : cl.nl);
+  if (nq <= 0) return;
+  const int64_t blocks = std::min<int64_t>((nq + 3) / 4, 16384);
+  hipLaunchKernelGGL(k_closeout<T>, dim3((unsigned)blocks), dim3(256), 0, s, cl, pass, err);
+}
+
 template <class T> __global__ void k_fill(T* p, int64_t n, T v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -2160,6 +2285,7 @@ void launch_check_finite(const double* X, int64_t n, int* flag, hipStream_t s) {
   template void launch_copy<T, double>(const CTask<T, double>*, int, int64_t, hipStream_t);   \
   template void launch_copy<T, float>(const CTask<T, float>*, int, int64_t, hipStream_t);     \
   template void launch_fill<T>(T*, int64_t, T, hipStream_t);                                  \
+  template void launch_closeout<T>(const CloseLevel<T>&, int, int*, hipStream_t);            \
   template void launch_gather_rows<T, double>(T*, int64_t, const double*, int64_t,            \
                                               const int64_t*, int64_t, int, hipStream_t);     \
   template void launch_scatter_rows<double, T>(double*, int64_t, const T*, int64_t,           \
