@@ -272,7 +272,9 @@ inline int64_t aug_work_elems(int n) { return 5 * (int64_t)n * n + 3 * (int64_t)
 // (outputs of few columns), where outputs with nsplit > 1 leave their chunks'
 // partial tiles in `parts` (64 x 16 or 64 x 32 each, column-major) for
 // launch_gemm_reduce; shape 2: 64 x 64 tiles, one workgroup per output (for
-// outputs of a few tiles)
+// outputs of a few tiles).  Shapes 1 and 3 plus 8: operands whose k index is
+// contiguous are read as 16-byte vectors, which takes the k-values of an
+// MFMA step out of ascending order (the sum is rounded differently)
 template <class T>
 void launch_gemm(const GOut<T>* outs, int nouts, const GCon<T>* cons, const int32_t* dyn,
                  int64_t ntiles, int shape, hipStream_t s, T* parts = nullptr);

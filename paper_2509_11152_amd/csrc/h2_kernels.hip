@@ -163,6 +163,20 @@ __global__ __launch_bounds__(256) void k_gemm(const GOut<T>* __restrict__ outs, 
   }
 }
 
+// 16-byte vector of T read from 4- (8-) byte aligned global memory
+template <class T> struct VecK;
+template <> struct VecK<float> {
+  typedef float __attribute__((ext_vector_type(4), aligned(4))) type;
+  static constexpr int n = 4;
+};
+template <> struct VecK<double> {
+  typedef double __attribute__((ext_vector_type(2), aligned(8))) type;
+  static constexpr int n = 2;
+};
+template <class T> __device__ inline typename VecK<T>::type ld_veck(gptr<const T> p) {
+  return *reinterpret_cast<const __attribute__((address_space(1))) typename VecK<T>::type*>(p);
+}
+
 // Skinny variant for outputs of few columns (the solves' right-hand sides):
 // a 64 x TN tile (TN = 16 FN) is computed by all four waves, each taking
 // every fourth k-step with four row fragments and FN column fragments in
@@ -171,7 +185,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GOut<T>* __restrict__ outs, 
 // contributor list cut into nsplit chunks, one workgroup each; their partial
 // tiles (column-major 64 x TN) go to `parts` and k_gemm_reduce adds them in
 // chunk order.
-template <class T, int FN>
+template <class T, int FN, int VK>
 __global__ __launch_bounds__(256) void k_gemm_skinny(const GOut<T>* __restrict__ outs, int nouts,
                                                      const GCon<T>* __restrict__ cons,
                                                      const int32_t* __restrict__ dyn,
@@ -207,31 +221,64 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(const GOut<T>* __restrict__
   const int cps = (ncon + ns - 1) / ns;
   const int cb = o.cbeg + sidx * cps;
   const int ce = min(o.cend, cb + cps);
+  // wave w takes blocks w, w + 4, ... of KBLK = 4 VK k-values, NB blocks in
+  // flight (64 k per round of the workgroup); in a block, lane group kq
+  // holds k = kb + VK kq + s for MFMA step s, so that with VK > 1 operands
+  // with k contiguous (B, and A when transposed) are read as one 16-byte
+  // vector.  VK = 1 keeps the plain ascending k order of every wave.
+  constexpr int KBLK = 4 * VK;
+  constexpr int NB = 64 / (4 * KBLK);
   for (int ci = cb; ci < ce; ++ci) {
     const GCon<T> g = cons[ci];
     const int k0 = g.k0d >= 0 ? dyn[g.k0d] : g.k0s;
     const int k1 = g.k1d >= 0 ? dyn[g.k1d] : g.k;
-    for (int kk = k0 + 4 * wave; kk < k1; kk += 16) {
-      const int kx = kk + kq;
-      const bool kok = kx < k1;
-      T bv[FN];
+    const gptr<const T> A = gmem(g.A), B = gmem(g.B);
+    for (int kb = k0 + wave * KBLK; kb < k1; kb += 4 * KBLK * NB) {
+      T av[NB][VK][4], bv[NB][VK][FN];
 #pragma unroll
-      for (int b = 0; b < FN; ++b) {
-        const int col = c0 + b * 16 + l16;
-        bv[b] = (kok && col < n1) ? g.B[kx + (int64_t)col * g.ldb] : T(0);
+      for (int q = 0; q < NB; ++q) {
+        const int kl = kb + q * 4 * KBLK + VK * kq;  // this lane's first k of the block
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+          const int col = c0 + b * 16 + l16;
+          if (VK > 1 && col < n1 && kl + VK <= k1) {
+            const typename VecK<T>::type v = ld_veck<T>(B + kl + (int64_t)col * g.ldb);
+#pragma unroll
+            for (int s2 = 0; s2 < VK; ++s2) bv[q][s2][b] = v[s2 % VecK<T>::n];
+          } else {
+#pragma unroll
+            for (int s2 = 0; s2 < VK; ++s2)
+              bv[q][s2][b] = (col < n1 && kl + s2 < k1) ? B[kl + s2 + (int64_t)col * g.ldb] : T(0);
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int row = r0 + a * 16 + l16;
+          if (VK > 1 && g.transA && row < m1 && kl + VK <= k1) {
+            const typename VecK<T>::type v = ld_veck<T>(A + kl + (int64_t)row * g.lda);
+#pragma unroll
+            for (int s2 = 0; s2 < VK; ++s2) av[q][s2][a] = v[s2 % VecK<T>::n];
+          } else {
+#pragma unroll
+            for (int s2 = 0; s2 < VK; ++s2) {
+              const int kx = kl + s2;
+              av[q][s2][a] = (kx < k1 && row < m1)
+                                 ? (g.transA ? A[kx + (int64_t)row * g.lda] : A[row + (int64_t)kx * g.lda])
+                                 : T(0);
+            }
+          }
+        }
       }
-      T av[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int row = r0 + a * 16 + l16;
-        av[a] = (kok && row < m1)
-                    ? (g.transA ? g.A[kx + (int64_t)row * g.lda] : g.A[row + (int64_t)kx * g.lda])
-                    : T(0);
-      }
+      for (int q = 0; q < NB; ++q)
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+        for (int s2 = 0; s2 < VK; ++s2) {
+          if (kb + q * 4 * KBLK + s2 >= k1) continue;
 #pragma unroll
-        for (int b = 0; b < FN; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b) acc[a][b] = mfma16(av[q][s2][a], bv[q][s2][b], acc[a][b]);
+        }
     }
   }
   // sum the four waves' tiles: waves 2 and 3 hand theirs to waves 0 and 1,
@@ -533,11 +580,18 @@ __global__ __launch_bounds__(256) void k_schur_enum(const SchurLevel<T>* __restr
 
 // workgroups loop over the targets: C -= sum of the contributors' products,
 // contributors ascending (bit order).  The active window of C is cut into
-// items of 16 rows x 32 columns (two 16 x 16 fragments), handed to the four
-// waves in turn, so blocks of any order up to a few hundred take no more
-// fragments than they cover; every item loads the operands of four k-steps
-// before their products.
-constexpr int kSchurKB = 4;
+// items of 32 x 32 (2 x 2 fragments of 16 x 16), handed to the four waves in
+// turn; C of an item is read before its products.  A multiplier block
+// D(i, k) is column-major with k contiguous, so every lane reads VK
+// consecutive k of its column as one 16-byte vector: MFMA step s of a block
+// of 4 VK k-values takes k = kb + VK kq + s in lane group kq, for the panel
+// D(j, i) as for the multipliers (any assignment of k to the steps gives the
+// same sum).
+// k-values a lane reads as one vector in the Schur update (FP64 keeps single
+// loads: its k order is then the plain ascending one), and blocks of 4 VK
+// k-values loaded ahead of their products
+template <class T> constexpr int schur_vk() { return sizeof(T) == 4 ? 4 : 1; }
+template <class T> constexpr int schur_nb() { return sizeof(T) == 4 ? 1 : 4; }
 template <class T>
 __global__ __launch_bounds__(256) void k_schur_apply(const SchurLevel<T>* __restrict__ lvs,
                                                      int ninst, int c,
@@ -545,7 +599,9 @@ __global__ __launch_bounds__(256) void k_schur_apply(const SchurLevel<T>* __rest
                                                      const SchurTarget* __restrict__ targets,
                                                      const int64_t* __restrict__ conts,
                                                      const int64_t* __restrict__ count) {
-  constexpr int CW = 2;  // column fragments per item
+  constexpr int VK = schur_vk<T>();
+  constexpr int KBLK = 4 * VK;
+  constexpr int kSchurNB = schur_nb<T>();
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, kq = lane >> 4;
@@ -562,15 +618,26 @@ __global__ __launch_bounds__(256) void k_schur_apply(const SchurLevel<T>* __rest
     const int n0 = L.color[k] <= c ? L.r[k] : 0;
     const gptr<const T> Dg = gmem((const T*)L.D);
     const gptr<T> C = gmem((L.kind[tg.e] == 1 ? L.F : L.D) + L.poff[tg.e]);
-    const int64_t ldc = nj;
-    const int nrg = (nj - m0 + 15) / 16;              // row fragments of the window
-    const int ncg = (nk - n0 + 16 * CW - 1) / (16 * CW);  // column items of the window
+    const int nrg = (nj - m0 + 31) / 32;  // row items of the window
+    const int ncg = (nk - n0 + 31) / 32;  // column items of the window
     for (int it = wave; it < nrg * ncg; it += 4) {
-      const int row = m0 + (it % nrg) * 16 + l16;
-      const int cb = n0 + (it / nrg) * 16 * CW;
-      typename Acc<T>::type acc[CW];
+      const int rb = m0 + (it % nrg) * 32;
+      const int cb = n0 + (it / nrg) * 32;
+      T cv[2][2][4];
 #pragma unroll
-      for (int b = 0; b < CW; ++b) acc[b] = (typename Acc<T>::type){0, 0, 0, 0};
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = rb + a * 16 + l16, col = cb + b * 16 + acc_row<T>(kq, i);
+            cv[a][b][i] = (row < nj && col < nk) ? C[row + col * nj] : T(0);
+          }
+      typename Acc<T>::type acc[2][2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = (typename Acc<T>::type){0, 0, 0, 0};
       int64_t cq = tg.cbeg;
       for (int x = 0; x < nc; ++x) {
         if (!((tg.mask >> x) & 1u)) continue;
@@ -580,39 +647,56 @@ __global__ __launch_bounds__(256) void k_schur_apply(const SchurLevel<T>* __rest
         const int k1 = L.r[i];
         const gptr<const T> A = Dg + L.poff[R.eji[x]];  // D(j, i), n_j x n_i
         const gptr<const T> B = Dg + L.poff[eb];        // D(i, k), n_i x n_k
-        for (int kb = 0; kb < k1; kb += 4 * kSchurKB) {
-          T av[kSchurKB], bv[kSchurKB][CW];
+        for (int kb = 0; kb < k1; kb += kSchurNB * KBLK) {
+          T av[kSchurNB][VK][2], bv[kSchurNB][VK][2];
 #pragma unroll
-          for (int qq = 0; qq < kSchurKB; ++qq) {
-            const int kx = kb + 4 * qq + kq;
-            const bool kok = kx < k1;
-            av[qq] = (kok && row < nj) ? A[row + (int64_t)kx * nj] : T(0);
+          for (int q = 0; q < kSchurNB; ++q) {
+            const int kl = kb + q * KBLK + VK * kq;  // this lane's first k of the block
 #pragma unroll
-            for (int b = 0; b < CW; ++b) {
+            for (int b = 0; b < 2; ++b) {
               const int col = cb + b * 16 + l16;
-              bv[qq][b] = (kok && col < nk) ? B[kx + (int64_t)col * ni] : T(0);
+              if (VK > 1 && col < nk && kl + VK <= k1) {
+                const typename VecK<T>::type v = ld_veck<T>(B + (kl + col * ni));
+#pragma unroll
+                for (int s2 = 0; s2 < VK; ++s2) bv[q][s2][b] = v[s2 % VecK<T>::n];
+              } else {
+#pragma unroll
+                for (int s2 = 0; s2 < VK; ++s2)
+                  bv[q][s2][b] = (col < nk && kl + s2 < k1) ? B[kl + s2 + col * ni] : T(0);
+              }
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+              const int row = rb + a * 16 + l16;
+#pragma unroll
+              for (int s2 = 0; s2 < VK; ++s2)
+                av[q][s2][a] = (row < nj && kl + s2 < k1) ? A[row + (kl + s2) * nj] : T(0);
             }
           }
           // operands swapped: the accumulator holds the transposed fragment,
           // lane l16 owning row l16 (coalesced epilogue)
 #pragma unroll
-          for (int qq = 0; qq < kSchurKB; ++qq) {
-            if (kb + 4 * qq >= k1) break;
+          for (int q = 0; q < kSchurNB; ++q)
 #pragma unroll
-            for (int b = 0; b < CW; ++b) acc[b] = mfma16(bv[qq][b], av[qq], acc[b]);
-          }
+            for (int s2 = 0; s2 < VK; ++s2) {
+              if (kb + q * KBLK + s2 >= k1) continue;
+#pragma unroll
+              for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(bv[q][s2][b], av[q][s2][a], acc[a][b]);
+            }
         }
       }
-      if (row < nj) {
 #pragma unroll
-        for (int b = 0; b < CW; ++b)
+      for (int a = 0; a < 2; ++a) {
+        const int row = rb + a * 16 + l16;
+        if (row >= nj) continue;
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int col = cb + b * 16 + acc_row<T>(kq, i);
-            if (col < nk) {
-              const gptr<T> p = C + row + (int64_t)col * ldc;
-              *p = *p - acc[b][i];
-            }
+            if (col < nk) C[row + col * nj] = cv[a][b][i] - acc[a][b][i];
           }
       }
     }
@@ -640,19 +724,28 @@ void launch_gemm(const GOut<T>* outs, int nouts, const GCon<T>* cons, const int3
                        nouts, cons, dyn);
   else if (shape == 2)
     hipLaunchKernelGGL((k_gemm_out<T>), dim3((unsigned)nouts), dim3(256), 0, s, outs, cons, dyn);
-  else if (shape == 3)
-    hipLaunchKernelGGL((k_gemm_skinny<T, 2>), dim3((unsigned)ntiles), dim3(256), 0, s, outs,
-                       nouts, cons, dyn, parts);
-  else
-    hipLaunchKernelGGL((k_gemm_skinny<T, 1>), dim3((unsigned)ntiles), dim3(256), 0, s, outs,
-                       nouts, cons, dyn, parts);
+  else if ((shape & 7) == 3) {
+    if (shape & 8)
+      hipLaunchKernelGGL((k_gemm_skinny<T, 2, VecK<T>::n>), dim3((unsigned)ntiles), dim3(256), 0,
+                         s, outs, nouts, cons, dyn, parts);
+    else
+      hipLaunchKernelGGL((k_gemm_skinny<T, 2, 1>), dim3((unsigned)ntiles), dim3(256), 0, s, outs,
+                         nouts, cons, dyn, parts);
+  } else {
+    if (shape & 8)
+      hipLaunchKernelGGL((k_gemm_skinny<T, 1, VecK<T>::n>), dim3((unsigned)ntiles), dim3(256), 0,
+                         s, outs, nouts, cons, dyn, parts);
+    else
+      hipLaunchKernelGGL((k_gemm_skinny<T, 1, 1>), dim3((unsigned)ntiles), dim3(256), 0, s, outs,
+                         nouts, cons, dyn, parts);
+  }
 }
 
 template <class T>
 void launch_gemm_reduce(const GOut<T>* routs, int nouts, const T* parts, int64_t ntiles,
                         int shape, hipStream_t s) {
   if (ntiles <= 0 || nouts <= 0) return;
-  if (shape == 3)
+  if ((shape & 7) == 3)
     hipLaunchKernelGGL((k_gemm_reduce<T, 32>), dim3((unsigned)ntiles), dim3(256), 0, s, routs,
                        nouts, parts);
   else
@@ -1699,13 +1792,19 @@ __global__ __launch_bounds__(256) void k_trsm_wave(const TrsmTask<T>* __restrict
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63;
   const int nu = (r + 63) >> 6;
-  for (int col = c0 + wave; col < tk.ncols; col += 4) {
-    T* b = tk.B + (int64_t)col * tk.ldb;
-    T x[4];
+  // every wave carries CB right-hand side columns through one sweep: each
+  // factor entry read from LDS serves all of them, and the substitution chain
+  // is walked once per CB columns
+  constexpr int CB = 8;
+  for (int col0 = c0 + wave * CB; col0 < tk.ncols; col0 += 4 * CB) {
+    const int ncb = min(CB, tk.ncols - col0);
+    T* b = tk.B + (int64_t)col0 * tk.ldb;
+    T x[4][CB];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int i = lane + 64 * u;
-      x[u] = i < r ? b[perm[i]] : T(0);
+#pragma unroll
+      for (int c = 0; c < CB; ++c) x[u][c] = (i < r && c < ncb) ? b[perm[i] + (int64_t)c * tk.ldb] : T(0);
     }
     // L y = P b (unit lower)
 #pragma unroll
@@ -1714,11 +1813,17 @@ __global__ __launch_bounds__(256) void k_trsm_wave(const TrsmTask<T>* __restrict
       const int jn = min(64, r - 64 * u);
       for (int jj = 0; jj < jn; ++jj) {
         const int j = 64 * u + jj;
-        const T bj = __shfl(x[u], jj, 64);
+        T bj[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) bj[c] = __shfl(x[u][c], jj, 64);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = lane + 64 * v;
-          if (v >= u && i > j && i < r) x[v] -= S[i + j * r] * bj;
+          if (v >= u && i > j && i < r) {
+            const T l = S[i + j * r];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) x[v][c] -= l * bj[c];
+          }
         }
       }
     }
@@ -1729,19 +1834,31 @@ __global__ __launch_bounds__(256) void k_trsm_wave(const TrsmTask<T>* __restrict
       const int jn = min(64, r - 64 * u);
       for (int jj = jn - 1; jj >= 0; --jj) {
         const int j = 64 * u + jj;
-        const T xj = __shfl(x[u], jj, 64) / S[j + j * r];
-        if (lane == jj) x[u] = xj;
+        const T d = S[j + j * r];
+        T xj[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          xj[c] = __shfl(x[u][c], jj, 64) / d;
+          if (lane == jj) x[u][c] = xj[c];
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = lane + 64 * v;
-          if (v <= u && i < j) x[v] -= S[i + j * r] * xj;
+          if (v <= u && i < j) {
+            const T uu = S[i + j * r];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) x[v][c] -= uu * xj[c];
+          }
         }
       }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int i = lane + 64 * u;
-      if (i < r) b[i] = x[u];
+      if (i < r)
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+          if (c < ncb) b[i + (int64_t)c * tk.ldb] = x[u][c];
     }
   }
 }

@@ -20,14 +20,59 @@ using namespace h2k;
 
 namespace {
 
-// contributor K per chunk above which a skinny output is split over workgroups
+// a skinny output is split over workgroups into chunks of about kSplitK
+// contributor K (at most `maxsplit` chunks when that is set)
 constexpr int64_t kSplitK = 192;
+// FP32 solves and the product: fewer, longer chunks (fewer partial tiles);
+// FP64 solves keep the unlimited split
+constexpr int kMaxSplit = 8;
 // block products with few right-hand sides use skinny tiles (K split over the
 // four waves, long contributor lists over workgroups): 64 x 16 up to 16
 // columns, 64 x 32 up to 64; wider blocks use 64 x 64 tiles
 constexpr int kSkinnyCols = 64;
 inline int product_shape(int nrhs) { return nrhs <= 16 ? 1 : nrhs <= kSkinnyCols ? 3 : 0; }
-inline int tile_cols(int shape) { return shape == 1 ? 16 : shape == 3 ? 32 : 64; }
+inline int tile_cols(int shape) { return (shape & 7) == 1 ? 16 : (shape & 7) == 3 ? 32 : 64; }
+
+// Append-only host image of descriptor arrays, each 256-byte aligned, kept in
+// chunks that are never moved or zero-filled; each chunk covers a contiguous
+// range of the device image it is uploaded into.
+struct HostImage {
+  static constexpr size_t kChunk = (size_t)64 << 20;
+  struct Chunk {
+    std::unique_ptr<char[]> h;
+    size_t dev_off = 0, used = 0, cap = 0;
+  };
+  std::vector<Chunk> chunks;
+  size_t total = 0;
+  bool empty() const { return total == 0; }
+  size_t size() const { return total; }
+  size_t append(const void* p, size_t bytes) {
+    const size_t off = (total + 255) & ~(size_t)255;
+    if (chunks.empty() || off - chunks.back().dev_off + bytes > chunks.back().cap) {
+      Chunk c;
+      c.cap = std::max(kChunk, bytes);
+      c.h.reset(new char[c.cap]);
+      c.dev_off = off;
+      chunks.push_back(std::move(c));
+    }
+    Chunk& c = chunks.back();
+    std::memcpy(c.h.get() + (off - c.dev_off), p, bytes);
+    c.used = off - c.dev_off + bytes;
+    total = off + bytes;
+    return off;
+  }
+  // copy into the device image dev (at least size() bytes); with a stream the
+  // copies are asynchronous and the image must outlive them
+  void upload(char* dev, hipStream_t s, bool async) const {
+    for (const Chunk& c : chunks) {
+      if (c.used == 0) continue;
+      if (async)
+        H2_HIP(hipMemcpyAsync(dev + c.dev_off, c.h.get(), c.used, hipMemcpyHostToDevice, s));
+      else
+        H2_HIP(hipMemcpy(dev + c.dev_off, c.h.get(), c.used, hipMemcpyHostToDevice));
+    }
+  }
+};
 
 // Where a solve's launches go: straight to the stream (descriptors staged
 // through the context's arena), or into a plan that later solves with the
@@ -39,15 +84,12 @@ template <class T> struct Emit {
   h2_context_s* ctx = nullptr;
   hipStream_t s = nullptr;
   bool rec = false;
-  std::vector<char> img;
+  HostImage img;
   std::vector<Step> steps;
   int64_t parts_need = 0;  // elements of partial-tile scratch the recorded steps use
 
   template <class X> size_t stage(const std::vector<X>& v) {
-    const size_t off = (img.size() + 255) & ~(size_t)255;
-    img.resize(off + sizeof(X) * v.size());
-    std::memcpy(img.data() + off, v.data(), sizeof(X) * v.size());
-    return off;
+    return img.append(v.data(), sizeof(X) * v.size());
   }
   void strip(const std::vector<STask<T>>& t, int64_t strips, int maxn) {
     if (t.empty()) return;
@@ -148,10 +190,14 @@ template <class T> struct Emit {
 template <class T> struct GemmBatch {
   std::vector<GOut<T>> outs;
   std::vector<GCon<T>> cons;
+  std::vector<int64_t> kss;  // contributor K of every output
   int64_t tiles = 0, ptiles = 0, rtiles = 0;
   int shape, TM, TN;
   bool pending = false;
-  explicit GemmBatch(int sh) : shape(sh), TM(64), TN(tile_cols(sh)) {}
+  bool veck;    // vector loads along k (shape + 8)
+  int maxsplit;  // chunks per output at most (0: no limit)
+  GemmBatch(int sh, bool vk, int ms)
+      : shape(sh), TM(64), TN(tile_cols(sh)), veck(vk), maxsplit(ms) {}
   // begin output C[m0:m, n0:n] = beta C + alpha sum ...
   void out(T* C, int64_t ldc, int m0, int m, int n0, int n, T alpha, T beta) {
     end();
@@ -190,8 +236,8 @@ template <class T> struct GemmBatch {
     cons.push_back(g);
     outs.back().cend = (int)cons.size();
   }
-  // close the current output (drops it when it has no tiles); a skinny output
-  // with a long contributor list is split into chunks of about kSplitK
+  // close the current output (drops it when it has no tiles); its split is
+  // chosen at launch
   void end() {
     if (!pending) return;
     pending = false;
@@ -202,30 +248,47 @@ template <class T> struct GemmBatch {
       outs.pop_back();
       return;
     }
-    int ns = 1;
-    if (shape == 1 || shape == 3) {
-      int64_t ks = 0;
-      for (int c = o.cbeg; c < o.cend; ++c) ks += cons[c].k - cons[c].k0s;
-      ns = (int)std::max<int64_t>(1, std::min<int64_t>(o.cend - o.cbeg, (ks + kSplitK - 1) / kSplitK));
-    }
-    o.nsplit = ns;
-    tiles += t * ns;
-    if (ns > 1) {
-      o.part0 = ptiles;
-      ptiles += t * ns;
-      o.rtile0 = rtiles;
-      rtiles += t;
+    int64_t ks = 0;
+    for (int c = o.cbeg; c < o.cend; ++c) ks += cons[c].k - cons[c].k0s;
+    kss.push_back(ks);
+  }
+  // tiles, partial tiles and reduction tiles of every output: skinny outputs
+  // with a long contributor list are cut into chunks (the choice depends on
+  // the output alone, so batched and single launches round alike)
+  void split() {
+    tiles = ptiles = rtiles = 0;
+    for (size_t q = 0; q < outs.size(); ++q) {
+      GOut<T>& o = outs[q];
+      const int64_t t = (int64_t)o.tm * o.tn;
+      int ns = 1;
+      if (shape == 1 || shape == 3) {
+        int64_t m = std::min<int64_t>(o.cend - o.cbeg, (kss[q] + kSplitK - 1) / kSplitK);
+        if (maxsplit > 0) m = std::min<int64_t>(m, maxsplit);
+        ns = (int)std::max<int64_t>(1, m);
+      }
+      o.nsplit = ns;
+      o.tile0 = tiles;
+      tiles += t * ns;
+      if (ns > 1) {
+        o.part0 = ptiles;
+        ptiles += t * ns;
+        o.rtile0 = rtiles;
+        rtiles += t;
+      }
     }
   }
   void launch(Emit<T>& em) {
     end();
     if (outs.empty()) return;
+    split();
     std::vector<GOut<T>> routs;
     for (auto& o : outs)
       if (o.nsplit > 1) routs.push_back(o);
-    em.gemm(outs, cons, tiles, shape, ptiles, routs, rtiles);
+    em.gemm(outs, cons, tiles, (shape == 1 || shape == 3) && veck ? shape + 8 : shape, ptiles,
+            routs, rtiles);
     outs.clear();
     cons.clear();
+    kss.clear();
     tiles = ptiles = rtiles = 0;
   }
 };
@@ -330,7 +393,9 @@ template <class T> struct ColourTasks {
   StripBatch<T> sb;
   std::vector<TrsmTask<T>> trs;
   GemmBatch<T> gb;
-  explicit ColourTasks(int shape) : gb(shape) {}
+  // FP32 products read k-contiguous operands as vectors; FP64 solves keep
+  // the ascending k order and the finer split
+  explicit ColourTasks(int shape) : gb(shape, sizeof(T) == 4, sizeof(T) == 4 ? kMaxSplit : 0) {}
 };
 
 // f(0) .. f(n - 1) on up to 16 threads (the calling thread included), each
@@ -476,7 +541,7 @@ void solve_body(Emit<T>& em, std::vector<SolveInst<T>>& si, int nrhs) {
       const int w = (int)std::min<int64_t>(nb, n - j0);
       em.trsm_block(M + j0 + j0 * n, n, b + j0, ldb2, w, nrhs, 1);
       if (j0 + w < n) {
-        GemmBatch<T> gb(shape);
+        GemmBatch<T> gb(shape, sizeof(T) == 4, sizeof(T) == 4 ? kMaxSplit : 0);
         gb.out(b + j0 + w, ldb2, 0, (int)(n - j0 - w), 0, nrhs, T(-1), T(1));
         gb.con(M + (j0 + w) + j0 * n, n, 0, b + j0, ldb2, 0, w);
         gb.launch(em);
@@ -486,7 +551,7 @@ void solve_body(Emit<T>& em, std::vector<SolveInst<T>>& si, int nrhs) {
       const int w = (int)std::min<int64_t>(nb, n - j0);
       em.trsm_block(M + j0 + j0 * n, n, b + j0, ldb2, w, nrhs, 0);
       if (j0 > 0) {
-        GemmBatch<T> gb(shape);
+        GemmBatch<T> gb(shape, sizeof(T) == 4, sizeof(T) == 4 ? kMaxSplit : 0);
         gb.out(b, ldb2, 0, (int)j0, 0, nrhs, T(-1), T(1));
         gb.con(M + j0 * n, n, 0, b + j0, ldb2, 0, w);
         gb.launch(em);
@@ -575,8 +640,7 @@ template <class T> struct Replay {
   }
   void take(Emit<T>& em, DevTracker* tr) {
     img.alloc(std::max<int64_t>((int64_t)em.img.size(), 1), tr);
-    if (!em.img.empty())
-      H2_HIP(hipMemcpy(img.p, em.img.data(), em.img.size(), hipMemcpyHostToDevice));
+    em.img.upload(img.p, nullptr, false);
     if (em.parts_need > 0) parts.alloc(em.parts_need, tr);
     steps = std::move(em.steps);
   }
@@ -719,7 +783,7 @@ void matvec_body(Emit<double>& em, const h2_matrix_s* H, const double* xt, doubl
   const int L = H->L;
   if (H->top >= 0) {
     // leaves: xh = U^T x
-    GemmBatch<double> gb(shape);
+    GemmBatch<double> gb(shape, true, kMaxSplit);
     for (int q = H->lp[L]; q < H->nn; ++q) {
       if (!H->rank[q]) continue;
       gb.out(hx(q), H->rank[q], 0, H->rank[q], 0, nrhs, 1.0, 0.0);
@@ -759,7 +823,7 @@ void matvec_body(Emit<double>& em, const h2_matrix_s* H, const double* xt, doubl
       gb.launch(em);
     }
   }
-  GemmBatch<double> gb(shape);
+  GemmBatch<double> gb(shape, true, kMaxSplit);
   for (int q = H->lp[L]; q < H->nn; ++q) {
     gb.out(yt + H->ib[q], N, 0, H->size(q), 0, nrhs, 1.0, 0.0);
     if (H->top >= 0 && H->rank[q])
@@ -850,8 +914,7 @@ void matvec_in(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, 
                                             std::to_string(cap) + " available");
   char* dimg = scratch + vec;
   double* parts = reinterpret_cast<double*>(dimg + img);
-  if (!em.img.empty())
-    H2_HIP(hipMemcpyAsync(dimg, em.img.data(), em.img.size(), hipMemcpyHostToDevice, s));
+  em.img.upload(dimg, s, true);
   launch_gather_rows<double, double>(xt, N, X, ldx, H->perm_d.p, N, nrhs, s);
   for (auto& st : em.steps) st(s, dimg, parts);
   launch_scatter_rows<double, double>(Y, ldy, yt, N, H->perm_d.p, N, nrhs, s);
