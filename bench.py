@@ -95,12 +95,17 @@ def copy_calibration():
 # device phases of the factorization (h2_stats indices 0..7) and their kernels
 PHASES = ["fill_row_qr", "augment", "project", "lu", "multipliers", "schur", "close_out", "top_lu"]
 KERNEL_OF = {"fill_row_qr": "k_rfactor", "augment": "k_augment", "project": "k_strip",
-             "lu": "k_lu", "multipliers": "k_trsm", "schur": "k_schur_enum + k_schur_apply",
-             "close_out": "k_copy", "top_lu": "k_panel_lu + k_laswp + k_trsm_block + k_gemm"}
+             "lu": "k_lu", "multipliers": "k_trsm_wave + k_trsm",
+             "schur": "k_schur_enum + k_schur_apply", "close_out": "k_closeout",
+             "top_lu": "k_panel_lu + k_laswp + k_trsm_block + k_gemm"}
+# the FP32 factorization reduces a fill row through its FP64 Gram matrix (FP64
+# MFMA) and a pivoted Cholesky instead of the Householder QR
+KERNEL_OF_F32 = dict(KERNEL_OF, fill_row_qr="k_gram + k_pchol_wave/k_pchol")
 # phases whose arithmetic runs on the vector ALU (Householder reductions,
 # Jacobi rotations, small LU and triangular solves); the others are priced
 # against MFMA or HBM by their algorithmic intensity
 ALU_PHASES = {"fill_row_qr", "augment", "lu", "multipliers"}
+ALU_PHASES_F32 = {"augment", "lu", "multipliers"}
 
 
 def roofline(st, dt):
@@ -109,6 +114,8 @@ def roofline(st, dt):
     launches on the library's stream, summed over the factorization).  Each
     phase 0..7 is one kernel, so rate = (work per launch) / (mean launch time)."""
     peak_f = PEAK[dt]
+    kernels = KERNEL_OF_F32 if dt == "f32" else KERNEL_OF
+    alu = ALU_PHASES_F32 if dt == "f32" else ALU_PHASES
     out = {}
     best = None
     for i, name in enumerate(PHASES):
@@ -116,15 +123,17 @@ def roofline(st, dt):
         fl, by, nl = st["phase_flops"][i], st["phase_bytes"][i], st["launches"][i]
         if t <= 0 or (fl <= 0 and by <= 0):
             continue
-        f_time = fl / (peak_f * 1e12)
+        # the FP32 fill-row Gram matrices are FP64 MFMA products
+        pk = PEAK["f64"] if (dt == "f32" and name == "fill_row_qr") else peak_f
+        f_time = fl / (pk * 1e12)
         b_time = by / (HBM_PEAK * 1e9)
-        if name in ALU_PHASES:
-            bound, ach, peak, unit = "alu", fl / t / 1e12, peak_f, "TFLOP/s"
+        if name in alu:
+            bound, ach, peak, unit = "alu", fl / t / 1e12, pk, "TFLOP/s"
         elif f_time >= b_time:
-            bound, ach, peak, unit = "mfma", fl / t / 1e12, peak_f, "TFLOP/s"
+            bound, ach, peak, unit = "mfma", fl / t / 1e12, pk, "TFLOP/s"
         else:
             bound, ach, peak, unit = "hbm", by / t / 1e9, HBM_PEAK, "GB/s"
-        out[name] = {"kernel": KERNEL_OF[name], "ms": t * 1e3, "launches": nl,
+        out[name] = {"kernel": kernels[name], "ms": t * 1e3, "launches": nl,
                      "ms_per_launch": t * 1e3 / max(nl, 1),
                      "flops": fl, "bytes": by, "bound": bound, "achieved": ach, "peak": peak,
                      "unit": unit, "frac": ach / peak}
@@ -138,7 +147,7 @@ def roofline(st, dt):
 
 
 # FP32 kernels of the phases whose HBM traffic the PMC summary records
-PMC_KERNEL = {"fill_row_qr": "h2k::k_rfactor<float>",
+PMC_KERNEL = {"fill_row_qr": "h2k::k_gram<float>",
               "augment": "h2k::k_augment<float, float, false>",
               "schur": "h2k::k_schur_apply<float>"}
 

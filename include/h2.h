@@ -42,12 +42,22 @@ typedef enum {
   H2_ERROR_UNSUPPORTED = 8       /* a size beyond what the kernels handle */
 } h2_status;
 
-/* Working precision of the factorization.  FP32: factor stored and computed
- * in FP32 (MFMA with FP32 accumulation), the fill row reduced by a Householder
- * QR (Section 2.1, second augmentation option).  FP32_GRAM: the same, except
- * that the augmentation works from the FP64 Gram matrix Y Y^T of each FP32
- * fill row and an FP64 eigendecomposition (Section 2.1, first option). */
-typedef enum { H2_PREC_FP64 = 0, H2_PREC_FP32 = 1, H2_PREC_FP32_GRAM = 2 } h2_prec;
+/* Working precision of the factorization.  FP64: the fill row reduced by a
+ * Householder QR (Section 2.1, second augmentation option).  The three FP32
+ * modes store and compute the factor in FP32 (MFMA with FP32 accumulation)
+ * and differ in how the augmentation sees the fill row Y:
+ *   FP32: Y Y^T formed in FP64 (Section 2.1, first option) and factored by a
+ *     Cholesky with diagonal pivoting, G = P R^T R P^T; the augmentation takes
+ *     the SVD of R P^T V_perp in FP32 (clusters of order above 128 take the
+ *     QR route);
+ *   FP32_GRAM: from the same FP64 Y Y^T, an FP64 eigendecomposition;
+ *   FP32_QR: a Householder QR of Y^T, as in FP64. */
+typedef enum {
+  H2_PREC_FP64 = 0,
+  H2_PREC_FP32 = 1,
+  H2_PREC_FP32_GRAM = 2,
+  H2_PREC_FP32_QR = 3
+} h2_prec;
 
 typedef struct h2_context_s* h2_context_t;
 typedef struct h2_matrix_s* h2_matrix_t;

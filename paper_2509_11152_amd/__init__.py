@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libh2rss.so")
 H2_PREC_FP64 = 0
 H2_PREC_FP32 = 1
 H2_PREC_FP32_GRAM = 2
+H2_PREC_FP32_QR = 3
 (INT_SIZES, INT_RANKS, INT_COLORS, INT_FILL, INT_NTOP, INT_LEVELS, INT_OFFSETS,
  INT_CLUSTER_OFFSETS, INT_OWNERS) = range(9)
 MAT_Q, MAT_BLOCK, MAT_TOP = range(3)

@@ -507,7 +507,8 @@ h2_status h2_factor_batched(h2_context_t ctx, int count, const h2_matrix_t* Hs, 
                             h2_prec prec, const h2_factor_opts* opts, h2_factor_t* Fs) {
   if (!ctx || count <= 0 || !Hs || !Fs) return H2_ERROR_INVALID_ARGUMENT;
   if (!(tol >= 0) || !std::isfinite(tol)) return H2_ERROR_INVALID_ARGUMENT;
-  if (prec != H2_PREC_FP64 && prec != H2_PREC_FP32 && prec != H2_PREC_FP32_GRAM)
+  if (prec != H2_PREC_FP64 && prec != H2_PREC_FP32 && prec != H2_PREC_FP32_GRAM &&
+      prec != H2_PREC_FP32_QR)
     return H2_ERROR_INVALID_ARGUMENT;
   h2_factor_opts o{};
   if (opts) o = *opts;

@@ -419,6 +419,8 @@ template <class T> struct ColourPlan {
   std::vector<GramTask<T>> gram;           // FP32: Gram matrices of the fill rows
   std::vector<FillRef<T>> grefs;
   int64_t gram_tiles = 0;
+  std::vector<CholTask<T>> chol;           // FP32: their pivoted Cholesky factors
+  int cmaxn = 1;
   std::vector<STask<T>> sl, sr;
   int64_t nsl = 0, nsr = 0;
   std::vector<LUTask<T>> lus;
@@ -436,8 +438,14 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
                        DevTracker* calltr, int lds) {
   hipStream_t s = ctx->stream;
   // FP32 with the Gram augmentation (Section 2.1, first option): the fill row
-  // enters the augmentation as its FP64 Gram matrix; otherwise the QR route
-  const bool gram_mode = sizeof(T) == 4 && !insts.empty() && insts[0].F->prec == H2_PREC_FP32_GRAM;
+  // enters the augmentation as its FP64 Gram matrix (gram_mode: FP64
+  // eigendecomposition; chol_mode: pivoted Cholesky factor, then the QR
+  // route's SVD); otherwise the QR route
+  const h2_prec prec = insts.empty() ? H2_PREC_FP64 : insts[0].F->prec;
+  const bool gram_mode = sizeof(T) == 4 && prec == H2_PREC_FP32_GRAM;
+  const bool chol_mode = sizeof(T) == 4 && prec == H2_PREC_FP32;
+  // chol_mode: this cluster's fill row goes through the Gram factor
+  auto use_chol = [&](int n) { return chol_mode && n <= kCholMaxOrder; };
   DescArena& ar = ctx->arena;
   ar.s = s;
   H2_HIP(hipMemsetAsync(ctx->d_err.p, 0, sizeof(int), s));
@@ -586,6 +594,9 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
           if (gram_mode) {
             w += 2 * aug_work_elems(P.n[i]);  // FP64 arithmetic in FP32 units
             gw += (int64_t)P.n[i] * P.n[i];
+          } else if (use_chol(P.n[i])) {
+            w += aug_work_elems(P.n[i]) + (int64_t)P.n[i] * P.n[i] + 4;
+            gw += (int64_t)P.n[i] * P.n[i] * (int64_t)rf_groups(rows, kGramChunk).size();
           } else {
             w += aug_work_elems(P.n[i]) + rf_scratch<T>(P.n[i], rows, lds);
           }
@@ -672,10 +683,43 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
             cp.gram.push_back(g);
             at.G = g.G;
           }
+          const bool chol = use_chol(ni);
+          if (chol) {
+            // partial Gram matrices over chunks of about kGramChunk fill
+            // columns (one workgroup tile each), summed and factored by the
+            // pivoted Cholesky
+            std::vector<int> rows(cur.size());
+            for (size_t q = 0; q < cur.size(); ++q) rows[q] = cur[q].ncols;
+            const auto groups = rf_groups(rows, kGramChunk);
+            CholTask<T> ct{};
+            ct.G = gwork.p + goff;
+            for (const auto& gr : groups) {
+              GramTask<T> g{};
+              g.G = gwork.p + goff;
+              goff += (int64_t)ni * ni;
+              g.n = ni;
+              g.fbeg = (int)cp.grefs.size();
+              cp.grefs.insert(cp.grefs.end(), cur.begin() + gr.first, cur.begin() + gr.second);
+              g.fend = (int)cp.grefs.size();
+              g.tm = (ni + 63) / 64;
+              g.tile0 = cp.gram_tiles;
+              cp.gram_tiles += (int64_t)g.tm * g.tm;
+              cp.gram.push_back(g);
+            }
+            ct.Rt = work.p + woff;
+            woff += (int64_t)ni * ni + 4;  // the factor, its rank, alignment
+            ct.n = ni;
+            ct.nch = (int)groups.size();
+            ct.eps = at.eps;
+            cp.chol.push_back(ct);
+            cp.cmaxn = std::max(cp.cmaxn, ni);
+            at.Rt = ct.Rt;
+            at.rgen = 1;
+          }
           // stages of the tall-skinny QR: groups of fill blocks, then groups of
           // the previous stage's factors, until one factor remains
           const bool rf_glob = !rf_in_lds<T>(ni, lds);
-          for (size_t st = 0; !gram_mode; ++st) {
+          for (size_t st = 0; !gram_mode && !chol; ++st) {
             // stage 0: groups of fill blocks; later stages: pairs of factors
             // (an odd one passes to the next stage as it is)
             std::vector<std::pair<int, int>> groups;
@@ -885,27 +929,25 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       const int32_t* dyn = rdev.p;
       const bool gram = gram_mode;
       // every descriptor of the colour staged first, then one transfer
-      const GramTask<T>* dgram = gram ? ar.put(cp.gram) : nullptr;
-      const FillRef<T>* dgrefs = gram ? ar.put(cp.grefs) : nullptr;
+      const GramTask<T>* dgram = ar.put(cp.gram);
+      const FillRef<T>* dgrefs = ar.put(cp.grefs);
+      const CholTask<T>* dchol = ar.put(cp.chol);
       std::vector<const RTask<T>*> drst(rst.size());
       std::vector<const FillRef<T>*> drrefs(rst.size());
-      if (!gram)
-        for (size_t st = 0; st < rst.size(); ++st) {
-          drst[st] = ar.put(rst[st]);
-          drrefs[st] = ar.put(rrefs[st]);
-        }
+      for (size_t st = 0; st < rst.size(); ++st) {
+        drst[st] = ar.put(rst[st]);
+        drrefs[st] = ar.put(rrefs[st]);
+      }
       const AugTask<T>* daug = ar.put(aug);
       const STask<T>* dsl = ar.put(sl);
       const STask<T>* dsr = ar.put(sr);
       const LUTask<T>* dlus = ar.put(lus);
       const TrsmTask<T>* dtrs = ar.put(trs);
       ar.flush(s);
-      if (gram) {
+      {
         auto m0 = mark(0);
         launch_gram<T>(dgram, (int)cp.gram.size(), dgrefs, rdev.p, cp.gram_tiles, s);
-        close_mark(m0);
-      } else {
-        auto m0 = mark(0);
+        launch_pchol<T>(dchol, (int)cp.chol.size(), cp.cmaxn, s);
         for (size_t st = 0; st < rst.size(); ++st)
           launch_rfactor<T>(drst[st], (int)rst[st].size(), drrefs[st], rdev.p, rmaxn[st], s, lds);
         close_mark(m0);
@@ -913,7 +955,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       auto m1 = mark(1);
       launch_augment<T>(daug, (int)aug.size(), rdev.p, ctx->d_err.p, maxn_aug, gram, s, lds);
       close_mark(m1);
-      launches[0] += gram ? 1 : (int64_t)rst.size();
+      launches[0] += (cp.gram.empty() ? 0 : 1) + (cp.chol.empty() ? 0 : 1) + (int64_t)rst.size();
       launches[1] += 1;
       launches[2] += 2;
       launches[3] += 1;
@@ -985,9 +1027,10 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       // algorithmic flop model of the level, on a worker thread while the
       // close-out is planned (it reads the plan and writes only the instance's
       // counters)
-      auto flop_model = std::async(std::launch::async, [I, &P, gm = gram_mode]() {
+      auto flop_model = std::async(std::launch::async, [I, &P, gmode = gram_mode, cmode = chol_mode]() {
         for (int i = 0; i < P.nl; ++i) {
           const double n = P.n[i], k = P.k[i], r = P.r[i], kt = n - r;
+          const bool gm = gmode || (cmode && P.n[i] <= kCholMaxOrder);
           double f = 0, W = kt, Wn = 0;
           for (int64_t e = P.pptr[i]; e < P.pptr[i + 1]; ++e) {
             const int j = P.pcol[e];

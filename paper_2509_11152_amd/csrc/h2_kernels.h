@@ -182,7 +182,8 @@ template <class T> struct AugTask {
   T* work;              // scratch
   int32_t n, k;
   int32_t ri;           // index into the r array (output)
-  int32_t pad0;
+  int32_t rgen;         // Rt holds a general factor (R with permuted columns), not a
+                        // triangle, followed by its number of nonzero rows (int32)
   double eps;           // truncation threshold eps_fill = tol ||A||_2 of the task's matrix
 };
 
@@ -194,6 +195,20 @@ template <class T> struct GramTask {
   int32_t fbeg, fend;
   int32_t tm;           // tiles per dimension
   int64_t tile0;        // first tile of this task in the launch
+};
+
+// Factor of a fill row's Gram matrix for the FP32 factorization (the Gram
+// option of Section 2.1): G is the sum of nch partial Gram matrices (FP64,
+// n x n each, consecutive), factored by Cholesky with diagonal pivoting,
+// G = P R^T R P^T, stopped once the largest remaining pivot is at most
+// max(1e-6 eps^2, 64 n u maxdiag(G)); Rt receives R P^T (rows past the
+// rank zero) as Rt[b + a n] = (R P^T)[a][b], and the rank as an int32 in the
+// element after it (Rt holds n^2 + 1 elements).
+template <class T> struct CholTask {
+  const double* G;
+  T* Rt;
+  int32_t n, nch;
+  double eps;           // eps_fill of the task's matrix
 };
 
 // LU with partial pivoting of the leading r x r block of A (r = dyn[ri]).
@@ -261,6 +276,8 @@ template <class T> __host__ __device__ inline bool rf_in_lds(int n, int lds = kL
 constexpr int kMaxAugOrder = 1024;
 // rows of Y^T one first-stage group takes (whole fill blocks, at least one)
 inline int rf_group_rows(int) { return 256; }
+// fill columns per partial Gram matrix (one workgroup tile of G per chunk)
+constexpr int kGramChunk = 4096;
 
 // scratch elements of one augmentation task of order n: V_perp (n^2), the
 // reflectors of V (n^2), M' or M and W' (2 n^2), G V_perp (n^2), singular
@@ -307,6 +324,10 @@ void launch_schur(const SchurLevel<T>* lv, int ninst, int64_t rows, int c, Schur
 template <class T>
 void launch_rfactor(const RTask<T>* tasks, int ntasks, const FillRef<T>* refs,
                     const int32_t* dyn, int maxn, hipStream_t s, int lds = kLdsBytes);
+// pivoted Cholesky factors, one workgroup per task (orders up to kCholMaxOrder)
+constexpr int kCholMaxOrder = 128;
+template <class T>
+void launch_pchol(const CholTask<T>* tasks, int ntasks, int maxn, hipStream_t s);
 template <class T>
 void launch_gram(const GramTask<T>* tasks, int ntasks, const FillRef<T>* refs,
                  const int32_t* dyn, int64_t ntiles, hipStream_t s);

@@ -1167,10 +1167,17 @@ __global__ __launch_bounds__(256) void k_gram(const GramTask<T>* __restrict__ ta
   const GramTask<T>& tk = tasks[lo];
   const int n = tk.n;
   const int64_t t = tile - tk.tile0;
-  const int r0 = (int)(t % tk.tm) * 64, c0 = (int)(t / tk.tm) * 64;
+  const int ti = (int)(t % tk.tm), tj = (int)(t / tk.tm);
+  // G is symmetric: tiles and 32 x 32 quadrants below the diagonal are
+  // written as the mirror of the ones above it
+  if (ti > tj) return;
+  const int r0 = ti * 64, c0 = tj * 64;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, kq = lane >> 4;
-  const int wr = r0 + (wave & 1) * 32, wc = c0 + (wave >> 1) * 32;
+  const int qr = wave & 1, qc = wave >> 1;
+  if (ti == tj && qr > qc) return;
+  const bool mirror = ti != tj || qr != qc;
+  const int wr = r0 + qr * 32, wc = c0 + qc * 32;
   typename Acc<double>::type acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -1181,22 +1188,49 @@ __global__ __launch_bounds__(256) void k_gram(const GramTask<T>* __restrict__ ta
     const int k0 = fr.d0 >= 0 ? dyn[fr.d0] : 0;
     const int k1 = fr.ncols;
     const int64_t rs = fr_rs(fr), cs = fr_cs(fr);
+    // a block stored transposed has its k index contiguous: each lane then
+    // reads four consecutive k of its row as one vector (FP32), and step s4
+    // takes k = kk + 4 kq + s4 (any order of k gives the same Gram matrix
+    // up to rounding)
+    const bool kvec = sizeof(T) == 4 && fr.tr;
     for (int kk = k0; kk < k1; kk += 16) {
       double av[4][2], bv[4][2];
+      if (kvec) {
+        const int kl = kk + 4 * kq;
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        const int kx = kk + 4 * s4 + kq;
-        const bool kok = kx < k1;
-        const T* col = fr.F + (int64_t)kx * cs;
+        for (int a = 0; a < 4; ++a) {
+          const int row = (a < 2 ? wr + a * 16 : wc + (a - 2) * 16) + l16;
+          double v4[4];
+          if (row < n && kl + 4 <= k1) {
+            const typename VecK<T>::type v = ld_veck<T>(gmem((const T*)fr.F) + kl + (int64_t)row * rs);
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const int row = wr + a * 16 + l16;
-          av[s4][a] = (kok && row < n) ? double(col[row * rs]) : 0.0;
+            for (int s4 = 0; s4 < 4; ++s4) v4[s4] = double(v[s4 % VecK<T>::n]);
+          } else {
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)
+              v4[s4] = (row < n && kl + s4 < k1) ? double(fr.F[kl + s4 + (int64_t)row * rs]) : 0.0;
+          }
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            if (a < 2) av[s4][a] = v4[s4]; else bv[s4][a - 2] = v4[s4];
+          }
         }
+      } else {
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const int cc = wc + b * 16 + l16;
-          bv[s4][b] = (kok && cc < n) ? double(col[cc * rs]) : 0.0;
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int kx = kk + 4 * s4 + kq;
+          const bool kok = kx < k1;
+          const T* col = fr.F + (int64_t)kx * cs;
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const int row = wr + a * 16 + l16;
+            av[s4][a] = (kok && row < n) ? double(col[row * rs]) : 0.0;
+          }
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            const int cc = wc + b * 16 + l16;
+            bv[s4][b] = (kok && cc < n) ? double(col[cc * rs]) : 0.0;
+          }
         }
       }
       // G = Y Y^T: the "B" operand is Y^T, whose (k, col) entry is Y[col][k];
@@ -1218,9 +1252,249 @@ __global__ __launch_bounds__(256) void k_gram(const GramTask<T>* __restrict__ ta
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int cc = wc + b * 16 + acc_row<double>(kq, i);
-        if (cc < n) tk.G[row + (int64_t)cc * n] = acc[a][b][i];
+        if (cc < n) {
+          tk.G[row + (int64_t)cc * n] = acc[a][b][i];
+          if (mirror) tk.G[cc + (int64_t)row * n] = acc[a][b][i];
+        }
       }
   }
+}
+
+// Cholesky with diagonal pivoting of a summed Gram matrix (CholTask), in LDS,
+// one workgroup per task.
+template <class T>
+__global__ __launch_bounds__(256) void k_pchol(const CholTask<T>* __restrict__ tasks) {
+  extern __shared__ char pc_smem[];
+  const CholTask<T> tk = tasks[blockIdx.x];
+  const int n = tk.n;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  double* Gs = reinterpret_cast<double*>(pc_smem);  // Gs[a + b n]
+  int* perm = reinterpret_cast<int*>(Gs + (int64_t)n * n);
+  int* iperm = perm + n;
+  __shared__ double wv[4];
+  __shared__ int wi[4];
+  if (n == 0) return;
+  // the partial Gram matrices, summed in chunk order
+  const gptr<const double> Gg = gmem(tk.G);
+  // eight independent loads in flight per thread and chunk
+  for (int e0 = tid; e0 < n * n; e0 += 256 * 8) {
+    double acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = 0;
+    for (int c = 0; c < tk.nch; ++c)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 256 * u;
+        if (e < n * n) acc[u] += Gg[(int64_t)c * n * n + e];
+      }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (e0 + 256 * u < n * n) Gs[e0 + 256 * u] = acc[u];
+  }
+  for (int j = tid; j < n; j += 256) perm[j] = j;
+  __syncthreads();
+  // largest remaining diagonal entry at or after j (ties: the smallest index)
+  auto pivot = [&](int j, double& dv, int& di) {
+    double v = -1.0;
+    int ix = n;
+    for (int i = j + tid; i < n; i += 256) {
+      const double g = Gs[i + (int64_t)i * n];
+      if (g > v) {
+        v = g;
+        ix = i;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double v2 = __shfl_xor(v, o, 64);
+      const int i2 = __shfl_xor(ix, o, 64);
+      if (v2 > v || (v2 == v && i2 < ix)) {
+        v = v2;
+        ix = i2;
+      }
+    }
+    if (lane == 0) {
+      wv[wave] = v;
+      wi[wave] = ix;
+    }
+    __syncthreads();
+    dv = wv[0];
+    di = wi[0];
+    for (int w = 1; w < 4; ++w)
+      if (wv[w] > dv || (wv[w] == dv && wi[w] < di)) {
+        dv = wv[w];
+        di = wi[w];
+      }
+    __syncthreads();
+  };
+  double dmax;
+  int dummy;
+  pivot(0, dmax, dummy);
+  const double thr = fmax(1e-6 * tk.eps * tk.eps, 64.0 * n * DBL_EPSILON * dmax);
+  int rank = 0;
+  for (int j = 0; j < n; ++j) {
+    double d;
+    int p;
+    pivot(j, d, p);
+    if (!(d > thr)) break;
+    rank = j + 1;
+    if (p != j) {
+      // symmetric exchange of rows and columns j and p (the computed rows of
+      // R take the column exchange too)
+      for (int e = tid; e < n; e += 256) {
+        const double x = Gs[j + (int64_t)e * n];
+        Gs[j + (int64_t)e * n] = Gs[p + (int64_t)e * n];
+        Gs[p + (int64_t)e * n] = x;
+      }
+      __syncthreads();
+      for (int e = tid; e < n; e += 256) {
+        const double x = Gs[e + (int64_t)j * n];
+        Gs[e + (int64_t)j * n] = Gs[e + (int64_t)p * n];
+        Gs[e + (int64_t)p * n] = x;
+      }
+      if (tid == 0) {
+        const int x = perm[j];
+        perm[j] = perm[p];
+        perm[p] = x;
+      }
+      __syncthreads();
+    }
+    // row j of R: R[j][i] = G[j][i] / sqrt(G[j][j]), i >= j
+    const double rd = sqrt(Gs[j + (int64_t)j * n]);
+    __syncthreads();
+    for (int i = j + tid; i < n; i += 256) Gs[j + (int64_t)i * n] /= rd;
+    __syncthreads();
+    // trailing update G[a][b] -= R[j][a] R[j][b], a, b > j
+    const int m = n - j - 1;
+    for (int e = tid; e < m * m; e += 256) {
+      const int a = j + 1 + e % m, b = j + 1 + e / m;
+      Gs[a + (int64_t)b * n] -= Gs[j + (int64_t)a * n] * Gs[j + (int64_t)b * n];
+    }
+    __syncthreads();
+  }
+  for (int c = tid; c < n; c += 256) iperm[perm[c]] = c;
+  __syncthreads();
+  // (R P^T)[a][b] = R[a][c] with perm[c] = b
+  const gptr<T> Rt = gmem(tk.Rt);
+  for (int e = tid; e < n * n; e += 256) {
+    const int b = e % n, a = e / n;
+    const int c = iperm[b];
+    Rt[b + (int64_t)a * n] = (a < rank && c >= a) ? T(Gs[a + (int64_t)c * n]) : T(0);
+  }
+  if (threadIdx.x == 0) *reinterpret_cast<__attribute__((address_space(1))) int32_t*>(Rt + (int64_t)n * n) = rank;
+}
+
+// The same for orders up to 64 with one wave per task: lane l owns column l
+// of the working matrix in LDS, the pivot search is a wave reduction and the
+// barriers cost next to nothing.
+template <class T>
+__global__ __launch_bounds__(64) void k_pchol_wave(const CholTask<T>* __restrict__ tasks) {
+  extern __shared__ char pc_smem[];
+  const CholTask<T> tk = tasks[blockIdx.x];
+  const int n = tk.n;
+  const int l = threadIdx.x;
+  double* Gs = reinterpret_cast<double*>(pc_smem);  // Gs[a + b n], column b of lane b
+  int* perm = reinterpret_cast<int*>(Gs + (int64_t)n * n);
+  int* iperm = perm + n;
+  if (n == 0) return;
+  const gptr<const double> Gg = gmem(tk.G);
+  // sixteen independent loads in flight per lane and chunk
+  for (int e0 = l; e0 < n * n; e0 += 64 * 16) {
+    double acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = 0;
+    for (int c = 0; c < tk.nch; ++c)
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = e0 + 64 * u;
+        if (e < n * n) acc[u] += Gg[(int64_t)c * n * n + e];
+      }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (e0 + 64 * u < n * n) Gs[e0 + 64 * u] = acc[u];
+  }
+  if (l < n) perm[l] = l;
+  __syncthreads();
+  // largest remaining diagonal entry at or after j (ties: the smallest index)
+  auto pivot = [&](int j, double& dv, int& di) {
+    double v = (l >= j && l < n) ? Gs[l + (int64_t)l * n] : -1.0;
+    int ix = (l >= j && l < n) ? l : n;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double v2 = __shfl_xor(v, o, 64);
+      const int i2 = __shfl_xor(ix, o, 64);
+      if (v2 > v || (v2 == v && i2 < ix)) {
+        v = v2;
+        ix = i2;
+      }
+    }
+    dv = v;
+    di = ix;
+  };
+  double dmax;
+  int dummy;
+  pivot(0, dmax, dummy);
+  const double thr = fmax(1e-6 * tk.eps * tk.eps, 64.0 * n * DBL_EPSILON * dmax);
+  int rank = 0;
+  for (int j = 0; j < n; ++j) {
+    double d;
+    int p;
+    pivot(j, d, p);
+    if (!(d > thr)) break;
+    rank = j + 1;
+    if (p != j) {
+      if (l < n) {  // rows j and p of column l, then columns j and p of row l
+        double x = Gs[j + (int64_t)l * n];
+        Gs[j + (int64_t)l * n] = Gs[p + (int64_t)l * n];
+        Gs[p + (int64_t)l * n] = x;
+      }
+      __syncthreads();
+      if (l < n) {
+        double x = Gs[l + (int64_t)j * n];
+        Gs[l + (int64_t)j * n] = Gs[l + (int64_t)p * n];
+        Gs[l + (int64_t)p * n] = x;
+      }
+      if (l == 0) {
+        const int x = perm[j];
+        perm[j] = perm[p];
+        perm[p] = x;
+      }
+      __syncthreads();
+    }
+    const double rd = sqrt(Gs[j + (int64_t)j * n]);
+    __syncthreads();
+    if (l >= j && l < n) Gs[j + (int64_t)l * n] /= rd;
+    __syncthreads();
+    if (l > j && l < n) {
+      const double rb = Gs[j + (int64_t)l * n];
+      for (int a = j + 1; a < n; ++a) Gs[a + (int64_t)l * n] -= Gs[j + (int64_t)a * n] * rb;
+    }
+    __syncthreads();
+  }
+  if (l < n) iperm[perm[l]] = l;
+  __syncthreads();
+  const gptr<T> Rt = gmem(tk.Rt);
+  for (int e = l; e < n * n; e += 64) {
+    const int b = e % n, a = e / n;
+    const int c = iperm[b];
+    Rt[b + (int64_t)a * n] = (a < rank && c >= a) ? T(Gs[a + (int64_t)c * n]) : T(0);
+  }
+  if (threadIdx.x == 0) *reinterpret_cast<__attribute__((address_space(1))) int32_t*>(Rt + (int64_t)n * n) = rank;
+}
+
+template <class T> void launch_pchol(const CholTask<T>* tasks, int ntasks, int maxn, hipStream_t s) {
+  if (ntasks <= 0) return;
+  if (maxn <= 64) {
+    const size_t lds = (size_t)maxn * maxn * sizeof(double) + 2 * (size_t)maxn * sizeof(int);
+    hipLaunchKernelGGL(k_pchol_wave<T>, dim3((unsigned)ntasks), dim3(64), lds, s, tasks);
+    return;
+  }
+  const size_t lds = (size_t)maxn * maxn * sizeof(double) + 2 * (size_t)maxn * sizeof(int);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_pchol<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kLdsBytes);
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_pchol<T>, dim3((unsigned)ntasks), dim3(256), lds, s, tasks);
 }
 
 template <class T>
@@ -1347,7 +1621,10 @@ __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__
   // GRAM path: M = V_perp^T G V_perp (mp x mp), symmetric positive
   // semidefinite; its right singular vectors are its eigenvectors and its
   // singular values the squares of those of the projected fill row.
-  const int mrow = GRAM ? mp : n;  // length of the columns Jacobi rotates
+  // length of the columns Jacobi rotates: mp for M; n for M' = R V_perp,
+  // or the rank of a pivoted Cholesky factor (rows past it are zero), stored
+  // after the factor
+  const int mrow = GRAM ? mp : tk.rgen ? min(n, *reinterpret_cast<const int32_t*>(Rt + (int64_t)n * n)) : n;
   const bool de_lds = (int64_t)mrow * mp + (int64_t)mp * mp + 8 <= cap;
   A* Ms = de_lds ? smem : Hm;                                       // mrow x mp, ld mrow
   A* Ws = de_lds ? smem + (int64_t)mrow * mp : Hm + (int64_t)mrow * mp;  // mp x mp
@@ -1367,10 +1644,10 @@ __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__
       Ms[e] = acc;
     }
   } else {
-    for (int e = tid; e < n * mp; e += nthr) {
-      const int a = e % n, c = e / n;
+    for (int e = tid; e < mrow * mp; e += nthr) {
+      const int a = e % mrow, c = e / mrow;
       A acc = 0;
-      for (int b = a; b < n; ++b) acc += A(Rt[b + (int64_t)a * n]) * Vp[b + (int64_t)c * n];
+      for (int b = tk.rgen ? 0 : a; b < n; ++b) acc += A(Rt[b + (int64_t)a * n]) * Vp[b + (int64_t)c * n];
       Ms[e] = acc;
     }
   }
@@ -1399,6 +1676,13 @@ __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__
   }
   const int grp = tid / LG, gl = tid % LG, ngrp = nthr / LG;
   const A tolj = eps_of<A>() * A(mrow);
+  // FP32 arithmetic: a pair whose inner product is below gabs_min counts as
+  // converged.  Off-diagonal entries of the columns' Gram matrix that small
+  // move its eigenvalues by at most mp gabs_min = 4e-3 eps_fill^2, so a
+  // singular value moves by at most 0.2% of eps_fill near the threshold: the
+  // truncation is unaffected, and the noise-level columns below eps_fill stop
+  // being rotated sweep after sweep.
+  const A gabs_min = sizeof(A) == 4 ? A(4e-3) * eps_fill * eps_fill / A(mp > 40 ? mp : 40) : A(0);
   for (int sweep = 0; sweep < 40 && mp > 1; ++sweep) {
     if (tid == 0) sh_flag = 0;
     __syncthreads();
@@ -1435,7 +1719,7 @@ __global__ __launch_bounds__(1024) void k_augment(const AugTask<T>* __restrict__
         // underflow for tiny columns, and a zero there would make every
         // nonzero gab look unconverged
         const A nab = sqrt(al) * sqrt(be);
-        if (gab != A(0) && nab > A(0) && fabs(gab) > tolj * nab) {
+        if (gab != A(0) && nab > A(0) && fabs(gab) > tolj * nab && fabs(gab) > gabs_min) {
           const A zeta = (be - al) / (A(2) * gab);
           const A tt = (zeta >= A(0) ? A(1) : A(-1)) / (fabs(zeta) + sqrt(A(1) + zeta * zeta));
           const A cs = A(1) / sqrt(A(1) + tt * tt);
@@ -2391,6 +2675,7 @@ void launch_check_finite(const double* X, int64_t n, int* flag, hipStream_t s) {
                                 SchurTarget*, int64_t*, int64_t*, int*, hipStream_t);         \
   template void launch_rfactor<T>(const RTask<T>*, int, const FillRef<T>*, const int32_t*, int, \
                                   hipStream_t, int);                                          \
+  template void launch_pchol<T>(const CholTask<T>*, int, int, hipStream_t);                  \
   template void launch_gram<T>(const GramTask<T>*, int, const FillRef<T>*, const int32_t*,    \
                                int64_t, hipStream_t);                                         \
   template void launch_augment<T>(const AugTask<T>*, int, int32_t*, int*, int, bool,          \

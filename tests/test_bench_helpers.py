@@ -20,8 +20,9 @@ def _stats(ms, flops, bytes_, launches):
 
 
 def test_roofline_picks_the_longest_phase_and_its_bound():
-    # fill_row_qr 10 ms (ALU), augment 5 ms, project 30 ms with high intensity
-    # (MFMA), schur 40 ms with low intensity (HBM)
+    # fill_row_qr 10 ms (FP32: Gram matrices on FP64 MFMA; FP64: Householder
+    # on the ALU), augment 5 ms, project 30 ms with high intensity (MFMA),
+    # schur 40 ms with low intensity (HBM)
     ms = [10, 5, 30, 0, 0, 40, 0, 0]
     fl = [1e12, 1e10, 3e14, 0, 0, 1e9, 0, 0]
     by = [1e9, 1e8, 1e9, 0, 0, 2e11, 0, 0]
@@ -31,10 +32,14 @@ def test_roofline_picks_the_longest_phase_and_its_bound():
     assert abs(roof["achieved"] - 2e11 / 0.040 / 1e9) < 1e-6
     assert abs(roof["frac"] - roof["achieved"] / bench.HBM_PEAK) < 1e-12
     assert roof["ms_per_launch"] == 10.0
-    assert phases["fill_row_qr"]["bound"] == "alu"
+    assert phases["fill_row_qr"]["bound"] == "mfma"
+    assert phases["fill_row_qr"]["peak"] == bench.PEAK["f64"]
+    assert phases["augment"]["bound"] == "alu"
     assert phases["project"]["bound"] == "mfma"
     assert phases["project"]["peak"] == bench.PEAK["f32"]
     assert "lu" not in phases  # no time, no work: not reported
+    _, p64 = bench.roofline(_stats(ms, fl, by, nl), "f64")
+    assert p64["fill_row_qr"]["bound"] == "alu" and p64["fill_row_qr"]["kernel"] == "k_rfactor"
 
 
 def test_traffic_lookup_requires_workload_phase_and_source_hash():

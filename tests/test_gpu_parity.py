@@ -175,7 +175,7 @@ def test_global_memory_variants(lib, ctx, name, spec, lds_kib):
           flush=True)
     assert rel <= 1e-10 and res <= 1e-10 and ew <= 1e-10
     # FP32 storage through the same variants still refines to 1e-12
-    F32 = lib.Factor(ctx, H, w["spec"]["tol"], lib.H2_PREC_FP32, lds_limit_kib=lds_kib)
+    F32 = lib.Factor(ctx, H, w["spec"]["tol"], lib.H2_PREC_FP32_QR, lds_limit_kib=lds_kib)
     X32, rep = lib.solve_ir(ctx, H, F32, _cuda(B), target=1e-12)
     eb = h2ops.backward_error(oracle_matrix(name, spec), X32.cpu().numpy(), B)
     assert rep["converged"] and eb.max() <= 1e-12, (rep, eb)
@@ -183,7 +183,7 @@ def test_global_memory_variants(lib, ctx, name, spec, lds_kib):
 
 @pytest.mark.parametrize("name,spec", [("exp2d_4096", None), ("exp3d_4096", EXP3D_4096),
                                        ("laplace3d_8192", None)])
-@pytest.mark.parametrize("mode", ["qr", "gram"])
+@pytest.mark.parametrize("mode", ["chol", "qr", "gram"])
 def test_fp32_factor_with_fp64_refinement(lib, ctx, name, spec, mode):
     from oracle import h2ops
 
@@ -191,7 +191,7 @@ def test_fp32_factor_with_fp64_refinement(lib, ctx, name, spec, mode):
     w = workload(name, spec)
     H = gpu_matrix(lib, ctx, name, spec)
     Ho = oracle_matrix(name, spec)
-    prec = lib.H2_PREC_FP32 if mode == "qr" else lib.H2_PREC_FP32_GRAM
+    prec = {"chol": lib.H2_PREC_FP32, "qr": lib.H2_PREC_FP32_QR, "gram": lib.H2_PREC_FP32_GRAM}[mode]
     F32 = lib.Factor(ctx, H, w["spec"]["tol"], prec)
     X, rep = lib.solve_ir(ctx, H, F32, _cuda(w["B"]), target=1e-12)
     X = X.cpu().numpy()
