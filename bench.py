@@ -466,9 +466,11 @@ def main():
         eb64, eb64p = bkwd(X64), bkwd(X64p)
         s64 = F64.stats()
         fp64 = {"ir": rep64}
+        # the allocator keeps the freed blocks for the next run (as in the
+        # FP32 steps); the first run, when there is time for two, warms it
         del F64, X64, X64p
-        torch.cuda.empty_cache()
         log(f"[bench] fp64 run {rep}: fp64+IR {t64:.3f}s plain fp64 {t64p:.3f}s; {left():.0f} s left")
+    torch.cuda.empty_cache()
     value = med(t32)
     roof, phases = roofline(s32, "f32")
     roof["traffic"] = measured_traffic(args.workload, roof["phase"])
