@@ -44,13 +44,13 @@ def test_roofline_picks_the_longest_phase_and_its_bound():
 
 def test_traffic_lookup_requires_workload_phase_and_source_hash():
     assert bench.measured_traffic("no_such_workload", "augment") is None
-    assert bench.measured_traffic("exp3d_262144", "project") is None
-    path = os.path.join(ROOT, "profiles", "pmc_traffic_exp3d_262144.md")
+    assert bench.measured_traffic("laplace3d_1048576", "project") is None
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_laplace3d_1048576.md")
     rec = json.loads(re.search(r"```json\n(.*?)\n```", open(path).read(), re.S).group(1))
     src = os.path.join(ROOT, "paper_2509_11152_amd", "csrc", "h2_kernels.hip")
     current = hashlib.sha256(open(src, "rb").read()).hexdigest() == rec["kernel_source_sha256"]
     for phase, kernel in bench.PMC_KERNEL.items():
-        t = bench.measured_traffic("exp3d_262144", phase)
+        t = bench.measured_traffic("laplace3d_1048576", phase)
         if current:
             assert t == rec["kernels"][kernel]["traffic_bytes_per_launch"] and t > 0
         else:
