@@ -288,6 +288,7 @@ template <class T> struct Inst {
   size_t li = 0;             // index of the current level in F->plans
   DevArray<T> Fbuf;          // fill blocks of the current level
   DevArray<T> Vbuf;          // bases of the current level
+  T* xmul = nullptr;         // the level's multiplier copies (read by the Schur updates)
   double norm = 0;           // ||A||_2 of eps_fill = tol ||A||_2
   double flops = 0;
   double pflops[H2_PHASES] = {0}, pbytes[H2_PHASES] = {0};
@@ -528,6 +529,13 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     // updates that are enumerated there (staged through the arena, which is
     // reset only after the level's last launch has completed)
     std::vector<SchurLevel<T>> lvh(act.size());
+    // kXmulCopy: the multipliers D_RR^{-1} D_{R_i,k} once more, compact
+    // (r_i x n_k) inside the region of the near block (i, k): the Schur
+    // updates read them there (the factor keeps them inside D for the solves)
+    std::vector<DevArray<T>> xmul(act.size());
+    if (kXmulCopy<T>())
+      for (size_t q = 0; q < act.size(); ++q)
+        xmul[q].alloc(std::max<int64_t>(act[q]->F->plans[act[q]->li].nD, 1), calltr);
     int64_t schur_rows = 0, schur_nnz = 0;
     for (size_t q = 0; q < act.size(); ++q) {
       Inst<T>* I = act[q];
@@ -542,6 +550,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       L.r = rdev.p + I->rbase;
       L.D = store_of<T>(I->F, I->li).D.p;
       L.F = I->Fbuf.p;
+      L.X = I->xmul = xmul[q].p;
       L.nl = P.nl;
       L.rows0 = schur_rows;
       schur_rows += P.nl;
@@ -844,6 +853,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
             tt.LU = lt.A;
             tt.piv = lt.piv;
             tt.B = S.D.p + P.poff[eik];
+            tt.Bc = I->xmul ? I->xmul + P.poff[eik] : nullptr;
             tt.ldlu = ni;
             tt.ldb = ni;
             tt.ncols = P.n[k];
@@ -987,7 +997,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       {
         auto m5 = mark(5);
         launch_schur<T>(lvdev, (int)act.size(), schur_rows, c, schur_rowtab.p, schur_targets.p,
-                        schur_conts.p, schur_count.p, ctx->d_err.p, s);
+                        schur_conts.p, schur_count.p, schur_conts.n, ctx->d_err.p, s);
         close_mark(m5);
       }
       H2_HIP(hipGetLastError());  // a rejected launch configuration
@@ -1002,9 +1012,9 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       if (herr & 1) throw H2Error(H2_ERROR_SINGULAR, "zero pivot in a redundant block");
       if (herr & 2) throw H2Error(H2_ERROR_NUMERIC, "non-finite singular value in augmentation");
       if (herr & 4)
-        throw H2Error(H2_ERROR_UNSUPPORTED, "a block row has more than " +
-                                                std::to_string(kSchurMaxContrib) +
-                                                " Schur contributors of one colour");
+        throw H2Error(H2_ERROR_UNSUPPORTED,
+                      "a block row has more than " + std::to_string(kSchurMaxContrib) +
+                          " Schur contributors of one colour, or the update list overflowed");
       if (herr & 8)
         throw H2Error(H2_ERROR_FORMAT, "close-out destination missing from the next level");
     }

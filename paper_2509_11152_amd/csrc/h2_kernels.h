@@ -94,6 +94,11 @@ template <class T> struct RTask {
 // 1 stored fill block, 2 fill entry stored as the transpose of its mirror),
 // and the clusters' colours and orders.  rows0: first global row of the
 // instance in a launch over several instances.
+// The Schur update reads the multipliers of a near block from a compact copy
+// that the triangular solves also write (FP64: its single-element loads touch
+// fewer lines there), or in place in D (FP32: its 16-byte loads along k ran
+// faster from D than from the copy).
+template <class T> constexpr bool kXmulCopy() { return sizeof(T) == 8; }
 template <class T> struct SchurLevel {
   const int64_t* pptr;
   const int32_t* pcol;
@@ -104,6 +109,9 @@ template <class T> struct SchurLevel {
   const int32_t* r;     // the level's r array (this instance's clusters)
   T* D;
   T* F;
+  const T* X;           // kXmulCopy: the multipliers D_RR^{-1} D_{R_i,k} of near entry
+                        // (i, k) in the n_i x n_k region at its offset (placed by
+                        // xmul_at); else unused
   int32_t nl;
   int32_t pad0;
   int64_t rows0;
@@ -156,14 +164,16 @@ template <class T> struct CloseLevel {
 };
 constexpr int kSchurMaxContrib = 32;
 // one Schur / fill-in target found on the device: global row g (instance row
-// offset + j), pattern entry e = (j, k), contributors (bit x: the x-th
-// contributor of row g)
+// offset + j), pattern entry e = (j, k), and its ncont contributions at
+// conts[cbeg..]: each (x << 48) | e_ik, x the contributor's slot in row g's
+// table, e_ik the entry (i, k) of its multipliers, in ascending x
 struct SchurTarget {
   int64_t e;
   int32_t g;
-  uint32_t mask;
-  int64_t cbeg;  // its contributors' entries (i, k), in bit order, at conts[cbeg..]
+  int32_t ncont;
+  int64_t cbeg;
 };
+constexpr int64_t kContEntryMask = ((int64_t)1 << 48) - 1;
 // contributors of one row for the colour being processed: cluster ids and
 // their entries (j, i)
 struct SchurRow {
@@ -225,6 +235,8 @@ template <class T> struct TrsmTask {
   const T* LU;
   const int32_t* piv;
   T* B;
+  T* Bc;                // optional: the result again, in a region of ldb x ncols
+                        // elements (placed as xmul_at places it)
   int64_t ldlu, ldb;
   int32_t ncols;
   int32_t ri, rs;       // order r: dyn[ri] or rs
@@ -312,12 +324,14 @@ void launch_strip(const STask<T>* tasks, int ntasks, const int32_t* dyn, int64_t
 // than kSchurMaxContrib contributors.
 // Two launches: the first finds every row's contributors (rowtab[g]), the
 // targets (appended to `targets`, at most the levels' pattern entries) and
-// each target's contributor entries (i, k) (appended to `conts`, at most the
-// colour's sum over its clusters of |N(i)|^2); count[0] and count[1] count
-// them (cleared first).  The second forms the targets' updates.
+// each target's contributions (appended to `conts`, at most ccap: the
+// colour's sum over its clusters of |N(i)|^2; beyond it a target keeps no
+// contributions and err bit 4 is set); count[0] and count[1] count them
+// (cleared first).  The second forms the targets' updates.
 template <class T>
 void launch_schur(const SchurLevel<T>* lv, int ninst, int64_t rows, int c, SchurRow* rowtab,
-                  SchurTarget* targets, int64_t* conts, int64_t* count, int* err, hipStream_t s);
+                  SchurTarget* targets, int64_t* conts, int64_t* count, int64_t ccap, int* err,
+                  hipStream_t s);
 // `lds`: LDS bytes per workgroup the path choices of the fill-row QR, the
 // augmentation, the LU and the multipliers may assume (at most kLdsBytes);
 // working sets beyond it take the global-memory variants

@@ -42,6 +42,25 @@ template <> __device__ inline int acc_row<float>(int kq, int i) { return 4 * kq 
 template <class T> using gptr = __attribute__((address_space(1))) T*;
 template <class T> __device__ inline gptr<T> gmem(T* p) { return (gptr<T>)p; }
 
+// Where the copy of the multipliers of a near block (r x nk) sits inside the
+// block's n x nk region of the copy array, and its leading dimension: from
+// the first 16-byte boundary with a leading dimension rounded up to 16 bytes
+// when that fits the region, else from the region's start with leading
+// dimension r.  The triangular solve that writes the copy and the Schur
+// update that reads it both place it here.
+template <class T, class P> __device__ inline P xmul_at(P base, int r, int n, int nk, int& ld) {
+  constexpr int ve = 16 / (int)sizeof(T);
+  const int mis = (int)(((uintptr_t)base / sizeof(T)) % ve);
+  const int shift = mis ? ve - mis : 0;
+  const int ldv = (r + ve - 1) / ve * ve;
+  if (shift + (int64_t)ldv * nk <= (int64_t)n * nk) {
+    ld = ldv;
+    return base + shift;
+  }
+  ld = r;
+  return base;
+}
+
 // 16-byte vector of T (one LDS b128 access)
 template <class T> struct Vec16;
 template <> struct Vec16<float> { typedef float __attribute__((ext_vector_type(4))) type; };
@@ -485,7 +504,7 @@ template <class T>
 __global__ __launch_bounds__(256) void k_schur_enum(const SchurLevel<T>* __restrict__ lvs,
                                                     int ninst, int c, SchurRow* rowtab,
                                                     SchurTarget* targets, int64_t* conts,
-                                                    int64_t* count, int* err) {
+                                                    int64_t* count, int64_t ccap, int* err) {
   __shared__ int ci[kSchurMaxContrib];
   __shared__ int64_t eji[kSchurMaxContrib];
   __shared__ int wcnt[4], wcon[4];
@@ -567,19 +586,23 @@ __global__ __launch_bounds__(256) void k_schur_enum(const SchurLevel<T>* __restr
       SchurTarget t;
       t.e = e;
       t.g = (int32_t)g;
-      t.mask = mask;
       t.cbeg = sh_cbase + coff;
+      const bool fits = t.cbeg + nb <= ccap;
+      t.ncont = fits ? nb : 0;
+      if (!fits) atomicOr(err, 4);
       targets[sh_base + off] = t;
       int q = 0;
-      for (int x = 0; x < nc; ++x)
-        if ((mask >> x) & 1u) conts[t.cbeg + q++] = schur_near_entry(L, ci[x], k);
+      if (fits)
+        for (int x = 0; x < nc; ++x)
+          if ((mask >> x) & 1u)
+            conts[t.cbeg + q++] = ((int64_t)x << 48) | schur_near_entry(L, ci[x], k);
     }
     __syncthreads();
   }
 }
 
 // workgroups loop over the targets: C -= sum of the contributors' products,
-// contributors ascending (bit order).  The active window of C is cut into
+// contributors ascending.  The active window of C is cut into
 // items of 32 x 32 (2 x 2 fragments of 16 x 16), handed to the four waves in
 // turn; C of an item is read before its products.  A multiplier block
 // D(i, k) is column-major with k contiguous, so every lane reads VK
@@ -588,10 +611,12 @@ __global__ __launch_bounds__(256) void k_schur_enum(const SchurLevel<T>* __restr
 // D(j, i) as for the multipliers (any assignment of k to the steps gives the
 // same sum).
 // k-values a lane reads as one vector in the Schur update (FP64 keeps single
-// loads: its k order is then the plain ascending one), and blocks of 4 VK
-// k-values loaded ahead of their products
+// loads: its k order is then the plain ascending one), and the blocks of 4 VK
+// k-values of one operand load; a wave issues the loads of its next block
+// (next k-values, else the next contribution's first) before the products of
+// the current one
 template <class T> constexpr int schur_vk() { return sizeof(T) == 4 ? 4 : 1; }
-template <class T> constexpr int schur_nb() { return sizeof(T) == 4 ? 1 : 4; }
+template <class T> constexpr int schur_nb() { return sizeof(T) == 4 ? 1 : 2; }
 template <class T>
 __global__ __launch_bounds__(256) void k_schur_apply(const SchurLevel<T>* __restrict__ lvs,
                                                      int ninst, int c,
@@ -612,11 +637,11 @@ __global__ __launch_bounds__(256) void k_schur_apply(const SchurLevel<T>* __rest
     const SchurRow& R = rowtab[tg.g];
     const int j = (int)(tg.g - L.rows0);
     const int k = L.pcol[tg.e];
-    const int nc = R.nc;
     const int nj = L.n[j], nk = L.n[k];
     const int m0 = L.color[j] <= c ? L.r[j] : 0;
     const int n0 = L.color[k] <= c ? L.r[k] : 0;
     const gptr<const T> Dg = gmem((const T*)L.D);
+    const gptr<const T> Xg = gmem(kXmulCopy<T>() ? L.X : L.D);
     const gptr<T> C = gmem((L.kind[tg.e] == 1 ? L.F : L.D) + L.poff[tg.e]);
     const int nrg = (nj - m0 + 31) / 32;  // row items of the window
     const int ncg = (nk - n0 + 31) / 32;  // column items of the window
@@ -638,53 +663,108 @@ __global__ __launch_bounds__(256) void k_schur_apply(const SchurLevel<T>* __rest
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = (typename Acc<T>::type){0, 0, 0, 0};
-      int64_t cq = tg.cbeg;
-      for (int x = 0; x < nc; ++x) {
-        if (!((tg.mask >> x) & 1u)) continue;
-        const int64_t eb = conts[cq++];
+      // the item's operand blocks, contributions ascending and k ascending,
+      // with the next block's loads issued before the current block's products
+      // (the products, and so the rounding, are those of the plain loop)
+      struct Blk {
+        gptr<const T> A, B;  // D(j, i) (n_j x n_i) and the multipliers of (i, k) (r_i x n_k)
+        int k1, kb, ldx;
+      };
+      auto setup = [&](int q, Blk& bk) {
+        const int64_t cv2 = conts[tg.cbeg + q];
+        const int x = (int)(cv2 >> 48);
         const int i = R.ci[x];
-        const int ni = L.n[i];
-        const int k1 = L.r[i];
-        const gptr<const T> A = Dg + L.poff[R.eji[x]];  // D(j, i), n_j x n_i
-        const gptr<const T> B = Dg + L.poff[eb];        // D(i, k), n_i x n_k
-        for (int kb = 0; kb < k1; kb += kSchurNB * KBLK) {
-          T av[kSchurNB][VK][2], bv[kSchurNB][VK][2];
+        bk.k1 = L.r[i];
+        bk.A = Dg + L.poff[R.eji[x]];
+        if (kXmulCopy<T>()) {
+          bk.B = xmul_at<T>(Xg + L.poff[cv2 & kContEntryMask], bk.k1, L.n[i], nk, bk.ldx);
+        } else {
+          bk.B = Dg + L.poff[cv2 & kContEntryMask];
+          bk.ldx = L.n[i];
+        }
+        bk.kb = 0;
+      };
+      auto load = [&](const Blk& bk, T (&av)[kSchurNB][VK][2], T (&bv)[kSchurNB][VK][2]) {
 #pragma unroll
-          for (int q = 0; q < kSchurNB; ++q) {
-            const int kl = kb + q * KBLK + VK * kq;  // this lane's first k of the block
+        for (int q = 0; q < kSchurNB; ++q) {
+          const int kl = bk.kb + q * KBLK + VK * kq;  // this lane's first k of the block
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-              const int col = cb + b * 16 + l16;
-              if (VK > 1 && col < nk && kl + VK <= k1) {
-                const typename VecK<T>::type v = ld_veck<T>(B + (kl + col * ni));
+          for (int b = 0; b < 2; ++b) {
+            const int col = cb + b * 16 + l16;
+            if (VK > 1 && col < nk && kl + VK <= bk.k1) {
+              const typename VecK<T>::type v = ld_veck<T>(bk.B + (kl + col * bk.ldx));
 #pragma unroll
-                for (int s2 = 0; s2 < VK; ++s2) bv[q][s2][b] = v[s2 % VecK<T>::n];
-              } else {
-#pragma unroll
-                for (int s2 = 0; s2 < VK; ++s2)
-                  bv[q][s2][b] = (col < nk && kl + s2 < k1) ? B[kl + s2 + col * ni] : T(0);
-              }
-            }
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-              const int row = rb + a * 16 + l16;
+              for (int s2 = 0; s2 < VK; ++s2) bv[q][s2][b] = v[s2 % VecK<T>::n];
+            } else {
 #pragma unroll
               for (int s2 = 0; s2 < VK; ++s2)
-                av[q][s2][a] = (row < nj && kl + s2 < k1) ? A[row + (kl + s2) * nj] : T(0);
+                bv[q][s2][b] = (col < nk && kl + s2 < bk.k1) ? bk.B[kl + s2 + col * bk.ldx] : T(0);
             }
           }
-          // operands swapped: the accumulator holds the transposed fragment,
-          // lane l16 owning row l16 (coalesced epilogue)
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const int row = rb + a * 16 + l16;
+#pragma unroll
+            for (int s2 = 0; s2 < VK; ++s2)
+              av[q][s2][a] = (row < nj && kl + s2 < bk.k1) ? bk.A[row + (kl + s2) * nj] : T(0);
+          }
+        }
+      };
+      // operands swapped: the accumulator holds the transposed fragment, lane
+      // l16 owning row l16 (coalesced epilogue)
+      auto prod = [&](const Blk& bk, const T (&av)[kSchurNB][VK][2], const T (&bv)[kSchurNB][VK][2]) {
+#pragma unroll
+        for (int q = 0; q < kSchurNB; ++q)
+#pragma unroll
+          for (int s2 = 0; s2 < VK; ++s2) {
+            if (bk.kb + q * KBLK + s2 >= bk.k1) continue;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+              for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(bv[q][s2][b], av[q][s2][a], acc[a][b]);
+          }
+      };
+      // next block after bk (false at the end); q is bk's contribution
+      auto advance = [&](int& q, Blk& bk) {
+        bk.kb += kSchurNB * KBLK;
+        if (bk.kb < bk.k1) return true;
+        for (++q; q < tg.ncont; ++q) {
+          setup(q, bk);
+          if (bk.k1 > 0) return true;
+        }
+        return false;
+      };
+      int qc = 0;
+      Blk cur;
+      bool have = false;
+      for (; qc < tg.ncont; ++qc) {
+        setup(qc, cur);
+        if (cur.k1 > 0) {
+          have = true;
+          break;
+        }
+      }
+      if (have) {
+        T av0[kSchurNB][VK][2], bv0[kSchurNB][VK][2], av1[kSchurNB][VK][2], bv1[kSchurNB][VK][2];
+        load(cur, av0, bv0);
+        for (;;) {
+          Blk nxt = cur;
+          int qn = qc;
+          const bool more = advance(qn, nxt);
+          if (more) load(nxt, av1, bv1);
+          prod(cur, av0, bv0);
+          if (!more) break;
+          cur = nxt;
+          qc = qn;
 #pragma unroll
           for (int q = 0; q < kSchurNB; ++q)
 #pragma unroll
-            for (int s2 = 0; s2 < VK; ++s2) {
-              if (kb + q * KBLK + s2 >= k1) continue;
+            for (int s2 = 0; s2 < VK; ++s2)
 #pragma unroll
-              for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(bv[q][s2][b], av[q][s2][a], acc[a][b]);
-            }
+              for (int e = 0; e < 2; ++e) {
+                av0[q][s2][e] = av1[q][s2][e];
+                bv0[q][s2][e] = bv1[q][s2][e];
+              }
         }
       }
 #pragma unroll
@@ -705,11 +785,12 @@ __global__ __launch_bounds__(256) void k_schur_apply(const SchurLevel<T>* __rest
 
 template <class T>
 void launch_schur(const SchurLevel<T>* lv, int ninst, int64_t rows, int c, SchurRow* rowtab,
-                  SchurTarget* targets, int64_t* conts, int64_t* count, int* err, hipStream_t s) {
+                  SchurTarget* targets, int64_t* conts, int64_t* count, int64_t ccap, int* err,
+                  hipStream_t s) {
   if (rows <= 0 || ninst <= 0) return;
   hipLaunchKernelGGL(k_fill<int64_t>, dim3(1), dim3(64), 0, s, count, (int64_t)2, (int64_t)0);
   hipLaunchKernelGGL(k_schur_enum<T>, dim3((unsigned)rows), dim3(256), 0, s, lv, ninst, c, rowtab,
-                     targets, conts, count, err);
+                     targets, conts, count, ccap, err);
   // workgroups loop over however many targets the first launch found
   hipLaunchKernelGGL(k_schur_apply<T>, dim3(8192), dim3(256), 0, s, lv, ninst, c, rowtab, targets,
                      conts, count);
@@ -1992,6 +2073,8 @@ __global__ __launch_bounds__(256) void k_trsm(const TrsmTask<T>* __restrict__ ta
   const int r = tk.ri >= 0 ? dyn[tk.ri] : tk.rs;
   if (r == 0) return;
   const int c0 = tk.c0d >= 0 ? dyn[tk.c0d] : tk.c0s;
+  int ldx = 0;
+  T* const xc = tk.Bc ? xmul_at<T>(tk.Bc, r, (int)tk.ldb, tk.ncols, ldx) : nullptr;
   const int cb = c0 + (int)blockIdx.y * tc;
   if (cb >= tk.ncols) return;
   const int ncol = min(tc, tk.ncols - cb);
@@ -2039,7 +2122,10 @@ __global__ __launch_bounds__(256) void k_trsm(const TrsmTask<T>* __restrict__ ta
       const T xj = bc[j] / LU[j + (int64_t)j * ld];
       if (xj != T(0))
         for (int i = rl; i < j; i += RL) bc[i] -= LU[i + (int64_t)j * ld] * xj;
-      if (rl == j % RL) Bg[j] = xj;
+      if (rl == j % RL) {
+        Bg[j] = xj;
+        if (xc) xc[j + (int64_t)(cb + col) * ldx] = xj;
+      }
     }
     __syncthreads();
   }
@@ -2056,6 +2142,8 @@ __global__ __launch_bounds__(256) void k_trsm_wave(const TrsmTask<T>* __restrict
   const int r = tk.ri >= 0 ? dyn[tk.ri] : tk.rs;
   if (r == 0) return;
   const int c0 = tk.c0d >= 0 ? dyn[tk.c0d] : tk.c0s;
+  int ldx = 0;
+  T* const xc = tk.Bc ? xmul_at<T>(tk.Bc, r, (int)tk.ldb, tk.ncols, ldx) : nullptr;
   T* S = reinterpret_cast<T*>(trw_smem);  // r x r, ld r
   int* perm = reinterpret_cast<int*>(S + (int64_t)r * r);
   int* pv = perm + r;  // the pivots, staged
@@ -2142,7 +2230,10 @@ __global__ __launch_bounds__(256) void k_trsm_wave(const TrsmTask<T>* __restrict
       if (i < r)
 #pragma unroll
         for (int c = 0; c < CB; ++c)
-          if (c < ncb) b[i + (int64_t)c * tk.ldb] = x[u][c];
+          if (c < ncb) {
+            b[i + (int64_t)c * tk.ldb] = x[u][c];
+            if (xc) xc[i + (int64_t)(col0 + c) * ldx] = x[u][c];
+          }
     }
   }
 }
@@ -2672,7 +2763,7 @@ void launch_check_finite(const double* X, int64_t n, int* flag, hipStream_t s) {
   template void launch_strip<T>(const STask<T>*, int, const int32_t*, int64_t, int,           \
                                 hipStream_t);                                                 \
   template void launch_schur<T>(const SchurLevel<T>*, int, int64_t, int, SchurRow*,           \
-                                SchurTarget*, int64_t*, int64_t*, int*, hipStream_t);         \
+                                SchurTarget*, int64_t*, int64_t*, int64_t, int*, hipStream_t); \
   template void launch_rfactor<T>(const RTask<T>*, int, const FillRef<T>*, const int32_t*, int, \
                                   hipStream_t, int);                                          \
   template void launch_pchol<T>(const CholTask<T>*, int, int, hipStream_t);                  \
