@@ -530,12 +530,27 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
     // reset only after the level's last launch has completed)
     std::vector<SchurLevel<T>> lvh(act.size());
     // kXmulCopy: the multipliers D_RR^{-1} D_{R_i,k} once more, compact
-    // (r_i x n_k) inside the region of the near block (i, k): the Schur
-    // updates read them there (the factor keeps them inside D for the solves)
+    // (r_i x n_k) in an n_i x n_k region of the colour's copy area: the Schur
+    // updates of the colour read them there (the factor keeps them inside D
+    // for the solves); the area is reused by every colour
     std::vector<DevArray<T>> xmul(act.size());
     if (kXmulCopy<T>())
-      for (size_t q = 0; q < act.size(); ++q)
-        xmul[q].alloc(std::max<int64_t>(act[q]->F->plans[act[q]->li].nD, 1), calltr);
+      for (size_t q = 0; q < act.size(); ++q) {
+        LevelPlan& P = act[q]->F->plans[act[q]->li];
+        P.xoff.assign(P.pcol.size(), 0);
+        P.nX = 0;
+        for (int c = 0; c < P.ncolors; ++c) {
+          int64_t off = 0;
+          for (int i : P.members[c])
+            for (int64_t e = P.pptr[i]; e < P.pptr[i + 1]; ++e)
+              if (!P.isF[e]) {
+                P.xoff[e] = off;
+                off += (int64_t)P.n[i] * P.n[P.pcol[e]];
+              }
+          P.nX = std::max(P.nX, off);
+        }
+        xmul[q].alloc(std::max<int64_t>(P.nX, 1), calltr);
+      }
     int64_t schur_rows = 0, schur_nnz = 0;
     for (size_t q = 0; q < act.size(); ++q) {
       Inst<T>* I = act[q];
@@ -544,6 +559,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       L.pptr = ar.put(P.pptr);
       L.pcol = ar.put(P.pcol);
       L.poff = ar.put(P.poff);
+      L.xoff = kXmulCopy<T>() ? ar.put(P.xoff) : nullptr;
       L.kind = ar.put(level_kinds(P));
       L.color = ar.put(P.color);
       L.n = ar.put(P.n);
@@ -853,7 +869,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
             tt.LU = lt.A;
             tt.piv = lt.piv;
             tt.B = S.D.p + P.poff[eik];
-            tt.Bc = I->xmul ? I->xmul + P.poff[eik] : nullptr;
+            tt.Bc = I->xmul ? I->xmul + P.xoff[eik] : nullptr;
             tt.ldlu = ni;
             tt.ldb = ni;
             tt.ncols = P.n[k];
@@ -973,8 +989,9 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       launches[5] += 1;
       {
         auto m2 = mark(2);
-        launch_strip<T>(dsl, (int)sl.size(), dyn, nsl, maxn, s);
-        launch_strip<T>(dsr, (int)sr.size(), dyn, nsr, maxn, s);
+        // the projections of a colour cover many strips: four per workgroup
+        launch_strip<T>(dsl, (int)sl.size(), dyn, nsl, maxn, s, 4);
+        launch_strip<T>(dsr, (int)sr.size(), dyn, nsr, maxn, s, 4);
         close_mark(m2);
       }
       {
@@ -1002,6 +1019,7 @@ static void run_factor(h2_context_s* ctx, std::vector<Inst<T>>& insts, double to
       }
       H2_HIP(hipGetLastError());  // a rejected launch configuration
     }
+    for (auto* I : act) std::vector<int64_t>().swap(I->F->plans[I->li].xoff);
     // ---- level end: read the ranks ----
     std::vector<int32_t> rh(total);
     H2_HIP(hipMemcpyAsync(rh.data(), rdev.p, sizeof(int32_t) * total, hipMemcpyDeviceToHost, s));

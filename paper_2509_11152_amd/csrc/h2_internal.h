@@ -273,6 +273,9 @@ struct LevelPlan {
                                // with k < j: offset of the stored block (k, j))
   std::vector<int> firstc;     // fill entries: first colour that writes it (-1 lifted)
   std::vector<int64_t> offQ, offV, offPiv;
+  std::vector<int64_t> xoff;   // near entry (i, k): offset of its multiplier copy in the
+                               // colour's copy area (when the Schur update reads copies)
+  int64_t nX = 0;              // largest copy area of a colour
   int64_t nD = 0, nF = 0, nQ = 0, nV = 0, nPiv = 0;
   std::vector<int> r;          // redundant counts (host copy after the level)
   std::vector<std::pair<int, int>> fill_pairs;  // (j, k) local, sorted (integer output)

@@ -110,8 +110,9 @@ template <class T> struct SchurLevel {
   T* D;
   T* F;
   const T* X;           // kXmulCopy: the multipliers D_RR^{-1} D_{R_i,k} of near entry
-                        // (i, k) in the n_i x n_k region at its offset (placed by
-                        // xmul_at); else unused
+                        // (i, k) of the colour being processed, in the n_i x n_k
+                        // region at xoff[e] (placed by xmul_at); else unused
+  const int64_t* xoff;
   int32_t nl;
   int32_t pad0;
   int64_t rows0;
@@ -312,9 +313,11 @@ void launch_gemm(const GOut<T>* outs, int nouts, const GCon<T>* cons, const int3
 template <class T>
 void launch_gemm_reduce(const GOut<T>* routs, int nouts, const T* parts, int64_t ntiles,
                         int shape, hipStream_t s);
+// `group`: strips one workgroup takes in turn (fewer, longer workgroups for
+// launches of many strips)
 template <class T>
 void launch_strip(const STask<T>* tasks, int ntasks, const int32_t* dyn, int64_t nstrips,
-                  int maxn, hipStream_t s);
+                  int maxn, hipStream_t s, int group = 1);
 // Schur and fill-in updates of colour c over every instance's level, found on
 // the device: the targets are the entries (j, k) of row j's pattern whose
 // block some cluster i of colour c updates (i near j and k; fill entries

@@ -604,7 +604,8 @@ __global__ __launch_bounds__(256) void k_schur_enum(const SchurLevel<T>* __restr
 // workgroups loop over the targets: C -= sum of the contributors' products,
 // contributors ascending.  The active window of C is cut into
 // items of 32 x 32 (2 x 2 fragments of 16 x 16), handed to the four waves in
-// turn; C of an item is read before its products.  A multiplier block
+// turn (from a different wave for each target of a group of four); C of an
+// item is read before its products.  A multiplier block
 // D(i, k) is column-major with k contiguous, so every lane reads VK
 // consecutive k of its column as one 16-byte vector: MFMA step s of a block
 // of 4 VK k-values takes k = kb + VK kq + s in lane group kq, for the panel
@@ -631,7 +632,11 @@ __global__ __launch_bounds__(256) void k_schur_apply(const SchurLevel<T>* __rest
   const int wave = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, kq = lane >> 4;
   const int64_t ntarg = *count;
-  for (int64_t t0 = blockIdx.x; t0 < ntarg; t0 += gridDim.x) {
+  // groups of four consecutive targets per workgroup; the items of the q-th
+  // target of a group start at wave q, so a run of one-item targets keeps
+  // all four waves busy
+  for (int64_t g0 = (int64_t)blockIdx.x * 4; g0 < ntarg; g0 += (int64_t)gridDim.x * 4)
+  for (int64_t t0 = g0; t0 < min(ntarg, g0 + 4); ++t0) {
     const SchurTarget tg = targets[t0];
     const SchurLevel<T>& L = lvs[schur_inst(lvs, ninst, tg.g)];
     const SchurRow& R = rowtab[tg.g];
@@ -645,7 +650,7 @@ __global__ __launch_bounds__(256) void k_schur_apply(const SchurLevel<T>* __rest
     const gptr<T> C = gmem((L.kind[tg.e] == 1 ? L.F : L.D) + L.poff[tg.e]);
     const int nrg = (nj - m0 + 31) / 32;  // row items of the window
     const int ncg = (nk - n0 + 31) / 32;  // column items of the window
-    for (int it = wave; it < nrg * ncg; it += 4) {
+    for (int it = (wave - (int)(t0 - g0) + 4) & 3; it < nrg * ncg; it += 4) {
       const int rb = m0 + (it % nrg) * 32;
       const int cb = n0 + (it / nrg) * 32;
       T cv[2][2][4];
@@ -677,7 +682,7 @@ __global__ __launch_bounds__(256) void k_schur_apply(const SchurLevel<T>* __rest
         bk.k1 = L.r[i];
         bk.A = Dg + L.poff[R.eji[x]];
         if (kXmulCopy<T>()) {
-          bk.B = xmul_at<T>(Xg + L.poff[cv2 & kContEntryMask], bk.k1, L.n[i], nk, bk.ldx);
+          bk.B = xmul_at<T>(Xg + L.xoff[cv2 & kContEntryMask], bk.k1, L.n[i], nk, bk.ldx);
         } else {
           bk.B = Dg + L.poff[cv2 & kContEntryMask];
           bk.ldx = L.n[i];
@@ -839,75 +844,97 @@ void launch_gemm_reduce(const GOut<T>* routs, int nouts, const T* parts, int64_t
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ __launch_bounds__(256) void k_strip(const STask<T>* __restrict__ tasks, int ntasks,
-                                               const int32_t* __restrict__ dyn) {
+                                               const int32_t* __restrict__ dyn, int64_t nstrips,
+                                               int group) {
   extern __shared__ char smem_raw[];
   T* xs = reinterpret_cast<T*>(smem_raw);
-  const int64_t sid = blockIdx.x;
-  int lo = 0, hi = ntasks - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (tasks[mid].strip0 <= sid) lo = mid; else hi = mid - 1;
-  }
-  const STask<T>& tk = tasks[lo];
-  const int s = (int)(sid - tk.strip0);
-  const int c0 = (tk.d0 >= 0 ? dyn[tk.d0] : tk.s0) + s * kStrip;
-  if (c0 >= tk.ext) return;
-  const int w = min(kStrip, tk.ext - c0);
-  const int n = tk.n;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, kq = lane >> 4;
-  if (tk.side == 0) {
-    // X[:, c0:c0+w] (n x w) -> LDS, layout xs[k + c*n]
-    for (int e = threadIdx.x; e < n * kStrip; e += blockDim.x) {
-      const int r = e % n, c = e / n;
-      xs[e] = c < w ? tk.X[r + (int64_t)(c0 + c) * tk.ldx] : T(0);
+  // `group` consecutive strips per workgroup, one after the other
+  const int64_t s_end = min(nstrips, (int64_t)(blockIdx.x + 1) * group);
+  for (int64_t sid = (int64_t)blockIdx.x * group; sid < s_end; ++sid) {
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (tasks[mid].strip0 <= sid) lo = mid; else hi = mid - 1;
     }
+    const STask<T>& tk = tasks[lo];
+    const int s = (int)(sid - tk.strip0);
+    const int c0 = (tk.d0 >= 0 ? dyn[tk.d0] : tk.s0) + s * kStrip;
+    if (c0 >= tk.ext) continue;  // the same for the whole workgroup
+    const int w = min(kStrip, tk.ext - c0);
+    const int n = tk.n;
+    // the previous strip's products have read xs
     __syncthreads();
-    for (int rt = wave; rt * 16 < n; rt += 4) {
-      typename Acc<T>::type acc = {0, 0, 0, 0};
-      const int row = rt * 16 + l16;
-      for (int kk = 0; kk < n; kk += 4) {
-        const int kx = kk + kq;
-        T a = 0, b = 0;
-        if (kx < n) {
-          if (row < n) a = tk.trans ? tk.Q[kx + (int64_t)row * n] : tk.Q[row + (int64_t)kx * n];
-          b = xs[kx + l16 * n];
-        }
-        acc = mfma16(a, b, acc);
+    if (tk.side == 0) {
+      // X[:, c0:c0+w] (n x w) -> LDS, layout xs[k + c*n]
+      for (int e = threadIdx.x; e < n * kStrip; e += blockDim.x) {
+        const int r = e % n, c = e / n;
+        xs[e] = c < w ? tk.X[r + (int64_t)(c0 + c) * tk.ldx] : T(0);
       }
-      const int col = l16;
-      if (col < w) {
+      __syncthreads();
+      for (int rt = wave; rt * 16 < n; rt += 4) {
+        typename Acc<T>::type acc = {0, 0, 0, 0};
+        const int row = rt * 16 + l16;
+        // four k-steps' operands loaded ahead of their products (the
+        // accumulation order is the plain ascending one)
+        for (int kk = 0; kk < n; kk += 16) {
+          T a[4], b[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int rr = rt * 16 + acc_row<T>(kq, i);
-          if (rr < n) tk.X[rr + (int64_t)(c0 + col) * tk.ldx] = acc[i];
-        }
-      }
-    }
-  } else {
-    // X[c0:c0+w, :] (w x n) -> LDS, layout xs[r + k*16]
-    for (int e = threadIdx.x; e < n * kStrip; e += blockDim.x) {
-      const int r = e % kStrip, k = e / kStrip;
-      xs[e] = r < w ? tk.X[(c0 + r) + (int64_t)k * tk.ldx] : T(0);
-    }
-    __syncthreads();
-    for (int ct = wave; ct * 16 < n; ct += 4) {
-      typename Acc<T>::type acc = {0, 0, 0, 0};
-      const int col = ct * 16 + l16;
-      for (int kk = 0; kk < n; kk += 4) {
-        const int kx = kk + kq;
-        T a = 0, b = 0;
-        if (kx < n) {
-          a = xs[l16 + kx * kStrip];
-          if (col < n) b = tk.trans ? tk.Q[col + (int64_t)kx * n] : tk.Q[kx + (int64_t)col * n];
-        }
-        acc = mfma16(a, b, acc);
-      }
-      if (col < n) {
+          for (int u = 0; u < 4; ++u) {
+            const int kx = kk + 4 * u + kq;
+            a[u] = T(0);
+            b[u] = T(0);
+            if (kx < n) {
+              if (row < n) a[u] = tk.trans ? tk.Q[kx + (int64_t)row * n] : tk.Q[row + (int64_t)kx * n];
+              b[u] = xs[kx + l16 * n];
+            }
+          }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int rr = acc_row<T>(kq, i);
-          if (rr < w) tk.X[(c0 + rr) + (int64_t)col * tk.ldx] = acc[i];
+          for (int u = 0; u < 4; ++u)
+            if (kk + 4 * u < n) acc = mfma16(a[u], b[u], acc);
+        }
+        const int col = l16;
+        if (col < w) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int rr = rt * 16 + acc_row<T>(kq, i);
+            if (rr < n) tk.X[rr + (int64_t)(c0 + col) * tk.ldx] = acc[i];
+          }
+        }
+      }
+    } else {
+      // X[c0:c0+w, :] (w x n) -> LDS, layout xs[r + k*16]
+      for (int e = threadIdx.x; e < n * kStrip; e += blockDim.x) {
+        const int r = e % kStrip, k = e / kStrip;
+        xs[e] = r < w ? tk.X[(c0 + r) + (int64_t)k * tk.ldx] : T(0);
+      }
+      __syncthreads();
+      for (int ct = wave; ct * 16 < n; ct += 4) {
+        typename Acc<T>::type acc = {0, 0, 0, 0};
+        const int col = ct * 16 + l16;
+        for (int kk = 0; kk < n; kk += 16) {
+          T a[4], b[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int kx = kk + 4 * u + kq;
+            a[u] = T(0);
+            b[u] = T(0);
+            if (kx < n) {
+              a[u] = xs[l16 + kx * kStrip];
+              if (col < n) b[u] = tk.trans ? tk.Q[col + (int64_t)kx * n] : tk.Q[kx + (int64_t)col * n];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (kk + 4 * u < n) acc = mfma16(a[u], b[u], acc);
+        }
+        if (col < n) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int rr = acc_row<T>(kq, i);
+            if (rr < w) tk.X[(c0 + rr) + (int64_t)col * tk.ldx] = acc[i];
+          }
         }
       }
     }
@@ -916,8 +943,9 @@ __global__ __launch_bounds__(256) void k_strip(const STask<T>* __restrict__ task
 
 template <class T>
 void launch_strip(const STask<T>* tasks, int ntasks, const int32_t* dyn, int64_t nstrips,
-                  int maxn, hipStream_t s) {
+                  int maxn, hipStream_t s, int group) {
   if (nstrips <= 0 || ntasks <= 0) return;
+  group = std::max(group, 1);
   const size_t lds = (size_t)maxn * kStrip * sizeof(T);
   static bool attr_set = false;
   if (!attr_set) {
@@ -925,7 +953,9 @@ void launch_strip(const STask<T>* tasks, int ntasks, const int32_t* dyn, int64_t
                               160 * 1024);
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_strip<T>, dim3((unsigned)nstrips), dim3(256), lds, s, tasks, ntasks, dyn);
+  const int64_t groups = (nstrips + group - 1) / group;
+  hipLaunchKernelGGL(k_strip<T>, dim3((unsigned)groups), dim3(256), lds, s, tasks, ntasks, dyn,
+                     nstrips, group);
 }
 
 // ---------------------------------------------------------------------------
@@ -2761,7 +2791,7 @@ void launch_check_finite(const double* X, int64_t n, int* flag, hipStream_t s) {
   template void launch_gemm_reduce<T>(const GOut<T>*, int, const T*, int64_t, int,             \
                                       hipStream_t);                                           \
   template void launch_strip<T>(const STask<T>*, int, const int32_t*, int64_t, int,           \
-                                hipStream_t);                                                 \
+                                hipStream_t, int);                                            \
   template void launch_schur<T>(const SchurLevel<T>*, int, int64_t, int, SchurRow*,           \
                                 SchurTarget*, int64_t*, int64_t*, int64_t, int*, hipStream_t); \
   template void launch_rfactor<T>(const RTask<T>*, int, const FillRef<T>*, const int32_t*, int, \
