@@ -56,6 +56,17 @@ def points(seed, n, dim):
     return uniform01(seed, n * dim).reshape(n, dim)
 
 
+def grid_points(n, dim):
+    """The n = s^dim cell centres ((i + 1/2)/s, ...) of the uniform grid on [0,1)^dim,
+    row-major n x dim, the first coordinate fastest (no random draw)."""
+    s = int(round(n ** (1.0 / dim)))
+    if s ** dim != n:
+        raise ValueError(f"{n} points do not form a {dim}-dimensional grid")
+    c = (np.arange(s, dtype=np.float64) + 0.5) / s
+    axes = np.meshgrid(*([c] * dim), indexing="ij")
+    return np.stack([a.reshape(-1, order="F") for a in axes], axis=1)
+
+
 def rhs(seed, n, nrhs):
     """n x nrhs right-hand sides with N(0,1) entries, column j = draws j*n..(j+1)*n-1."""
     return np.asfortranarray(normal(seed, n * nrhs).reshape(nrhs, n).T)

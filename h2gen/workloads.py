@@ -6,7 +6,8 @@ configurations mirror the kernel-matrix families of the paper's Section 3
 precision and scale studies; the smaller variants keep the same recipe at
 sizes the CPU oracle finishes in seconds.
 
-Fields: N, dim, point seed, kernel (name, length, nugget), tree kind
+Fields: N, dim, point seed (or points="grid": the uniform grid's cell centres),
+kernel (name, length or None for the grid's cell side, nugget), tree kind
 ("2d" = quadtree/octree, "kd" = binary KD), leaf size m, admissibility eta
 (max-diameter form), factorization tolerance tol (construction uses tol/10),
 number of right-hand sides and their seed, Chebyshev leaf order p0.
@@ -41,6 +42,16 @@ WORKLOADS = {
                            tree="kd", leaf=64, eta=0.7, tol=1e-6, nrhs=4, rhs_seed=215, p0=5),
     "gauss2d_3000": dict(N=3000, dim=2, seed=3000, kernel=("gauss", 0.05, 1e-3), tree="kd",
                          leaf=64, eta=0.7, tol=1e-8, nrhs=16, rhs_seed=4000, p0=10),
+    # 2D Laplace volume integral equation (Section 3.1, Table 2: m 64, p0 8, alpha_r 1e-5,
+    # eps 1e-7, eps_lu 1e-6) on the uniform grid of cell centres; the kernel's
+    # parameter (None) is the grid's cell side
+    "laplace2d_1024": dict(N=1024, dim=2, seed=0, points="grid", kernel=("laplace2d", None, 1e-5),
+                           tree="2d", leaf=64, eta=0.7, tol=1e-6, nrhs=2, rhs_seed=221, p0=8),
+    "laplace2d_4096": dict(N=4096, dim=2, seed=0, points="grid", kernel=("laplace2d", None, 1e-5),
+                           tree="2d", leaf=64, eta=0.7, tol=1e-6, nrhs=4, rhs_seed=222, p0=8),
+    "laplace2d_262144": dict(N=262144, dim=2, seed=0, points="grid",
+                             kernel=("laplace2d", None, 1e-5), tree="2d", leaf=64, eta=0.7,
+                             tol=1e-6, nrhs=8, rhs_seed=223, p0=8),
 }
 
 
@@ -60,8 +71,13 @@ def make(spec, device="cpu", want_blob=True, verbose=False):
     """Points, constructor output, serialized blob and right-hand sides of a workload."""
     if isinstance(spec, str):
         spec = WORKLOADS[spec]
-    pts = rng.points(spec["seed"], spec["N"], spec["dim"])
+    if spec.get("points") == "grid":
+        pts = rng.grid_points(spec["N"], spec["dim"])
+    else:
+        pts = rng.points(spec["seed"], spec["N"], spec["dim"])
     kname, kpar, alpha = spec["kernel"]
+    if kpar is None:  # the grid's cell side
+        kpar = 1.0 / round(spec["N"] ** (1.0 / spec["dim"]))
     K = kernels.Kernel(kname, kpar, alpha)
     h = cons.construct(pts, K, spec["leaf"], spec["tree"], spec["eta"], 0, spec["tol"] / 10,
                        p0=spec["p0"], device=device, verbose=verbose)

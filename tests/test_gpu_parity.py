@@ -23,6 +23,8 @@ CASES = [
     ("gauss2d_leaf128", GAUSS_L128),
     # the scale workload's regularised 3D Laplace kernel at a size the oracle factors in seconds
     ("laplace3d_8192", None),
+    # the 2D Laplace volume integral equation on its uniform grid (Section 3.1)
+    ("laplace2d_4096", None),
 ]
 
 
@@ -182,7 +184,7 @@ def test_global_memory_variants(lib, ctx, name, spec, lds_kib):
 
 
 @pytest.mark.parametrize("name,spec", [("exp2d_4096", None), ("exp3d_4096", EXP3D_4096),
-                                       ("laplace3d_8192", None)])
+                                       ("laplace3d_8192", None), ("laplace2d_4096", None)])
 @pytest.mark.parametrize("mode", ["chol", "qr", "gram"])
 def test_fp32_factor_with_fp64_refinement(lib, ctx, name, spec, mode):
     from oracle import h2ops

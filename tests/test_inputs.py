@@ -21,6 +21,41 @@ def test_rng_moments_and_determinism():
     assert not np.array_equal(rng.uniform01(7, 10), rng.uniform01(8, 10))
 
 
+def test_grid_points_are_the_cell_centres():
+    p = rng.grid_points(1024, 2)
+    assert p.shape == (1024, 2)
+    # every cell of the 32 x 32 grid holds exactly one point, at its centre
+    cells = np.floor(p * 32).astype(np.int64)
+    assert len({(int(a), int(b)) for a, b in cells}) == 1024
+    assert np.allclose(p, (cells + 0.5) / 32, rtol=0, atol=1e-15)
+    assert np.array_equal(rng.grid_points(27, 3)[:4], [[1 / 6, 1 / 6, 1 / 6], [0.5, 1 / 6, 1 / 6],
+                                                      [5 / 6, 1 / 6, 1 / 6], [1 / 6, 0.5, 1 / 6]])
+    with pytest.raises(ValueError):
+        rng.grid_points(1000, 2)
+
+
+@pytest.mark.parametrize("h", [1 / 32, 1 / 512])
+def test_laplace2d_self_term_is_the_cell_mean(h):
+    """The diagonal of the 2D Laplace kernel matrix is the kernel's mean over
+    the point's cell of side h; checked against a midpoint rule on a fine
+    sub-grid of the cell, whose error is O(1/s) from the log singularity."""
+    import math
+
+    import torch
+    from h2gen import kernels
+
+    K = kernels.Kernel("laplace2d", h, 0.0)
+    d = float(K.radial(torch.zeros(1, dtype=torch.float64))[0])
+    s = 2000
+    u = ((np.arange(s) + 0.5) / s - 0.5) * h
+    X, Y = np.meshgrid(u, u)
+    mean = np.mean(-np.log(np.sqrt(X * X + Y * Y)) / (2 * math.pi))
+    assert abs(d - mean) <= 1e-4 * abs(mean)
+    # off the diagonal: the free-space Green's function
+    r = torch.tensor([0.25, 1.0], dtype=torch.float64)
+    assert torch.allclose(K.radial(r), -torch.log(r) / (2 * math.pi), rtol=1e-15, atol=0)
+
+
 @pytest.mark.parametrize("kind,dim,n,m", [("2d", 2, 1024, 64), ("kd", 3, 3000, 32), ("2d", 3, 4096, 64)])
 def test_tree_balanced_and_partitioned(kind, dim, n, m):
     p = rng.points(5, n, dim)
@@ -88,9 +123,10 @@ def test_no_far_case_has_no_top_level():
     assert H.top is None and len(H.S) == 0
 
 
-def test_construction_error_and_orthonormal_bases():
-    w = workload("exp2d_1024")
-    H = oracle_matrix("exp2d_1024")
+@pytest.mark.parametrize("name", ["exp2d_1024", "laplace2d_1024"])
+def test_construction_error_and_orthonormal_bases(name):
+    w = workload(name)
+    H = oracle_matrix(name)
     A = w["kernel"].dense(w["points"])
     from oracle import h2ops
 

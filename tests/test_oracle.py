@@ -11,6 +11,9 @@
   * colouring proper and equal to Jones-Plassmann; fill pattern equal to the
     boolean product of the near graph with itself (Section 2.2);
   * GMRES-IR reaches 1e-12 and matches the dense solution.
+
+The 2D Laplace volume integral equation (Section 3.1) enters the same pins
+(matvec, exact elimination, invariants, colouring, refinement).
 """
 import numpy as np
 import pytest
@@ -21,7 +24,8 @@ from oracle import factor as of
 from oracle import h2ops, ir
 
 
-@pytest.mark.parametrize("name,spec", [("exp2d_1024", None), ("exp3d_4096", EXP3D_4096)])
+@pytest.mark.parametrize("name,spec", [("exp2d_1024", None), ("exp3d_4096", EXP3D_4096),
+                                       ("laplace2d_1024", None)])
 def test_matvec_against_kernel_matrix(name, spec):
     w = workload(name, spec)
     H = oracle_matrix(name, spec)
@@ -39,7 +43,7 @@ def test_matvec_against_kernel_matrix(name, spec):
 
 
 @pytest.mark.parametrize("name,spec", [("exp2d_1024", None), ("exp2d_4096", None),
-                                       ("exp3d_4096", EXP3D_4096)])
+                                       ("exp3d_4096", EXP3D_4096), ("laplace2d_4096", None)])
 def test_factor_without_truncation_is_dense_solve(name, spec):
     """With eps_lu -> 0 nothing is truncated and every level (one level for the
     first case, two for the others) is an exact block elimination."""
@@ -77,7 +81,8 @@ def test_backward_error_falls_with_tolerance():
         assert eb <= bound
 
 
-@pytest.mark.parametrize("name,spec", [("exp2d_1024", None), ("exp3d_4096", EXP3D_4096)])
+@pytest.mark.parametrize("name,spec", [("exp2d_1024", None), ("exp3d_4096", EXP3D_4096),
+                                       ("laplace2d_4096", None)])
 def test_skeletonization_invariants(name, spec):
     H = oracle_matrix(name, spec)
     Fz = oracle_factor(name, spec=spec)
@@ -124,7 +129,8 @@ def _jones_plassmann(nodes, nbrs):
     return color
 
 
-@pytest.mark.parametrize("name,spec", [("exp2d_1024", None), ("exp3d_4096", EXP3D_4096)])
+@pytest.mark.parametrize("name,spec", [("exp2d_1024", None), ("exp3d_4096", EXP3D_4096),
+                                       ("laplace2d_4096", None)])
 def test_colouring_and_fill_pattern(name, spec):
     H = oracle_matrix(name, spec)
     Fz = oracle_factor(name, spec=spec)
@@ -151,10 +157,14 @@ def test_colouring_and_fill_pattern(name, spec):
     assert Lf.fpat == expect
 
 
-def test_gmres_ir_reaches_1e12():
-    H = oracle_matrix("exp2d_1024")
-    B = workload("exp2d_1024")["B"]
-    Fz = of.factor(H, 1e-4)
+@pytest.mark.parametrize("name,tol", [("exp2d_1024", 1e-4), ("laplace2d_1024", 1e-6)])
+def test_gmres_ir_reaches_1e12(name, tol):
+    """The 2D Laplace case uses the paper's eps_lu for that problem (Section 3.1,
+    Table 2): its plain solve reaches a backward error near 1e-4, the
+    refinement 1e-12."""
+    H = oracle_matrix(name)
+    B = workload(name)["B"]
+    Fz = of.factor(H, tol)
     X, eb, its = ir.gmres_ir(H, Fz, B, target=1e-12)
     assert eb.max() <= 1e-12
     Xd = np.linalg.solve(h2ops.dense(H), B)
