@@ -11,6 +11,7 @@
 #include <cstring>
 #include <functional>
 #include <memory>
+#include <mutex>
 
 #include "h2_driver.h"
 
@@ -33,30 +34,91 @@ constexpr int kSkinnyCols = 64;
 inline int product_shape(int nrhs) { return nrhs <= 16 ? 1 : nrhs <= kSkinnyCols ? 3 : 0; }
 inline int tile_cols(int shape) { return (shape & 7) == 1 ? 16 : (shape & 7) == 3 ? 32 : 64; }
 
+// Host chunks of recorded descriptor images, kept for later recordings in
+// pinned memory: a fresh chunk's first touch (page faults) and a pageable
+// upload cost more than the copies themselves.  At most kPoolMax chunks are
+// kept; the pool lives until the process ends.
+constexpr size_t kImageChunk = (size_t)64 << 20;
+struct ChunkPool {
+  static constexpr size_t kPoolMax = 16;
+  std::mutex m;
+  std::vector<char*> free;
+  // a pinned chunk of kImageChunk bytes, or nullptr when none can be pinned
+  char* get() {
+    {
+      std::lock_guard<std::mutex> g(m);
+      if (!free.empty()) {
+        char* p = free.back();
+        free.pop_back();
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, kImageChunk, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return static_cast<char*>(p);
+  }
+  void put(char* p) {
+    {
+      std::lock_guard<std::mutex> g(m);
+      if (free.size() < kPoolMax) {
+        free.push_back(p);
+        return;
+      }
+    }
+    (void)hipHostFree(p);
+  }
+};
+ChunkPool& chunk_pool() {
+  static ChunkPool* pool = new ChunkPool;  // never destroyed (outlives the runtime's users)
+  return *pool;
+}
+
 // Append-only host image of descriptor arrays, each 256-byte aligned, kept in
 // chunks that are never moved or zero-filled; each chunk covers a contiguous
-// range of the device image it is uploaded into.
+// range of the device image it is uploaded into.  Chunks of the standard size
+// come from the pinned pool and go back to it with the image.
 struct HostImage {
-  static constexpr size_t kChunk = (size_t)64 << 20;
   struct Chunk {
-    std::unique_ptr<char[]> h;
+    char* h = nullptr;
+    bool pooled = false;
     size_t dev_off = 0, used = 0, cap = 0;
   };
   std::vector<Chunk> chunks;
   size_t total = 0;
+  bool use_pool = true;  // false: plain host memory only (no HIP call at all)
+  HostImage() = default;
+  HostImage(const HostImage&) = delete;
+  HostImage& operator=(const HostImage&) = delete;
+  ~HostImage() {
+    for (Chunk& c : chunks) {
+      if (c.pooled)
+        chunk_pool().put(c.h);
+      else
+        delete[] c.h;
+    }
+  }
   bool empty() const { return total == 0; }
   size_t size() const { return total; }
   size_t append(const void* p, size_t bytes) {
     const size_t off = (total + 255) & ~(size_t)255;
     if (chunks.empty() || off - chunks.back().dev_off + bytes > chunks.back().cap) {
       Chunk c;
-      c.cap = std::max(kChunk, bytes);
-      c.h.reset(new char[c.cap]);
+      if (use_pool && bytes <= kImageChunk) c.h = chunk_pool().get();
+      if (c.h) {
+        c.pooled = true;
+        c.cap = kImageChunk;
+      } else {
+        c.cap = std::max(kImageChunk, bytes);
+        c.h = new char[c.cap];
+      }
       c.dev_off = off;
-      chunks.push_back(std::move(c));
+      chunks.push_back(c);
     }
     Chunk& c = chunks.back();
-    std::memcpy(c.h.get() + (off - c.dev_off), p, bytes);
+    std::memcpy(c.h + (off - c.dev_off), p, bytes);
     c.used = off - c.dev_off + bytes;
     total = off + bytes;
     return off;
@@ -67,9 +129,9 @@ struct HostImage {
     for (const Chunk& c : chunks) {
       if (c.used == 0) continue;
       if (async)
-        H2_HIP(hipMemcpyAsync(dev + c.dev_off, c.h.get(), c.used, hipMemcpyHostToDevice, s));
+        H2_HIP(hipMemcpyAsync(dev + c.dev_off, c.h, c.used, hipMemcpyHostToDevice, s));
       else
-        H2_HIP(hipMemcpy(dev + c.dev_off, c.h.get(), c.used, hipMemcpyHostToDevice));
+        H2_HIP(hipMemcpy(dev + c.dev_off, c.h, c.used, hipMemcpyHostToDevice));
     }
   }
 };
@@ -905,6 +967,7 @@ void matvec_in(h2_context_s* ctx, h2_matrix_s* H, const double* X, int64_t ldx, 
   em.ctx = ctx;
   em.s = s;
   em.rec = true;
+  em.img.use_pool = false;  // no pinned allocation on this path
   matvec_body(em, H, xt, yt, xh, yh, nrhs);
   const int64_t img = up((int64_t)em.img.size());
   const int64_t need = vec + img + 8 * em.parts_need;
