@@ -70,6 +70,9 @@ def parse():
                         "PATH.blob.npy and PATH.rhs.npy")
     p.add_argument("--load-blob", default=None,
                    help="skip construction: read the files --save-blob wrote for this workload")
+    p.add_argument("--sweep", default=None, choices=sorted(SWEEPS),
+                   help="time and peak device memory over N for a workload family (prints "
+                        "one JSON line with the fitted log-log slopes) instead of the bench")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run plain 256 MiB device copies (reference reading for HBM "
                         "byte counters) and print their size")
@@ -334,10 +337,97 @@ def finish_cpu_baseline(proc, wait_s):
     return None
 
 
+# workload families of the linear-complexity sweep: the recipe and its sizes
+SWEEPS = {
+    "laplace3d": ("laplace3d_1048576", [2 ** 16, 2 ** 17, 2 ** 18, 2 ** 19, 2 ** 20]),
+    "laplace2d": ("laplace2d_262144", [4 ** 7, 4 ** 8, 4 ** 9, 4 ** 10]),
+}
+
+
+def loglog_slope(xs, ys):
+    """Least-squares slope of log y against log x."""
+    import numpy as np
+
+    return float(np.polyfit(np.log(np.asarray(xs, dtype=np.float64)),
+                            np.log(np.asarray(ys, dtype=np.float64)), 1)[0])
+
+
+def sweep_main(args):
+    """Linear time and memory on the device (Section 2.4, Section 3.3): for each
+    size of a workload family, the median of two FP32 factorizations and their
+    refinements to 1e-12 and one FP64 factorization (each after an untimed run),
+    the peak device bytes of both factors and the matrix's bytes; then the
+    fitted log-log slopes over N."""
+    import numpy as np
+    import torch
+
+    import paper_2509_11152_amd as h2
+    from h2gen import workloads
+
+    name, sizes = SWEEPS[args.sweep]
+    base = workloads.WORKLOADS[name]
+    ctx = h2.Context(0)
+    rows = []
+    for N in sizes:
+        spec = dict(base, N=N)
+        t0 = time.perf_counter()
+        w = workloads.make(spec, device=args.construct_device)
+        H = h2.Matrix(ctx, w["blob"])
+        B = torch.tensor(w["B"], dtype=torch.float64, device="cuda")
+        del w
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        tol = spec["tol"]
+        f32, ir32 = [], []
+        for rep in range(3):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            F = h2.Factor(ctx, H, tol, h2.H2_PREC_FP32)
+            torch.cuda.synchronize()
+            b = time.perf_counter()
+            X, rep_ir = h2.solve_ir(ctx, H, F, B, target=1e-12)
+            torch.cuda.synchronize()
+            c = time.perf_counter()
+            if rep:
+                f32.append(b - a)
+                ir32.append(c - b)
+            s32 = F.stats()
+            del F, X
+        f64 = []
+        for rep in range(2):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            F = h2.Factor(ctx, H, tol, h2.H2_PREC_FP64)
+            torch.cuda.synchronize()
+            f64.append(time.perf_counter() - a)
+            s64 = F.stats()
+            del F
+        row = {"N": N, "build_s": t_build, "fp32_factor_s": float(np.median(f32)),
+               "fp32_ir_s": float(np.median(ir32)), "fp64_factor_s": f64[-1],
+               "peak_fp32_bytes": s32["peak_bytes"], "peak_fp64_bytes": s64["peak_bytes"],
+               "matrix_bytes": H.device_bytes, "ir_converged": bool(rep_ir["converged"]),
+               "ir_bkwd": rep_ir["max_bkwd"]}
+        rows.append(row)
+        log(f"[sweep] {name} N={N}: build {t_build:.1f} s, fp32 factor {row['fp32_factor_s']:.3f} s "
+            f"+ IR {row['fp32_ir_s']:.3f} s, fp64 factor {row['fp64_factor_s']:.3f} s, peak "
+            f"{row['peak_fp32_bytes'] / 1e9:.2f} / {row['peak_fp64_bytes'] / 1e9:.2f} GB")
+        del H, B
+        torch.cuda.empty_cache()
+    Ns = [r["N"] for r in rows]
+    keys = ["fp32_factor_s", "fp32_ir_s", "fp64_factor_s", "peak_fp32_bytes", "peak_fp64_bytes",
+            "matrix_bytes"]
+    print(json.dumps({"sweep": args.sweep, "workload": name, "rows": rows,
+                      "slopes": {k: loglog_slope(Ns, [r[k] for r in rows]) for k in keys}}),
+          flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.sweep:
+        sweep_main(args)
         return
     if args.cpu_baseline_only:
         cpu_baseline_main(args)

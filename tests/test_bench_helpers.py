@@ -55,3 +55,12 @@ def test_traffic_lookup_requires_workload_phase_and_source_hash():
             assert t == rec["kernels"][kernel]["traffic_bytes_per_launch"] and t > 0
         else:
             assert t is None
+
+
+def test_loglog_slope_of_power_laws():
+    import bench
+
+    Ns = [2 ** 16, 2 ** 17, 2 ** 18, 2 ** 19, 2 ** 20]
+    assert abs(bench.loglog_slope(Ns, [3e-6 * n for n in Ns]) - 1.0) < 1e-12
+    assert abs(bench.loglog_slope(Ns, [n ** 1.5 for n in Ns]) - 1.5) < 1e-12
+    assert set(bench.SWEEPS) == {"laplace2d", "laplace3d"}
